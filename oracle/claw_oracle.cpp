@@ -1,0 +1,951 @@
+// claw_oracle.cpp -- TEST INFRASTRUCTURE ONLY.
+//
+// A plain, slow, FP64 CPU implementation of one finite-volume time step for
+// q_t + f(q)_x + g(q)_y = 0 on a uniform Cartesian grid, in the two forms the
+// PyClaw paper describes (Section 2, "Finite Volume Hyperbolic PDE solvers",
+// and Section 2.1, "Clawpack and SharpClaw"):
+//
+//   * classic Clawpack wave propagation: a Riemann solve at every interface,
+//     waves limited by the upwind neighbour, a second-order correction flux
+//     (eq. lwflux: F = F_upwind + F_correction, first-order part written as
+//     fluctuations) and, in 2D, the unsplit transverse corrections computed by
+//     a secondary "transverse" Riemann solver;
+//   * SharpClaw method of lines: WENO5 edge values, an interface Riemann flux
+//     and flux differencing (eq. fluxdiff), inside SSP Runge-Kutta stages.
+//
+// The paper prints none of the Riemann solvers, limiters, WENO weights or RK
+// coefficients; it defers to LeVeque (1997, 2002), Jiang-Shu and Shu-Osher.
+// The formulas below are those published definitions written out plainly.
+// Every choice the paper leaves open is fixed once here and listed in the
+// design notes of the repository (entropy fix form, transverse factor, WENO
+// epsilon, Courant number definition, step controller).
+//
+// Nothing in the GPU library may include, link or call this file; it exists
+// so tests and the CPU baseline can check the GPU results against it.  It is
+// compiled with -O2 -ffp-contract=off and no fast-math.
+//
+// Layout of every array: component-major, x fastest: q[k][j][i],
+// k = component, j = row (y), i = column (x); interior cells only.
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <vector>
+
+extern "C" {
+
+// Problem description (the oracle's own struct; the GPU library has its own).
+struct OCfg {
+  int ndim;            // 1 or 2
+  int nx, ny;          // interior cells (ny = 1 in 1D)
+  double xlo, xhi, ylo, yhi;
+  int scheme;          // 1 classic wave propagation, 2 SharpClaw (WENO5 + SSPRK(3,3))
+  int solver;          // 1 advection, 2 shallow water Roe, 3 Euler HLLE, 4 elasticity (variable coeff.)
+  int limiter;         // 0 none (Lax-Wendroff), 1 minmod, 2 MC
+  int transverse;      // 0 none, 1 fluctuations, 2 full (fluctuations -/+ second-order term)
+  int efix;            // 1: Harten-Hyman entropy fix in the shallow-water Roe solver
+  int bc[4];           // x-lower, x-upper, y-lower, y-upper: 1 extrap, 2 periodic, 3 wall, 4 Dirichlet
+  double bcstate[4][8];// Dirichlet state per side
+  double weno_eps;     // WENO epsilon
+  double pd[8];        // problem data: advection (u, v); shallow water (g); Euler (gamma)
+};
+
+}  // extern "C"
+
+namespace {
+
+enum { S_ADV = 1, S_SW = 2, S_EULER = 3, S_ELASTIC = 4 };
+enum { BC_EXTRAP = 1, BC_PERIODIC = 2, BC_WALL = 3, BC_DIRICHLET = 4 };
+
+int num_eqn(const OCfg& c) {
+  switch (c.solver) {
+    case S_ADV: return 1;
+    case S_SW: return c.ndim == 1 ? 2 : 3;
+    case S_EULER: return c.ndim == 1 ? 3 : 4;
+    case S_ELASTIC: return 5;
+  }
+  return 0;
+}
+int num_waves(const OCfg& c) {
+  switch (c.solver) {
+    case S_ADV: return 1;
+    case S_SW: return c.ndim == 1 ? 2 : 3;
+    case S_EULER: return 2;
+    case S_ELASTIC: return 4;
+  }
+  return 0;
+}
+int num_aux(const OCfg& c) { return c.solver == S_ELASTIC ? 3 : 0; }
+
+double dx_of(const OCfg& c) { return (c.xhi - c.xlo) / c.nx; }
+double dy_of(const OCfg& c) { return c.ndim == 2 ? (c.yhi - c.ylo) / c.ny : 1.0; }
+
+// Components whose sign flips under reflection through a wall normal to
+// direction d (the "normal-odd" components).
+bool odd_under_reflection(const OCfg& c, int d, int k) {
+  switch (c.solver) {
+    case S_SW:
+    case S_EULER: return k == 1 + d;                 // normal momentum
+    case S_ELASTIC: return k == 2 || k == 3 + d;      // shear stress and normal velocity
+  }
+  return false;
+}
+
+// Ghost-padded field: g ghost layers in x, and in y when ndim == 2.
+struct Field {
+  int m = 0, nx = 0, ny = 0, g = 0, gy = 0, NX = 0, NY = 0;
+  std::vector<double> v;
+  void init(int m_, int nx_, int ny_, int g_, int ndim) {
+    m = m_; nx = nx_; ny = ny_; g = g_; gy = ndim == 2 ? g_ : 0;
+    NX = nx + 2 * g; NY = ny + 2 * gy;
+    v.assign((size_t)std::max(m, 1) * NX * NY, 0.0);
+  }
+  double& at(int k, int j, int i) { return v[((size_t)k * NY + (j + gy)) * NX + (i + g)]; }
+  double at(int k, int j, int i) const { return v[((size_t)k * NY + (j + gy)) * NX + (i + g)]; }
+};
+
+// Ghost cells (Section 5, "Parallelization": ghost layers set from the boundary
+// conditions before each step).  x ghosts are filled for interior rows first;
+// then y ghosts for every column, ghost columns included, so a corner ghost is
+// the y-boundary image of an x-ghost.
+void fill_ghosts(const OCfg& c, Field& f, bool is_aux) {
+  const int nx = f.nx, ny = f.ny, g = f.g;
+  auto bc_of = [&](int side) {
+    int b = c.bc[side];
+    if (is_aux && b == BC_DIRICHLET) b = BC_EXTRAP;   // material data: copy the edge
+    return b;
+  };
+  for (int j = 0; j < ny; ++j)
+    for (int kk = 1; kk <= g; ++kk)
+      for (int k = 0; k < f.m; ++k) {
+        // lower x side, ghost column i = -kk
+        switch (bc_of(0)) {
+          case BC_EXTRAP: f.at(k, j, -kk) = f.at(k, j, 0); break;
+          case BC_PERIODIC: f.at(k, j, -kk) = f.at(k, j, nx - kk); break;
+          case BC_WALL: {
+            double s = (!is_aux && odd_under_reflection(c, 0, k)) ? -1.0 : 1.0;
+            f.at(k, j, -kk) = s * f.at(k, j, kk - 1);
+          } break;
+          case BC_DIRICHLET: f.at(k, j, -kk) = c.bcstate[0][k]; break;
+        }
+        // upper x side, ghost column i = nx - 1 + kk
+        switch (bc_of(1)) {
+          case BC_EXTRAP: f.at(k, j, nx - 1 + kk) = f.at(k, j, nx - 1); break;
+          case BC_PERIODIC: f.at(k, j, nx - 1 + kk) = f.at(k, j, kk - 1); break;
+          case BC_WALL: {
+            double s = (!is_aux && odd_under_reflection(c, 0, k)) ? -1.0 : 1.0;
+            f.at(k, j, nx - 1 + kk) = s * f.at(k, j, nx - kk);
+          } break;
+          case BC_DIRICHLET: f.at(k, j, nx - 1 + kk) = c.bcstate[1][k]; break;
+        }
+      }
+  if (c.ndim != 2) return;
+  for (int i = -g; i < nx + g; ++i)
+    for (int kk = 1; kk <= g; ++kk)
+      for (int k = 0; k < f.m; ++k) {
+        switch (bc_of(2)) {
+          case BC_EXTRAP: f.at(k, -kk, i) = f.at(k, 0, i); break;
+          case BC_PERIODIC: f.at(k, -kk, i) = f.at(k, ny - kk, i); break;
+          case BC_WALL: {
+            double s = (!is_aux && odd_under_reflection(c, 1, k)) ? -1.0 : 1.0;
+            f.at(k, -kk, i) = s * f.at(k, kk - 1, i);
+          } break;
+          case BC_DIRICHLET: f.at(k, -kk, i) = c.bcstate[2][k]; break;
+        }
+        switch (bc_of(3)) {
+          case BC_EXTRAP: f.at(k, ny - 1 + kk, i) = f.at(k, ny - 1, i); break;
+          case BC_PERIODIC: f.at(k, ny - 1 + kk, i) = f.at(k, kk - 1, i); break;
+          case BC_WALL: {
+            double s = (!is_aux && odd_under_reflection(c, 1, k)) ? -1.0 : 1.0;
+            f.at(k, ny - 1 + kk, i) = s * f.at(k, ny - kk, i);
+          } break;
+          case BC_DIRICHLET: f.at(k, ny - 1 + kk, i) = c.bcstate[3][k]; break;
+        }
+      }
+}
+
+void load_field(const OCfg& c, Field& f, const double* src, int m, int g, bool is_aux) {
+  f.init(m, c.nx, c.ny, g, c.ndim);
+  if (m == 0) return;
+  for (int k = 0; k < m; ++k)
+    for (int j = 0; j < c.ny; ++j)
+      for (int i = 0; i < c.nx; ++i) f.at(k, j, i) = src[((size_t)k * c.ny + j) * c.nx + i];
+  fill_ghosts(c, f, is_aux);
+}
+
+// ---------------------------------------------------------------------------
+// Riemann solvers (the problem-specific kernels of Section 2.1).  A solve at
+// a face normal to direction d takes the left state ql (lower index side) and
+// right state qr, and returns waves W^p, speeds s^p and the fluctuations
+// A^-dQ, A^+dQ.
+// ---------------------------------------------------------------------------
+
+struct FaceSol {
+  double W[4][5];
+  double s[4];
+  double amdq[5], apdq[5];
+};
+
+// Scalar advection q_t + u q_x + v q_y = 0: one wave, the jump.
+void rp_advection(const OCfg& c, int d, const double* ql, const double* qr, FaceSol& r) {
+  const double u = c.pd[d];
+  const double dq = qr[0] - ql[0];
+  r.W[0][0] = dq;
+  r.s[0] = u;
+  r.amdq[0] = std::min(u, 0.0) * dq;
+  r.apdq[0] = std::max(u, 0.0) * dq;
+}
+
+// Shallow water, Roe linearisation (LeVeque 2002, ch. 15; the "Roe solver
+// with an entropy fix" of the paper's serial timing study, Section 6).
+// q = (h, hu) in 1D, (h, hu, hv) in 2D.  Components: 0 depth, n normal
+// momentum, t tangential momentum.
+struct RoeSW {
+  double ubar, vbar, cbar;   // normal velocity, tangential velocity, celerity
+};
+
+RoeSW sw_roe_avg(const OCfg& c, int d, const double* ql, const double* qr) {
+  const double gr = c.pd[0];
+  const int n = 1 + d, t = 2 - d;
+  const double hl = ql[0], hr = qr[0];
+  const double sl = std::sqrt(hl), sr = std::sqrt(hr);
+  RoeSW a;
+  a.ubar = (sl * (ql[n] / hl) + sr * (qr[n] / hr)) / (sl + sr);
+  a.vbar = c.ndim == 2 ? (sl * (ql[t] / hl) + sr * (qr[t] / hr)) / (sl + sr) : 0.0;
+  a.cbar = std::sqrt(gr * 0.5 * (hl + hr));
+  return a;
+}
+
+void rp_sw_roe(const OCfg& c, int d, const double* ql, const double* qr, FaceSol& r) {
+  const double gr = c.pd[0];
+  const int m = num_eqn(c);
+  const int n = 1 + d, t = 2 - d;
+  const RoeSW a = sw_roe_avg(c, d, ql, qr);
+  double dq[3];
+  for (int k = 0; k < m; ++k) dq[k] = qr[k] - ql[k];
+  const double a1 = ((a.ubar + a.cbar) * dq[0] - dq[n]) / (2.0 * a.cbar);
+  const double a3 = (-(a.ubar - a.cbar) * dq[0] + dq[n]) / (2.0 * a.cbar);
+  std::memset(r.W, 0, sizeof(r.W));
+  // family "first" (left-going acoustic) and "last" (right-going acoustic)
+  const int last = m == 2 ? 1 : 2;
+  r.W[0][0] = a1; r.W[0][n] = a1 * (a.ubar - a.cbar);
+  r.s[0] = a.ubar - a.cbar;
+  r.W[last][0] = a3; r.W[last][n] = a3 * (a.ubar + a.cbar);
+  r.s[last] = a.ubar + a.cbar;
+  if (m == 3) {
+    r.W[0][t] = a1 * a.vbar;
+    r.W[2][t] = a3 * a.vbar;
+    r.W[1][t] = dq[t] - a.vbar * dq[0];   // shear wave
+    r.s[1] = a.ubar;
+  }
+  const int mw = m;
+  for (int k = 0; k < m; ++k) { r.amdq[k] = 0.0; r.apdq[k] = 0.0; }
+  if (!c.efix) {
+    for (int p = 0; p < mw; ++p)
+      for (int k = 0; k < m; ++k) {
+        r.amdq[k] += std::min(r.s[p], 0.0) * r.W[p][k];
+        r.apdq[k] += std::max(r.s[p], 0.0) * r.W[p][k];
+      }
+    return;
+  }
+  // Harten-Hyman entropy fix: a transonic rarefaction in an acoustic family
+  // splits that wave's contribution between A^- and A^+.
+  double coef[3];
+  {  // first family: characteristic speed left of and right of the wave
+    const double lam_l = ql[n] / ql[0] - std::sqrt(gr * ql[0]);
+    const double hm = ql[0] + r.W[0][0], hum = ql[n] + r.W[0][n];
+    const double lam_r = hum / hm - std::sqrt(gr * hm);
+    if (lam_l < 0.0 && 0.0 < lam_r)
+      coef[0] = lam_l * (lam_r - r.s[0]) / (lam_r - lam_l);
+    else
+      coef[0] = std::min(r.s[0], 0.0);
+  }
+  if (m == 3) coef[1] = std::min(r.s[1], 0.0);
+  {  // last family
+    const double hm = qr[0] - r.W[last][0], hum = qr[n] - r.W[last][n];
+    const double lam_l = hum / hm + std::sqrt(gr * hm);
+    const double lam_r = qr[n] / qr[0] + std::sqrt(gr * qr[0]);
+    if (lam_l < 0.0 && 0.0 < lam_r)
+      coef[last] = lam_l * (lam_r - r.s[last]) / (lam_r - lam_l);
+    else
+      coef[last] = std::min(r.s[last], 0.0);
+  }
+  for (int p = 0; p < mw; ++p)
+    for (int k = 0; k < m; ++k) r.amdq[k] += coef[p] * r.W[p][k];
+  for (int k = 0; k < m; ++k) {
+    double sw = 0.0;
+    for (int p = 0; p < mw; ++p) sw += r.s[p] * r.W[p][k];
+    r.apdq[k] = sw - r.amdq[k];
+  }
+}
+
+// Linear elasticity with variable coefficients (LeVeque 2002, ch. 22 system,
+// decomposed as for variable-coefficient acoustics, ch. 9).
+// q = (s11, s22, s12, u, v); aux = (rho, lambda, mu).
+struct Mat {
+  double rho, lam, mu, a, cp, cs;
+};
+Mat material(const double* aux) {
+  Mat t;
+  t.rho = aux[0]; t.lam = aux[1]; t.mu = aux[2];
+  t.a = t.lam + 2.0 * t.mu;
+  t.cp = std::sqrt(t.a / t.rho);
+  t.cs = std::sqrt(t.mu / t.rho);
+  return t;
+}
+// Index map for direction d: sn normal stress, so other normal stress,
+// sh shear stress, vn normal velocity, vt tangential velocity.
+struct EIdx { int sn, so, sh, vn, vt; };
+EIdx eidx(int d) { return d == 0 ? EIdx{0, 1, 2, 3, 4} : EIdx{1, 0, 2, 4, 3}; }
+
+void rp_elastic(int d, const double* ql, const double* qr, const double* auxl,
+                const double* auxr, FaceSol& r) {
+  const EIdx e = eidx(d);
+  const Mat L = material(auxl), R = material(auxr);
+  double dq[5];
+  for (int k = 0; k < 5; ++k) dq[k] = qr[k] - ql[k];
+  const double D = L.a * R.cp + R.a * L.cp;
+  const double a1 = (R.cp * dq[e.sn] + R.a * dq[e.vn]) / D;
+  const double a4 = (L.cp * dq[e.sn] - L.a * dq[e.vn]) / D;
+  const double Ds = L.mu * R.cs + R.mu * L.cs;
+  const double a2 = (R.cs * dq[e.sh] + R.mu * dq[e.vt]) / Ds;
+  const double a3 = (L.cs * dq[e.sh] - L.mu * dq[e.vt]) / Ds;
+  std::memset(r.W, 0, sizeof(r.W));
+  r.W[0][e.sn] = a1 * L.a; r.W[0][e.so] = a1 * L.lam; r.W[0][e.vn] = a1 * L.cp;
+  r.s[0] = -L.cp;
+  r.W[1][e.sh] = a2 * L.mu; r.W[1][e.vt] = a2 * L.cs;
+  r.s[1] = -L.cs;
+  r.W[2][e.sh] = a3 * R.mu; r.W[2][e.vt] = -a3 * R.cs;
+  r.s[2] = R.cs;
+  r.W[3][e.sn] = a4 * R.a; r.W[3][e.so] = a4 * R.lam; r.W[3][e.vn] = -a4 * R.cp;
+  r.s[3] = R.cp;
+  for (int k = 0; k < 5; ++k) {
+    r.amdq[k] = r.s[0] * r.W[0][k] + r.s[1] * r.W[1][k];
+    r.apdq[k] = r.s[2] * r.W[2][k] + r.s[3] * r.W[3][k];
+  }
+}
+
+void rp_normal(const OCfg& c, int d, const double* ql, const double* qr, const double* auxl,
+               const double* auxr, FaceSol& r) {
+  switch (c.solver) {
+    case S_ADV: rp_advection(c, d, ql, qr, r); break;
+    case S_SW: rp_sw_roe(c, d, ql, qr, r); break;
+    case S_ELASTIC: rp_elastic(d, ql, qr, auxl, auxr, r); break;
+    default: std::memset(&r, 0, sizeof(r)); break;
+  }
+}
+
+// Transverse Riemann solver (Section 2.1: the secondary solver of the unsplit
+// multidimensional algorithms).  A fluctuation asdq produced at a face normal
+// to direction d lives in one cell; split it into the parts propagating toward
+// lower (bm) and higher (bp) index in the other direction.  ql, qr are the
+// states of the face where asdq was produced; aux_m, aux_c, aux_p are the
+// materials of that cell's lower neighbour, the cell, and its upper neighbour
+// in the transverse direction.
+void rp_transverse(const OCfg& c, int d, const double* ql, const double* qr, const double* aux_m,
+                   const double* aux_c, const double* aux_p, const double* asdq, double* bm,
+                   double* bp) {
+  const int m = num_eqn(c);
+  if (c.solver == S_ADV) {
+    const double v = c.pd[1 - d];
+    bm[0] = std::min(v, 0.0) * asdq[0];
+    bp[0] = std::max(v, 0.0) * asdq[0];
+    return;
+  }
+  if (c.solver == S_SW) {
+    // eigen-decomposition in the transverse direction with the face's Roe averages
+    const RoeSW a = sw_roe_avg(c, d, ql, qr);
+    const int n = 1 + d, t = 2 - d;
+    const double b1 = ((a.vbar + a.cbar) * asdq[0] - asdq[t]) / (2.0 * a.cbar);
+    const double b3 = (-(a.vbar - a.cbar) * asdq[0] + asdq[t]) / (2.0 * a.cbar);
+    const double b2 = asdq[n] - a.ubar * asdq[0];
+    const double l1 = a.vbar - a.cbar, l2 = a.vbar, l3 = a.vbar + a.cbar;
+    double r1[3], r2[3], r3[3];
+    r1[0] = 1.0; r1[n] = a.ubar; r1[t] = a.vbar - a.cbar;
+    r2[0] = 0.0; r2[n] = 1.0;    r2[t] = 0.0;
+    r3[0] = 1.0; r3[n] = a.ubar; r3[t] = a.vbar + a.cbar;
+    for (int k = 0; k < 3; ++k) {
+      bm[k] = std::min(l1, 0.0) * b1 * r1[k] + std::min(l2, 0.0) * b2 * r2[k] +
+              std::min(l3, 0.0) * b3 * r3[k];
+      bp[k] = std::max(l1, 0.0) * b1 * r1[k] + std::max(l2, 0.0) * b2 * r2[k] +
+              std::max(l3, 0.0) * b3 * r3[k];
+    }
+    (void)m;
+    return;
+  }
+  if (c.solver == S_ELASTIC) {
+    const int t = 1 - d;   // transverse direction
+    const EIdx e = eidx(t);
+    const Mat M = material(aux_m), C = material(aux_c), P = material(aux_p);
+    // down-going: the face between the lower neighbour (left) and the cell (right)
+    const double b1 = (C.cp * asdq[e.sn] + C.a * asdq[e.vn]) / (M.a * C.cp + C.a * M.cp);
+    const double b2 = (C.cs * asdq[e.sh] + C.mu * asdq[e.vt]) / (M.mu * C.cs + C.mu * M.cs);
+    // up-going: the face between the cell (left) and the upper neighbour (right)
+    const double b3 = (C.cs * asdq[e.sh] - C.mu * asdq[e.vt]) / (C.mu * P.cs + P.mu * C.cs);
+    const double b4 = (C.cp * asdq[e.sn] - C.a * asdq[e.vn]) / (C.a * P.cp + P.a * C.cp);
+    for (int k = 0; k < 5; ++k) { bm[k] = 0.0; bp[k] = 0.0; }
+    // bm = -cp_m b1 r1(m) - cs_m b2 r2(m)
+    bm[e.sn] += -M.cp * b1 * M.a;
+    bm[e.so] += -M.cp * b1 * M.lam;
+    bm[e.vn] += -M.cp * b1 * M.cp;
+    bm[e.sh] += -M.cs * b2 * M.mu;
+    bm[e.vt] += -M.cs * b2 * M.cs;
+    // bp = cs_p b3 r3(p) + cp_p b4 r4(p)
+    bp[e.sh] += P.cs * b3 * P.mu;
+    bp[e.vt] += P.cs * b3 * (-P.cs);
+    bp[e.sn] += P.cp * b4 * P.a;
+    bp[e.so] += P.cp * b4 * P.lam;
+    bp[e.vn] += P.cp * b4 * (-P.cp);
+    return;
+  }
+  for (int k = 0; k < m; ++k) { bm[k] = 0.0; bp[k] = 0.0; }
+}
+
+// Wave limiter (Section 2: the limiter acts on waves, not fluxes; LeVeque 2002,
+// ch. 6 and 9).  theta = (W_upwind . W) / (W . W); the upwind face is the
+// lower-index neighbour when s > 0, else the higher-index one.
+double limiter_phi(int lim, double th) {
+  switch (lim) {
+    case 0: return 1.0;
+    case 1: return std::max(0.0, std::min(1.0, th));                                // minmod
+    case 2: return std::max(0.0, std::min(std::min((1.0 + th) / 2.0, 2.0), 2.0 * th));  // MC
+  }
+  return 1.0;
+}
+
+void limit_waves(const OCfg& c, int m, int mw, const FaceSol& lo, const FaceSol& me,
+                 const FaceSol& hi, double Wl[4][5]) {
+  for (int p = 0; p < mw; ++p) {
+    double nrm = 0.0, dlo = 0.0, dhi = 0.0;
+    for (int k = 0; k < m; ++k) {
+      nrm += me.W[p][k] * me.W[p][k];
+      dlo += lo.W[p][k] * me.W[p][k];
+      dhi += hi.W[p][k] * me.W[p][k];
+    }
+    double phi = 0.0;
+    if (nrm != 0.0) {
+      const double th = (me.s[p] > 0.0 ? dlo : dhi) / nrm;
+      phi = limiter_phi(c.limiter, th);
+    }
+    for (int k = 0; k < m; ++k) Wl[p][k] = phi * me.W[p][k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Classic Clawpack step (Section 2, eq. lwflux and eq. fluxdiff; Section 2.1,
+// transverse corrections; LeVeque 1997).
+// ---------------------------------------------------------------------------
+
+double classic_1d(const OCfg& c, const double* qin, double* qout, double dt) {
+  const int m = num_eqn(c), mw = num_waves(c), nx = c.nx;
+  const double dx = dx_of(c), dtdx = dt / dx;
+  Field Q;
+  load_field(c, Q, qin, m, 2, false);
+  // faces f = -1 .. nx+1 ; face f lies between cells f-1 and f
+  std::vector<FaceSol> F(nx + 3);
+  for (int f = -1; f <= nx + 1; ++f) {
+    double ql[5], qr[5];
+    for (int k = 0; k < m; ++k) { ql[k] = Q.at(k, 0, f - 1); qr[k] = Q.at(k, 0, f); }
+    rp_normal(c, 0, ql, qr, nullptr, nullptr, F[f + 1]);
+  }
+  double smax = 0.0;
+  std::vector<double> Ft((size_t)(nx + 1) * m, 0.0);
+  for (int f = 0; f <= nx; ++f) {
+    const FaceSol& me = F[f + 1];
+    double Wl[4][5];
+    limit_waves(c, m, mw, F[f], me, F[f + 2], Wl);
+    for (int p = 0; p < mw; ++p) {
+      const double as = std::fabs(me.s[p]);
+      smax = std::max(smax, as / dx);
+      for (int k = 0; k < m; ++k) Ft[(size_t)f * m + k] += 0.5 * as * (1.0 - dtdx * as) * Wl[p][k];
+    }
+  }
+  for (int k = 0; k < m; ++k)
+    for (int i = 0; i < nx; ++i) {
+      const FaceSol& lo = F[i + 1];   // face i   (left of cell i)
+      const FaceSol& hi = F[i + 2];   // face i+1 (right of cell i)
+      qout[(size_t)k * nx + i] =
+          Q.at(k, 0, i) - dtdx * (lo.apdq[k] + hi.amdq[k]) -
+          dtdx * (Ft[(size_t)(i + 1) * m + k] - Ft[(size_t)i * m + k]);
+    }
+  return smax;
+}
+
+double classic_2d(const OCfg& c, const double* qin, const double* auxin, double* qout, double dt) {
+  const int m = num_eqn(c), mw = num_waves(c), na = num_aux(c);
+  const int nx = c.nx, ny = c.ny;
+  const double dx = dx_of(c), dy = dy_of(c);
+  const double dtdx = dt / dx, dtdy = dt / dy;
+  Field Q, A;
+  load_field(c, Q, qin, m, 2, false);
+  load_field(c, A, auxin, na, 2, true);
+  static const double zero_aux[3] = {0.0, 0.0, 0.0};
+  auto auxp = [&](int j, int i, double* buf) -> const double* {
+    if (na == 0) return zero_aux;
+    for (int k = 0; k < na; ++k) buf[k] = A.at(k, j, i);
+    return buf;
+  };
+
+  // x-faces: face (f, j) between cells (f-1, j) and (f, j); f in [-1, nx+1], j in [-1, ny]
+  const int XW = nx + 3, XH = ny + 2;
+  std::vector<FaceSol> XF((size_t)XW * XH);
+  auto xf = [&](int f, int j) -> FaceSol& { return XF[(size_t)(j + 1) * XW + (f + 1)]; };
+  // y-faces: face (i, g) between cells (i, g-1) and (i, g); g in [-1, ny+1], i in [-1, nx]
+  const int YW = nx + 2, YH = ny + 3;
+  std::vector<FaceSol> YF((size_t)YW * YH);
+  auto yf = [&](int i, int g) -> FaceSol& { return YF[(size_t)(g + 1) * YW + (i + 1)]; };
+
+#pragma omp parallel for schedule(static)
+  for (int j = -1; j <= ny; ++j)
+    for (int f = -1; f <= nx + 1; ++f) {
+      double ql[5], qr[5], al[3], ar[3];
+      for (int k = 0; k < m; ++k) { ql[k] = Q.at(k, j, f - 1); qr[k] = Q.at(k, j, f); }
+      rp_normal(c, 0, ql, qr, auxp(j, f - 1, al), auxp(j, f, ar), xf(f, j));
+    }
+#pragma omp parallel for schedule(static)
+  for (int g = -1; g <= ny + 1; ++g)
+    for (int i = -1; i <= nx; ++i) {
+      double ql[5], qr[5], al[3], ar[3];
+      for (int k = 0; k < m; ++k) { ql[k] = Q.at(k, g - 1, i); qr[k] = Q.at(k, g, i); }
+      rp_normal(c, 1, ql, qr, auxp(g - 1, i, al), auxp(g, i, ar), yf(i, g));
+    }
+
+  // Correction fluxes: Fx at x-faces (f in [0,nx], j in [0,ny)), Gy at y-faces
+  // (i in [0,nx), g in [0,ny]).  Each holds the limited second-order term plus
+  // the transverse contributions from faces of the other direction.
+  std::vector<double> Fc((size_t)(nx + 1) * ny * m, 0.0), Gc((size_t)nx * (ny + 1) * m, 0.0);
+  auto fc = [&](int f, int j, int k) -> double& { return Fc[((size_t)j * (nx + 1) + f) * m + k]; };
+  auto gc = [&](int i, int g, int k) -> double& { return Gc[((size_t)g * nx + i) * m + k]; };
+
+  double smax = 0.0;
+  // x sweep: limiter, correction flux, transverse split into G (serial: scatter)
+  for (int j = -1; j <= ny; ++j)
+    for (int f = 0; f <= nx; ++f) {
+      const FaceSol& me = xf(f, j);
+      double Wl[4][5], cq[5] = {0, 0, 0, 0, 0};
+      limit_waves(c, m, mw, xf(f - 1, j), me, xf(f + 1, j), Wl);
+      for (int p = 0; p < mw; ++p) {
+        const double as = std::fabs(me.s[p]);
+        if (j >= 0 && j < ny) smax = std::max(smax, as / dx);
+        for (int k = 0; k < m; ++k) cq[k] += as * (1.0 - dtdx * as) * Wl[p][k];
+      }
+      if (j >= 0 && j < ny)
+        for (int k = 0; k < m; ++k) fc(f, j, k) += 0.5 * cq[k];
+      if (c.transverse == 0) continue;
+      double am[5], ap[5];
+      for (int k = 0; k < m; ++k) {
+        am[k] = me.amdq[k] + (c.transverse == 2 ? cq[k] : 0.0);
+        ap[k] = me.apdq[k] - (c.transverse == 2 ? cq[k] : 0.0);
+      }
+      double ql[5], qr[5];
+      for (int k = 0; k < m; ++k) { ql[k] = Q.at(k, j, f - 1); qr[k] = Q.at(k, j, f); }
+      double bm[5], bp[5], a0[3], a1[3], a2[3];
+      // A^+ part lives in cell (f, j): feeds G at y-faces (f, j) and (f, j+1)
+      rp_transverse(c, 0, ql, qr, auxp(j - 1, f, a0), auxp(j, f, a1), auxp(j + 1, f, a2), ap, bm, bp);
+      if (f < nx) {
+        if (j + 1 >= 0 && j + 1 <= ny)
+          for (int k = 0; k < m; ++k) gc(f, j + 1, k) -= 0.5 * dtdx * bp[k];
+        if (j >= 0 && j <= ny)
+          for (int k = 0; k < m; ++k) gc(f, j, k) -= 0.5 * dtdx * bm[k];
+      }
+      // A^- part lives in cell (f-1, j)
+      rp_transverse(c, 0, ql, qr, auxp(j - 1, f - 1, a0), auxp(j, f - 1, a1), auxp(j + 1, f - 1, a2),
+                    am, bm, bp);
+      if (f - 1 >= 0) {
+        if (j + 1 >= 0 && j + 1 <= ny)
+          for (int k = 0; k < m; ++k) gc(f - 1, j + 1, k) -= 0.5 * dtdx * bp[k];
+        if (j >= 0 && j <= ny)
+          for (int k = 0; k < m; ++k) gc(f - 1, j, k) -= 0.5 * dtdx * bm[k];
+      }
+    }
+  // y sweep
+  for (int g = 0; g <= ny; ++g)
+    for (int i = -1; i <= nx; ++i) {
+      const FaceSol& me = yf(i, g);
+      double Wl[4][5], cq[5] = {0, 0, 0, 0, 0};
+      limit_waves(c, m, mw, yf(i, g - 1), me, yf(i, g + 1), Wl);
+      for (int p = 0; p < mw; ++p) {
+        const double as = std::fabs(me.s[p]);
+        if (i >= 0 && i < nx) smax = std::max(smax, as / dy);
+        for (int k = 0; k < m; ++k) cq[k] += as * (1.0 - dtdy * as) * Wl[p][k];
+      }
+      if (i >= 0 && i < nx)
+        for (int k = 0; k < m; ++k) gc(i, g, k) += 0.5 * cq[k];
+      if (c.transverse == 0) continue;
+      double bmq[5], bpq[5];
+      for (int k = 0; k < m; ++k) {
+        bmq[k] = me.amdq[k] + (c.transverse == 2 ? cq[k] : 0.0);
+        bpq[k] = me.apdq[k] - (c.transverse == 2 ? cq[k] : 0.0);
+      }
+      double ql[5], qr[5];
+      for (int k = 0; k < m; ++k) { ql[k] = Q.at(k, g - 1, i); qr[k] = Q.at(k, g, i); }
+      double lm[5], lp[5], a0[3], a1[3], a2[3];
+      // B^+ part lives in cell (i, g): feeds F at x-faces (i, g) and (i+1, g)
+      rp_transverse(c, 1, ql, qr, auxp(g, i - 1, a0), auxp(g, i, a1), auxp(g, i + 1, a2), bpq, lm, lp);
+      if (g < ny) {
+        if (i + 1 >= 0 && i + 1 <= nx)
+          for (int k = 0; k < m; ++k) fc(i + 1, g, k) -= 0.5 * dtdy * lp[k];
+        if (i >= 0 && i <= nx)
+          for (int k = 0; k < m; ++k) fc(i, g, k) -= 0.5 * dtdy * lm[k];
+      }
+      // B^- part lives in cell (i, g-1)
+      rp_transverse(c, 1, ql, qr, auxp(g - 1, i - 1, a0), auxp(g - 1, i, a1), auxp(g - 1, i + 1, a2),
+                    bmq, lm, lp);
+      if (g - 1 >= 0) {
+        if (i + 1 >= 0 && i + 1 <= nx)
+          for (int k = 0; k < m; ++k) fc(i + 1, g - 1, k) -= 0.5 * dtdy * lp[k];
+        if (i >= 0 && i <= nx)
+          for (int k = 0; k < m; ++k) fc(i, g - 1, k) -= 0.5 * dtdy * lm[k];
+      }
+    }
+
+  // cell update, eq. fluxdiff with fluctuations and correction fluxes
+#pragma omp parallel for schedule(static)
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i)
+      for (int k = 0; k < m; ++k) {
+        const double xs = xf(i, j).apdq[k] + xf(i + 1, j).amdq[k] + fc(i + 1, j, k) - fc(i, j, k);
+        const double ys = yf(i, j).apdq[k] + yf(i, j + 1).amdq[k] + gc(i, j + 1, k) - gc(i, j, k);
+        qout[((size_t)k * ny + j) * nx + i] = Q.at(k, j, i) - dtdx * xs - dtdy * ys;
+      }
+  return smax;
+}
+
+// ---------------------------------------------------------------------------
+// SharpClaw (Section 2, method of lines; Section 2.1: WENO5 in space, SSP
+// Runge-Kutta in time, normal Riemann problems only in multi-D).
+// ---------------------------------------------------------------------------
+
+// WENO5 (Jiang-Shu) from five cell averages v[0..4] centred on cell i = v[2]:
+// qL = value at the right edge of cell i (x_{i+1/2}, seen from the left),
+// qR = value at the left edge of cell i (x_{i-1/2}, seen from the right).
+void weno5(const double* v, double eps, double* qL, double* qR) {
+  const double vm2 = v[0], vm1 = v[1], v0 = v[2], vp1 = v[3], vp2 = v[4];
+  const double b0 = 13.0 / 12.0 * (vm2 - 2.0 * vm1 + v0) * (vm2 - 2.0 * vm1 + v0) +
+                    0.25 * (vm2 - 4.0 * vm1 + 3.0 * v0) * (vm2 - 4.0 * vm1 + 3.0 * v0);
+  const double b1 = 13.0 / 12.0 * (vm1 - 2.0 * v0 + vp1) * (vm1 - 2.0 * v0 + vp1) +
+                    0.25 * (vm1 - vp1) * (vm1 - vp1);
+  const double b2 = 13.0 / 12.0 * (v0 - 2.0 * vp1 + vp2) * (v0 - 2.0 * vp1 + vp2) +
+                    0.25 * (3.0 * v0 - 4.0 * vp1 + vp2) * (3.0 * v0 - 4.0 * vp1 + vp2);
+  // right edge of cell i
+  {
+    const double p0 = (2.0 * vm2 - 7.0 * vm1 + 11.0 * v0) / 6.0;
+    const double p1 = (-vm1 + 5.0 * v0 + 2.0 * vp1) / 6.0;
+    const double p2 = (2.0 * v0 + 5.0 * vp1 - vp2) / 6.0;
+    const double a0 = 0.1 / ((eps + b0) * (eps + b0));
+    const double a1 = 0.6 / ((eps + b1) * (eps + b1));
+    const double a2 = 0.3 / ((eps + b2) * (eps + b2));
+    *qL = (a0 * p0 + a1 * p1 + a2 * p2) / (a0 + a1 + a2);
+  }
+  // left edge of cell i: mirror image (stencils reversed, linear weights reversed)
+  {
+    const double p0 = (-vm2 + 5.0 * vm1 + 2.0 * v0) / 6.0;
+    const double p1 = (2.0 * vm1 + 5.0 * v0 - vp1) / 6.0;
+    const double p2 = (11.0 * v0 - 7.0 * vp1 + 2.0 * vp2) / 6.0;
+    const double a0 = 0.3 / ((eps + b0) * (eps + b0));
+    const double a1 = 0.6 / ((eps + b1) * (eps + b1));
+    const double a2 = 0.1 / ((eps + b2) * (eps + b2));
+    *qR = (a0 * p0 + a1 * p1 + a2 * p2) / (a0 + a1 + a2);
+  }
+}
+
+// Physical flux in direction d.
+void euler_flux(const OCfg& c, int d, const double* q, double* f, double* un_out, double* cs_out) {
+  const double gam = c.pd[0];
+  const int m = num_eqn(c);
+  const double rho = q[0];
+  const double u = q[1] / rho;
+  const double v = m == 4 ? q[2] / rho : 0.0;
+  const double E = q[m - 1];
+  const double p = (gam - 1.0) * (E - 0.5 * rho * (u * u + v * v));
+  const double un = d == 0 ? u : v;
+  f[0] = rho * un;
+  f[1] = q[1] * un + (d == 0 ? p : 0.0);
+  if (m == 4) f[2] = q[2] * un + (d == 1 ? p : 0.0);
+  f[m - 1] = (E + p) * un;
+  *un_out = un;
+  *cs_out = std::sqrt(gam * p / rho);
+}
+
+// HLLE numerical flux (Einfeldt 1988) with Roe-average speed estimates.
+double flux_hlle(const OCfg& c, int d, const double* ql, const double* qr, double* F) {
+  const double gam = c.pd[0];
+  const int m = num_eqn(c);
+  double fl[4], fr[4], unl, unr, cl, cr;
+  euler_flux(c, d, ql, fl, &unl, &cl);
+  euler_flux(c, d, qr, fr, &unr, &cr);
+  const double rl = ql[0], rr = qr[0];
+  const double wl = std::sqrt(rl), wr = std::sqrt(rr);
+  const double ul = ql[1] / rl, ur = qr[1] / rr;
+  const double vl = m == 4 ? ql[2] / rl : 0.0, vr = m == 4 ? qr[2] / rr : 0.0;
+  const double pl = (gam - 1.0) * (ql[m - 1] - 0.5 * rl * (ul * ul + vl * vl));
+  const double pr = (gam - 1.0) * (qr[m - 1] - 0.5 * rr * (ur * ur + vr * vr));
+  const double Hl = (ql[m - 1] + pl) / rl, Hr = (qr[m - 1] + pr) / rr;
+  const double ut = (wl * ul + wr * ur) / (wl + wr);
+  const double vt = (wl * vl + wr * vr) / (wl + wr);
+  const double Ht = (wl * Hl + wr * Hr) / (wl + wr);
+  const double ct = std::sqrt((gam - 1.0) * (Ht - 0.5 * (ut * ut + vt * vt)));
+  const double unt = d == 0 ? ut : vt;
+  const double s1 = std::min(unl - cl, unt - ct);
+  const double s2 = std::max(unr + cr, unt + ct);
+  for (int k = 0; k < m; ++k) {
+    if (s1 >= 0.0)
+      F[k] = fl[k];
+    else if (s2 <= 0.0)
+      F[k] = fr[k];
+    else
+      F[k] = (s2 * fl[k] - s1 * fr[k] + s1 * s2 * (qr[k] - ql[k])) / (s2 - s1);
+  }
+  return std::max(std::fabs(s1), std::fabs(s2));
+}
+
+// Upwind flux for scalar advection.
+double flux_advection(const OCfg& c, int d, const double* ql, const double* qr, double* F) {
+  const double u = c.pd[d];
+  F[0] = u > 0.0 ? u * ql[0] : u * qr[0];
+  return std::fabs(u);
+}
+
+double num_flux(const OCfg& c, int d, const double* ql, const double* qr, double* F) {
+  if (c.solver == S_EULER) return flux_hlle(c, d, ql, qr, F);
+  return flux_advection(c, d, ql, qr, F);
+}
+
+// Semi-discrete operator L(Q) = -(F_{i+1/2}-F_{i-1/2})/dx - (G_{j+1/2}-G_{j-1/2})/dy.
+// Returns the largest |speed|/spacing over faces bounding interior cells.
+double sharpclaw_L(const OCfg& c, const double* qin, double* L) {
+  const int m = num_eqn(c), nx = c.nx, ny = c.ny;
+  const double dx = dx_of(c), dy = dy_of(c);
+  Field Q;
+  load_field(c, Q, qin, m, 3, false);
+  std::fill(L, L + (size_t)m * nx * ny, 0.0);
+  double smax = 0.0;
+  // x direction: one row at a time
+#pragma omp parallel for schedule(static) reduction(max : smax)
+  for (int j = 0; j < ny; ++j) {
+    // edge values of cells -1 .. nx
+    std::vector<double> eL((size_t)(nx + 2) * m), eR((size_t)(nx + 2) * m);
+    for (int i = -1; i <= nx; ++i)
+      for (int k = 0; k < m; ++k) {
+        double v[5];
+        for (int s = 0; s < 5; ++s) v[s] = Q.at(k, j, i - 2 + s);
+        weno5(v, c.weno_eps, &eL[(size_t)(i + 1) * m + k], &eR[(size_t)(i + 1) * m + k]);
+      }
+    std::vector<double> Fx((size_t)(nx + 1) * m);
+    for (int f = 0; f <= nx; ++f) {
+      double ql[5], qr[5];
+      for (int k = 0; k < m; ++k) {
+        ql[k] = eL[(size_t)f * m + k];         // right edge of cell f-1
+        qr[k] = eR[(size_t)(f + 1) * m + k];   // left edge of cell f
+      }
+      const double sp = num_flux(c, 0, ql, qr, &Fx[(size_t)f * m]);
+      smax = std::max(smax, sp / dx);
+    }
+    for (int i = 0; i < nx; ++i)
+      for (int k = 0; k < m; ++k)
+        L[((size_t)k * ny + j) * nx + i] -= (Fx[(size_t)(i + 1) * m + k] - Fx[(size_t)i * m + k]) / dx;
+  }
+  if (c.ndim == 2) {
+#pragma omp parallel for schedule(static) reduction(max : smax)
+    for (int i = 0; i < nx; ++i) {
+      std::vector<double> eL((size_t)(ny + 2) * m), eR((size_t)(ny + 2) * m);
+      for (int j = -1; j <= ny; ++j)
+        for (int k = 0; k < m; ++k) {
+          double v[5];
+          for (int s = 0; s < 5; ++s) v[s] = Q.at(k, j - 2 + s, i);
+          weno5(v, c.weno_eps, &eL[(size_t)(j + 1) * m + k], &eR[(size_t)(j + 1) * m + k]);
+        }
+      std::vector<double> Gy((size_t)(ny + 1) * m);
+      for (int g = 0; g <= ny; ++g) {
+        double ql[5], qr[5];
+        for (int k = 0; k < m; ++k) {
+          ql[k] = eL[(size_t)g * m + k];
+          qr[k] = eR[(size_t)(g + 1) * m + k];
+        }
+        const double sp = num_flux(c, 1, ql, qr, &Gy[(size_t)g * m]);
+        smax = std::max(smax, sp / dy);
+      }
+      for (int j = 0; j < ny; ++j)
+        for (int k = 0; k < m; ++k)
+          L[((size_t)k * ny + j) * nx + i] -= (Gy[(size_t)(j + 1) * m + k] - Gy[(size_t)j * m + k]) / dy;
+    }
+  }
+  return smax;
+}
+
+// SSPRK(3,3) of Shu and Osher.  The Courant number is taken from the speeds
+// of the first stage (at Q^n).
+double sharpclaw_step(const OCfg& c, const double* qin, double* qout, double dt) {
+  const size_t N = (size_t)num_eqn(c) * c.nx * c.ny;
+  std::vector<double> L(N), Q1(N), Q2(N);
+  const double smax = sharpclaw_L(c, qin, L.data());
+  for (size_t n = 0; n < N; ++n) Q1[n] = qin[n] + dt * L[n];
+  sharpclaw_L(c, Q1.data(), L.data());
+  for (size_t n = 0; n < N; ++n) Q2[n] = 0.75 * qin[n] + 0.25 * (Q1[n] + dt * L[n]);
+  sharpclaw_L(c, Q2.data(), L.data());
+  for (size_t n = 0; n < N; ++n) qout[n] = qin[n] / 3.0 + 2.0 / 3.0 * (Q2[n] + dt * L[n]);
+  return smax;
+}
+
+double one_step(const OCfg& c, const double* qin, const double* aux, double* qout, double dt) {
+  if (c.scheme == 2) return sharpclaw_step(c, qin, qout, dt);
+  if (c.ndim == 1) return classic_1d(c, qin, qout, dt);
+  return classic_2d(c, qin, aux, qout, dt);
+}
+
+// Largest characteristic speed over spacing among the cells: used for the
+// a-priori first time step when none is given.
+double max_cell_speed(const OCfg& c, const double* q, const double* aux) {
+  const int m = num_eqn(c);
+  const size_t N = (size_t)c.nx * c.ny;
+  const double dx = dx_of(c), dy = dy_of(c);
+  double best = 0.0;
+  for (size_t n = 0; n < N; ++n) {
+    double s = 0.0;
+    switch (c.solver) {
+      case S_ADV:
+        s = std::fabs(c.pd[0]) / dx;
+        if (c.ndim == 2) s = std::max(s, std::fabs(c.pd[1]) / dy);
+        break;
+      case S_SW: {
+        const double h = q[n], cel = std::sqrt(c.pd[0] * h);
+        s = (std::fabs(q[N + n] / h) + cel) / dx;
+        if (c.ndim == 2) s = std::max(s, (std::fabs(q[2 * N + n] / h) + cel) / dy);
+      } break;
+      case S_EULER: {
+        const double rho = q[n], u = q[N + n] / rho;
+        const double v = m == 4 ? q[2 * N + n] / rho : 0.0;
+        const double E = q[(size_t)(m - 1) * N + n];
+        const double p = (c.pd[0] - 1.0) * (E - 0.5 * rho * (u * u + v * v));
+        const double cs = std::sqrt(c.pd[0] * p / rho);
+        s = (std::fabs(u) + cs) / dx;
+        if (c.ndim == 2) s = std::max(s, (std::fabs(v) + cs) / dy);
+      } break;
+      case S_ELASTIC: {
+        const double cp = std::sqrt((aux[N + n] + 2.0 * aux[2 * N + n]) / aux[n]);
+        s = std::max(cp / dx, cp / dy);
+      } break;
+    }
+    best = std::max(best, s);
+  }
+  return best;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C entry points used by the Python test harness.
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int or_num_eqn(const OCfg* c) { return num_eqn(*c); }
+int or_num_waves(const OCfg* c) { return num_waves(*c); }
+int or_num_aux(const OCfg* c) { return num_aux(*c); }
+
+// One step of size dt from qin to qout.  *speed receives the largest
+// |wave speed|/spacing over faces bounding interior cells (the Courant number
+// of the step is dt * speed).
+int or_step(const OCfg* c, const double* qin, const double* aux, double* qout, double dt,
+            double* speed) {
+  *speed = one_step(*c, qin, aux, qout, dt);
+  return 0;
+}
+
+double or_max_cell_speed(const OCfg* c, const double* q, const double* aux) {
+  return max_cell_speed(*c, q, aux);
+}
+
+// Time-step controller (Section 5: after each step the Courant number is
+// checked against the stability limit and the next step size is chosen).
+//   dt_try = min(dt, t_end - t); step; C = dt_try * speed;
+//   C <= cfl_max: accept (t = t_end exactly on the clipped step), else keep Q^n;
+//   dt = min(dt_max, dt_try * cfl_desired / C)  (dt_max if C == 0).
+// q is updated in place.  Logs (optional, capacity log_cap): dt tried and
+// whether it was accepted.  Returns 0, or -5 on a non-finite Courant number,
+// or -8 when max_steps attempts did not reach t_end.
+int or_advance(const OCfg* c, double* q, const double* aux, double* t_io, double t_end,
+               double* dt_io, double cfl_desired, double cfl_max, double dt_max, long max_steps,
+               double* dt_log, int* acc_log, long log_cap, long* n_acc, long* n_rej,
+               double* max_courant) {
+  const size_t N = (size_t)num_eqn(*c) * c->nx * c->ny;
+  std::vector<double> qn(N);
+  double t = *t_io, dt = *dt_io;
+  if (dt_max <= 0.0) dt_max = std::numeric_limits<double>::infinity();
+  if (dt <= 0.0) {
+    const double s = max_cell_speed(*c, q, aux);
+    dt = s > 0.0 ? std::min(dt_max, cfl_desired / s) : dt_max;
+  }
+  long acc = 0, rej = 0, attempts = 0;
+  double cmax = 0.0;
+  int rc = 0;
+  while (t < t_end) {
+    if (attempts >= max_steps) { rc = -8; break; }
+    const bool clipped = t + dt >= t_end;
+    const double dt_try = clipped ? t_end - t : dt;
+    const double speed = one_step(*c, q, aux, qn.data(), dt_try);
+    const double C = dt_try * speed;
+    if (!(C == C) || std::isinf(C)) { rc = -5; break; }
+    const bool ok = C <= cfl_max;
+    if (dt_log && attempts < log_cap) { dt_log[attempts] = dt_try; acc_log[attempts] = ok ? 1 : 0; }
+    ++attempts;
+    if (ok) {
+      std::memcpy(q, qn.data(), N * sizeof(double));
+      t = clipped ? t_end : t + dt_try;
+      ++acc;
+      cmax = std::max(cmax, C);
+    } else {
+      ++rej;
+    }
+    dt = C > 0.0 ? std::min(dt_max, dt_try * cfl_desired / C) : dt_max;
+  }
+  *t_io = t;
+  *dt_io = dt;
+  *n_acc = acc;
+  *n_rej = rej;
+  *max_courant = cmax;
+  return rc;
+}
+
+// Per-face Riemann solve (exposed for algebraic identity tests).
+int or_riemann(const OCfg* c, int d, const double* ql, const double* qr, const double* auxl,
+               const double* auxr, double* W /*[4][5]*/, double* s /*[4]*/, double* amdq,
+               double* apdq) {
+  FaceSol r;
+  std::memset(&r, 0, sizeof(r));
+  rp_normal(*c, d, ql, qr, auxl, auxr, r);
+  std::memcpy(W, r.W, sizeof(r.W));
+  std::memcpy(s, r.s, sizeof(r.s));
+  std::memcpy(amdq, r.amdq, sizeof(r.amdq));
+  std::memcpy(apdq, r.apdq, sizeof(r.apdq));
+  return 0;
+}
+
+int or_transverse(const OCfg* c, int d, const double* ql, const double* qr, const double* aux_m,
+                  const double* aux_c, const double* aux_p, const double* asdq, double* bm,
+                  double* bp) {
+  rp_transverse(*c, d, ql, qr, aux_m, aux_c, aux_p, asdq, bm, bp);
+  return 0;
+}
+
+double or_num_flux(const OCfg* c, int d, const double* ql, const double* qr, double* F) {
+  return num_flux(*c, d, ql, qr, F);
+}
+
+void or_weno5(const double* v, double eps, double* qL, double* qR) { weno5(v, eps, qL, qR); }
+
+double or_limiter(int lim, double theta) { return limiter_phi(lim, theta); }
+
+// Conserved totals: sum over cells of q_k * dx * dy.
+void or_totals(const OCfg* c, const double* q, double* tot) {
+  const int m = num_eqn(*c);
+  const size_t N = (size_t)c->nx * c->ny;
+  const double cell = dx_of(*c) * dy_of(*c);
+  for (int k = 0; k < m; ++k) {
+    double s = 0.0;
+    for (size_t n = 0; n < N; ++n) s += q[(size_t)k * N + n];
+    tot[k] = s * cell;
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,627 @@
+"""Pins for the FP64 oracle: exact solutions, closed forms, invariants and
+measured convergence, so that a dropped term, wrong sign or wrong index in the
+oracle fails at least one test.  CPU only."""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from exact import sw_exact, sw_middle_state
+from paper_1111_6583_amd import workloads as W
+
+
+def spec1d(riemann, n, lo, hi, **kw):
+    s = dict(ndim=1, num_cells=(n,), lower=(lo,), upper=(hi,), scheme="classic", riemann=riemann,
+             limiter="mc", transverse=0, entropy_fix=0, bc_lower=("extrap",),
+             bc_upper=("extrap",), problem_data=[1.0], cfl_desired=0.9, cfl_max=1.0)
+    s.update(kw)
+    return s
+
+
+def spec2d(riemann, n, lo=(0.0, 0.0), hi=(1.0, 1.0), **kw):
+    s = dict(ndim=2, num_cells=(n, n) if np.isscalar(n) else tuple(n), lower=lo, upper=hi,
+             scheme="classic", riemann=riemann, limiter="mc", transverse=2, entropy_fix=0,
+             bc_lower=("periodic", "periodic"), bc_upper=("periodic", "periodic"),
+             problem_data=[1.0, 1.0], cfl_desired=0.9, cfl_max=1.0)
+    s.update(kw)
+    return s
+
+
+# --------------------------------------------------------------------------
+# P1: 1D shallow-water dam break against the exact Riemann solution
+# --------------------------------------------------------------------------
+def test_dam_break_middle_state_constants():
+    hm, um = sw_middle_state(2.0, 0.0, 1.0, 0.0, g=1.0)
+    assert hm == pytest.approx(1.453840892374573, abs=1e-12)
+    assert um == pytest.approx(0.416920630975483, abs=1e-12)
+
+
+def test_dam_break_plateau_and_waves():
+    spec, q = W.dam_break_1d(1000)
+    qf, info = oracle.advance(spec, q, 2.0)
+    assert info["rc"] == 0 and info["t"] == 2.0
+    x, _ = W.centers(spec)
+    hm, um = sw_middle_state(2.0, 0.0, 1.0, 0.0)
+    h, hu = qf[0, 0], qf[1, 0]
+    # plateau: between the rarefaction tail (x=-1.5777) and the shock (x=2.6711), >= 10 cells away
+    tail, shock = 2.0 * (um - math.sqrt(hm)), 2.0 * (hm * um) / (hm - 1.0)
+    plat = (x > tail + 0.1) & (x < shock - 0.1)
+    assert np.all(np.abs(h[plat] - hm) < 1e-3)
+    assert np.all(np.abs(hu[plat] / h[plat] - um) < 1e-3)
+    # undisturbed states beyond the waves
+    assert np.all(np.abs(h[x < -2.0 * math.sqrt(2.0) - 0.2] - 2.0) < 1e-6)
+    assert np.all(np.abs(h[x > shock + 0.1] - 1.0) < 1e-12)
+
+
+def test_dam_break_l1_converges():
+    errs = []
+    ns = [250, 500, 1000, 2000]
+    for n in ns:
+        spec, q = W.dam_break_1d(n)
+        qf, _ = oracle.advance(spec, q, 2.0)
+        x, _ = W.centers(spec)
+        he, _ = sw_exact(2.0, 0.0, 1.0, 0.0, x / 2.0)
+        errs.append(np.sum(np.abs(qf[0, 0] - he)) * 10.0 / n)
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    assert errs[-1] < 2e-3
+    assert min(rates) > 0.6, (errs, rates)
+
+
+# --------------------------------------------------------------------------
+# P2: totals with boundary flux (waves stay inside [-5,5] until t=2)
+# --------------------------------------------------------------------------
+def test_dam_break_mass_and_momentum_budget():
+    spec, q = W.dam_break_1d(1000)
+    qf, _ = oracle.advance(spec, q, 2.0)
+    tot = oracle.totals(spec, qf)
+    assert tot[0] == pytest.approx(15.0, abs=1e-11)
+    # d/dt sum(hu dx) = g/2 (h_left^2 - h_right^2) = 1.5
+    assert tot[1] == pytest.approx(3.0, abs=1e-11)
+
+
+# --------------------------------------------------------------------------
+# P3: exact translation at Courant number 1
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("lim", ["none", "minmod", "mc"])
+def test_advection_cfl1_exact_1d(lim):
+    n = 64
+    s = spec1d("advection", n, 0.0, 1.0, limiter=lim, bc_lower=("periodic",),
+               bc_upper=("periodic",), problem_data=[1.0])
+    rng = np.random.default_rng(3)
+    q0 = rng.standard_normal((1, 1, n))
+    q = q0
+    for _ in range(10):
+        q, sp = oracle.step(s, q, 1.0 / n)
+        assert sp == pytest.approx(n)
+    np.testing.assert_allclose(q, np.roll(q0, 10, axis=2), rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("uv,shift", [((1.0, 1.0), (1, 1)), ((1.0, -1.0), (-1, 1)),
+                                      ((-1.0, 1.0), (1, -1)), ((-1.0, -1.0), (-1, -1))])
+@pytest.mark.parametrize("mode", [1, 2])
+def test_advection_cfl1_diagonal_2d(uv, shift, mode):
+    """Corner transport: with the transverse terms the unsplit method moves
+    data exactly one cell diagonally per step at Courant number 1 in x and y."""
+    n = 16
+    s = spec2d("advection", n, problem_data=list(uv), transverse=mode, limiter="mc")
+    rng = np.random.default_rng(4)
+    q0 = rng.standard_normal((1, n, n))
+    q = q0
+    for _ in range(5):
+        q, _ = oracle.step(s, q, 1.0 / n)
+    np.testing.assert_allclose(q, np.roll(q0, (5 * shift[0], 5 * shift[1]), axis=(1, 2)),
+                               rtol=0, atol=1e-12)
+
+
+def test_advection_without_transverse_is_not_exact():
+    n = 16
+    s = spec2d("advection", n, transverse=0, limiter="none")
+    q0 = np.random.default_rng(4).standard_normal((1, n, n))
+    q, _ = oracle.step(s, q0, 0.5 / n)   # stable at Courant 1/2 only without transverse terms
+    q1, _ = oracle.step(dict(s, transverse=1), q0, 0.5 / n)
+    assert np.max(np.abs(q - q1)) > 1e-3
+
+
+def test_elastic_p_wave_translates_at_cfl1():
+    """A right-going P wave in a homogeneous medium is carried one cell per
+    step when dt = dx / cp."""
+    n, ny = 64, 4
+    rho, lam, mu = 2.0, 3.0, 1.5
+    cp = math.sqrt((lam + 2 * mu) / rho)
+    s = spec2d("elastic_vc", (n, ny), hi=(1.0, ny / n), limiter="mc",
+               bc_lower=("periodic", "periodic"), bc_upper=("periodic", "periodic"))
+    x = (np.arange(n) + 0.5) / n
+    amp = np.exp(-((x - 0.3) / 0.05) ** 2)
+    r4 = np.array([lam + 2 * mu, lam, 0.0, -cp, 0.0])
+    q0 = np.broadcast_to((amp[None, :] * r4[:, None])[:, None, :], (5, ny, n)).copy()
+    aux = np.zeros((3, ny, n))
+    aux[0], aux[1], aux[2] = rho, lam, mu
+    q = q0
+    for _ in range(8):
+        q, sp = oracle.step(s, q, (1.0 / n) / cp, aux=aux)
+    np.testing.assert_allclose(q, np.roll(q0, 8, axis=2), rtol=0, atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# P4: conservation on periodic grids
+# --------------------------------------------------------------------------
+def test_conservation_sw_classic_periodic():
+    spec, q = W.random_smooth_sw(48, seed=1)
+    t0 = oracle.totals(spec, q)
+    qf, info = oracle.advance(spec, q, 0.2)
+    assert info["accepted"] > 10
+    np.testing.assert_allclose(oracle.totals(spec, qf), t0, rtol=0, atol=1e-12)
+
+
+def test_conservation_euler_sharpclaw_periodic():
+    spec, q = W.random_smooth_euler(32, seed=2)
+    t0 = oracle.totals(spec, q)
+    qf, info = oracle.advance(spec, q, 0.05)
+    assert info["accepted"] >= 5
+    np.testing.assert_allclose(oracle.totals(spec, qf), t0, rtol=0, atol=1e-12)
+
+
+def test_conservation_elastic_periodic():
+    n = 32
+    s = spec2d("elastic_vc", n)
+    rng = np.random.default_rng(5)
+    aux = np.stack([rng.uniform(1, 4, (n, n)), rng.uniform(1, 10, (n, n)), rng.uniform(1, 10, (n, n))])
+    q = rng.standard_normal((5, n, n))
+    t0 = oracle.totals(s, q)
+    qf, info = oracle.advance(s, q, 0.02, aux=aux)
+    assert info["accepted"] >= 3
+    # stresses are not conserved across material jumps (non-conservative form); momenta rho*u are
+    # not the state either, but with periodic BCs the fluctuation sums of the velocity rows are
+    # not telescoping.  Mass-like check only for a homogeneous medium:
+    aux_h = np.ones_like(aux)
+    aux_h[1:] = 2.0
+    qh, _ = oracle.advance(s, q, 0.02, aux=aux_h)
+    np.testing.assert_allclose(oracle.totals(s, qh), t0, rtol=0, atol=1e-11)
+
+
+# --------------------------------------------------------------------------
+# P5 / P6: measured convergence order on smooth data
+# --------------------------------------------------------------------------
+def _adv1d_error(n, scheme, lim="none", tfinal=1.0, dt_rule=None):
+    s = spec1d("advection", n, 0.0, 1.0, scheme=scheme, limiter=lim, bc_lower=("periodic",),
+               bc_upper=("periodic",), problem_data=[1.0])
+    x = (np.arange(n) + 0.5) / n
+    dx = 1.0 / n
+    # exact cell averages of sin(2 pi x)
+    avg = lambda shift: (np.cos(2 * np.pi * (x - dx / 2 - shift)) - np.cos(2 * np.pi * (x + dx / 2 - shift))) / (2 * np.pi * dx)
+    q = avg(0.0).reshape(1, 1, n)
+    dt = dt_rule(dx) if dt_rule else 0.8 * dx
+    nsteps = int(round(tfinal / dt))
+    dt = tfinal / nsteps
+    for _ in range(nsteps):
+        q, _ = oracle.step(s, q, dt)
+    return np.sum(np.abs(q[0, 0] - avg(tfinal))) * dx
+
+
+def test_classic_second_order_1d():
+    ns = [40, 80, 160, 320]
+    e = [_adv1d_error(n, "classic", "none") for n in ns]
+    rates = [math.log2(e[i] / e[i + 1]) for i in range(3)]
+    assert min(rates) > 1.9, rates
+    e = [_adv1d_error(n, "classic", "mc") for n in ns]
+    rates = [math.log2(e[i] / e[i + 1]) for i in range(3)]
+    assert rates[-1] > 1.6, rates
+
+
+def test_classic_second_order_2d_diagonal():
+    errs = []
+    for n in (16, 32, 64):
+        s = spec2d("advection", n, problem_data=[1.0, 0.5], limiter="none", transverse=2)
+        x = (np.arange(n) + 0.5) / n
+        X, Y = np.meshgrid(x, x)
+        h = 1.0 / n
+        # exact cell averages of sin(2 pi x) sin(2 pi y) translated by (ut, vt)
+        def avg(sx, sy):
+            ax = (np.cos(2 * np.pi * (X - h / 2 - sx)) - np.cos(2 * np.pi * (X + h / 2 - sx))) / (2 * np.pi * h)
+            ay = (np.cos(2 * np.pi * (Y - h / 2 - sy)) - np.cos(2 * np.pi * (Y + h / 2 - sy))) / (2 * np.pi * h)
+            return ax * ay
+        q = avg(0, 0)[None]
+        nsteps = int(round(1.0 / (0.8 / n)))
+        dt = 1.0 / nsteps
+        for _ in range(nsteps):
+            q, _ = oracle.step(s, q, dt)
+        errs.append(np.sum(np.abs(q[0] - avg(1.0, 0.5))) * h * h)
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert min(rates) > 1.85, rates
+
+
+def test_sharpclaw_fifth_order_1d():
+    ns = [20, 40, 80]
+    e = [_adv1d_error(n, "sharpclaw", tfinal=0.5, dt_rule=lambda dx: 0.5 * dx ** (5.0 / 3.0)) for n in ns]
+    rates = [math.log2(e[i] / e[i + 1]) for i in range(2)]
+    assert min(rates) > 4.7, (e, rates)
+
+
+def test_sharpclaw_linear_2d_high_order():
+    errs = []
+    for n in (16, 32):
+        s = dict(spec2d("advection", n, problem_data=[1.0, 0.5]), scheme="sharpclaw")
+        x = (np.arange(n) + 0.5) / n
+        X, Y = np.meshgrid(x, x)
+        h = 1.0 / n
+        def avg(sx, sy):
+            ax = (np.cos(2 * np.pi * (X - h / 2 - sx)) - np.cos(2 * np.pi * (X + h / 2 - sx))) / (2 * np.pi * h)
+            ay = (np.cos(2 * np.pi * (Y - h / 2 - sy)) - np.cos(2 * np.pi * (Y + h / 2 - sy))) / (2 * np.pi * h)
+            return ax * ay
+        q = avg(0, 0)[None]
+        dt0 = 0.5 * h ** (5.0 / 3.0)
+        nsteps = int(math.ceil(0.25 / dt0))
+        dt = 0.25 / nsteps
+        for _ in range(nsteps):
+            q, _ = oracle.step(s, q, dt)
+        errs.append(np.sum(np.abs(q[0] - avg(0.25, 0.125))) * h * h)
+    assert math.log2(errs[0] / errs[1]) > 4.5, errs
+
+
+# --------------------------------------------------------------------------
+# P7: WENO5 closed forms
+# --------------------------------------------------------------------------
+def test_weno5_quadratic_exact():
+    # cell averages of q(x) = a + b x + c x^2 on unit cells centred at -2..2
+    a, b, c = 0.3, -1.7, 2.2
+    prim = lambda x: a * x + b * x ** 2 / 2 + c * x ** 3 / 3
+    v = np.array([prim(k + 0.5) - prim(k - 0.5) for k in range(-2, 3)])
+    qL, qR = oracle.weno5(v, 1e-6)
+    assert qL == pytest.approx(a + b * 0.5 + c * 0.25, abs=1e-13)
+    assert qR == pytest.approx(a - b * 0.5 + c * 0.25, abs=1e-13)
+
+
+def test_weno5_equal_smoothness_gives_linear_weights():
+    # v = (4,1,0,1,4): all three smoothness indicators equal 13/3
+    v = np.array([4.0, 1.0, 0.0, 1.0, 4.0])
+    qL, qR = oracle.weno5(v, 1e-6)
+    assert qL == pytest.approx((2 * 4 - 13 * 1 + 47 * 0 + 27 * 1 - 3 * 4) / 60.0, abs=1e-14)
+    assert qR == pytest.approx((-3 * 4 + 27 * 1 + 47 * 0 - 13 * 1 + 2 * 4) / 60.0, abs=1e-14)
+
+
+def test_weno5_non_oscillatory_at_jump():
+    qL, qR = oracle.weno5(np.array([0.0, 0.0, 0.0, 1.0, 1.0]), 1e-6)
+    assert abs(qL) < 1e-6 and abs(qR) < 1e-10
+    qL, qR = oracle.weno5(np.array([0.0, 0.0, 1.0, 1.0, 1.0]), 1e-6)
+    assert abs(qL - 1.0) < 1e-10 and abs(qR - 1.0) < 1e-6
+
+
+@pytest.mark.parametrize("th,mc,mm", [(-1.0, 0, 0), (0.0, 0, 0), (0.25, 0.5, 0.25), (0.5, 0.75, 0.5),
+                                      (1.0, 1.0, 1.0), (2.0, 1.5, 1.0), (3.0, 2.0, 1.0), (10.0, 2.0, 1.0)])
+def test_limiter_values(th, mc, mm):
+    assert oracle.limiter("mc", th) == pytest.approx(mc)
+    assert oracle.limiter("minmod", th) == pytest.approx(mm)
+    assert oracle.limiter("none", th) == 1.0
+
+
+# --------------------------------------------------------------------------
+# P8: Riemann solver identities
+# --------------------------------------------------------------------------
+def sw_flux(q, d, g=1.0):
+    h = q[0]
+    u, v = q[1] / h, (q[2] / h if len(q) == 3 else 0.0)
+    un = (u, v)[d]
+    f = np.array([h * un, q[1] * un, 0.0][:len(q)])
+    if len(q) == 3:
+        f[2] = q[2] * un
+    f[1 + d] += 0.5 * g * h * h
+    return f
+
+
+@pytest.mark.parametrize("efix", [0, 1])
+@pytest.mark.parametrize("d", [0, 1])
+def test_sw_roe_identities(efix, d):
+    s = spec2d("sw_roe", 4, entropy_fix=efix, problem_data=[9.81])
+    rng = np.random.default_rng(10 + d + 2 * efix)
+    for _ in range(200):
+        ql = np.array([rng.uniform(0.5, 3.0), rng.uniform(-3, 3), rng.uniform(-3, 3)])
+        qr = np.array([rng.uniform(0.5, 3.0), rng.uniform(-3, 3), rng.uniform(-3, 3)])
+        Wv, sp, am, ap = oracle.riemann(s, d, ql, qr)
+        np.testing.assert_allclose(Wv.sum(axis=0), qr - ql, atol=1e-12)
+        np.testing.assert_allclose(am + ap, sw_flux(qr, d, 9.81) - sw_flux(ql, d, 9.81), atol=1e-11)
+        Wv, sp, am, ap = oracle.riemann(s, d, ql, ql)
+        assert np.all(Wv == 0) and np.all(am == 0) and np.all(ap == 0)
+
+
+def test_sw_roe_1d_identities():
+    s = spec1d("sw_roe", 4, 0, 1, entropy_fix=1, problem_data=[2.0])
+    rng = np.random.default_rng(7)
+    for _ in range(100):
+        ql = np.array([rng.uniform(0.5, 3.0), rng.uniform(-3, 3)])
+        qr = np.array([rng.uniform(0.5, 3.0), rng.uniform(-3, 3)])
+        Wv, sp, am, ap = oracle.riemann(s, 0, ql, qr)
+        np.testing.assert_allclose(Wv.sum(axis=0), qr - ql, atol=1e-12)
+        np.testing.assert_allclose(am + ap, sw_flux(qr, 0, 2.0) - sw_flux(ql, 0, 2.0), atol=1e-11)
+
+
+@pytest.mark.parametrize("d", [0, 1])
+def test_sw_transverse_is_roe_matrix(d):
+    """bm + bp equals the transverse flux Jacobian at the face's Roe-averaged
+    state applied to the fluctuation; bm has only non-positive speeds."""
+    g = 9.81
+    s = spec2d("sw_roe", 4, problem_data=[g])
+    rng = np.random.default_rng(20 + d)
+    for _ in range(100):
+        ql = np.array([rng.uniform(0.5, 3.0), rng.uniform(-2, 2), rng.uniform(-2, 2)])
+        qr = np.array([rng.uniform(0.5, 3.0), rng.uniform(-2, 2), rng.uniform(-2, 2)])
+        dq = rng.standard_normal(3)
+        bm, bp = oracle.transverse(s, d, ql, qr, dq)
+        sl, sr = math.sqrt(ql[0]), math.sqrt(qr[0])
+        u = (sl * ql[1] / ql[0] + sr * qr[1] / qr[0]) / (sl + sr)
+        v = (sl * ql[2] / ql[0] + sr * qr[2] / qr[0]) / (sl + sr)
+        c2 = g * 0.5 * (ql[0] + qr[0])
+        if d == 0:   # transverse direction is y: Jacobian of (hv, huv, hv^2 + g h^2/2)
+            B = np.array([[0, 0, 1], [-u * v, v, u], [c2 - v * v, 0, 2 * v]])
+        else:        # transverse direction is x: Jacobian of (hu, hu^2 + g h^2/2, huv)
+            B = np.array([[0, 1, 0], [c2 - u * u, 2 * u, 0], [-u * v, v, u]])
+        np.testing.assert_allclose(bm + bp, B @ dq, atol=1e-10)
+
+
+def elastic_matrix(d, rho, lam, mu):
+    A = np.zeros((5, 5))
+    if d == 0:
+        A[0, 3], A[1, 3], A[2, 4], A[3, 0], A[4, 2] = -(lam + 2 * mu), -lam, -mu, -1 / rho, -1 / rho
+    else:
+        A[0, 4], A[1, 4], A[2, 3], A[4, 1], A[3, 2] = -lam, -(lam + 2 * mu), -mu, -1 / rho, -1 / rho
+    return A
+
+
+@pytest.mark.parametrize("d", [0, 1])
+def test_elastic_riemann_identities(d):
+    s = spec2d("elastic_vc", 4)
+    rng = np.random.default_rng(30 + d)
+    for _ in range(100):
+        al = np.array([rng.uniform(1, 4), rng.uniform(1, 10), rng.uniform(1, 10)])
+        ar = np.array([rng.uniform(1, 4), rng.uniform(1, 10), rng.uniform(1, 10)])
+        ql, qr = rng.standard_normal(5), rng.standard_normal(5)
+        Wv, sp, am, ap = oracle.riemann(s, d, ql, qr, al, ar)
+        # waves sum to the jump except the zero-speed (other normal stress) remainder
+        so = 1 if d == 0 else 0
+        rem = (qr - ql) - Wv.sum(axis=0)
+        rem[so] = 0.0
+        np.testing.assert_allclose(rem, 0, atol=1e-12)
+        # the states between the waves carry continuous traction and velocity across the interface
+        qml = ql + Wv[0] + Wv[1]
+        qmr = qr - Wv[2] - Wv[3]
+        sn, vn, vt = (0, 3, 4) if d == 0 else (1, 4, 3)
+        for k in (sn, 2, vn, vt):
+            assert qml[k] == pytest.approx(qmr[k], abs=1e-12)
+        # each wave is an eigenvector of its own medium's matrix with its speed
+        Al, Ar = elastic_matrix(d, *al), elastic_matrix(d, *ar)
+        for p_, A_ in ((0, Al), (1, Al), (2, Ar), (3, Ar)):
+            np.testing.assert_allclose(A_ @ Wv[p_], sp[p_] * Wv[p_], atol=1e-10)
+        # speeds: -cp_l, -cs_l, cs_r, cp_r
+        cpl = math.sqrt((al[1] + 2 * al[2]) / al[0]); csr = math.sqrt(ar[2] / ar[0])
+        assert sp[0] == pytest.approx(-cpl) and sp[2] == pytest.approx(csr)
+        # homogeneous medium: the fluctuations sum to A * jump
+        Wv, sp, am, ap = oracle.riemann(s, d, ql, qr, al, al)
+        np.testing.assert_allclose(am + ap, elastic_matrix(d, *al) @ (qr - ql), atol=1e-10)
+
+
+@pytest.mark.parametrize("d", [0, 1])
+def test_elastic_transverse_homogeneous(d):
+    """In a homogeneous medium the transverse split of a fluctuation sums to
+    the other direction's matrix times it."""
+    s = spec2d("elastic_vc", 4)
+    rng = np.random.default_rng(40 + d)
+    for _ in range(50):
+        a = np.array([rng.uniform(1, 4), rng.uniform(1, 10), rng.uniform(1, 10)])
+        dq = rng.standard_normal(5)
+        bm, bp = oracle.transverse(s, d, np.zeros(5), np.zeros(5), dq, a, a, a)
+        np.testing.assert_allclose(bm + bp, elastic_matrix(1 - d, *a) @ dq, atol=1e-10)
+
+
+def euler_flux(q, d, gam=1.4):
+    rho, mu, mv, E = q
+    u, v = mu / rho, mv / rho
+    p = (gam - 1) * (E - 0.5 * rho * (u * u + v * v))
+    un = (u, v)[d]
+    f = np.array([rho * un, mu * un, mv * un, (E + p) * un])
+    f[1 + d] += p
+    return f
+
+
+def test_hlle_consistency_and_upwinding():
+    s = dict(spec2d("euler_hlle", 4, problem_data=[1.4]), scheme="sharpclaw")
+    rng = np.random.default_rng(50)
+    for _ in range(100):
+        q = np.array(W.euler_conserved(rng.uniform(0.5, 2), rng.uniform(-1, 1), rng.uniform(-1, 1), rng.uniform(0.5, 2)))
+        for d in (0, 1):
+            F, sp = oracle.num_flux(s, d, q, q)
+            np.testing.assert_allclose(F, euler_flux(q, d), atol=1e-12)
+    # supersonic to the right: HLLE picks the left flux
+    ql = np.array(W.euler_conserved(1.0, 5.0, 0.0, 1.0))
+    qr = np.array(W.euler_conserved(0.5, 4.0, 0.1, 0.8))
+    F, _ = oracle.num_flux(s, 0, ql, qr)
+    np.testing.assert_allclose(F, euler_flux(ql, 0), atol=1e-12)
+    F, _ = oracle.num_flux(s, 0, np.array(W.euler_conserved(1.0, -5.0, 0.0, 1.0)),
+                           np.array(W.euler_conserved(0.5, -4.0, 0.1, 0.8)))
+    np.testing.assert_allclose(F, euler_flux(np.array(W.euler_conserved(0.5, -4.0, 0.1, 0.8)), 0), atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Entropy fix: a transonic rarefaction converges to the exact solution
+# --------------------------------------------------------------------------
+def test_entropy_fix_transonic_rarefaction():
+    """Without the fix, Roe's solver leaves an entropy-violating jump at the
+    sonic point of a transonic rarefaction; with it the fan is smooth."""
+    hl, hr = 4.0, 0.05   # 1-rarefaction tail speed u_m - c_m > 0: transonic
+    hm, um = sw_middle_state(hl, 0.0, hr, 0.0)
+    assert um - math.sqrt(hm) > 0.0 > -math.sqrt(hl)
+    jumps = {}
+    for efix in (0, 1):
+        spec, q = W.dam_break_1d(400, hl=hl, hr=hr, limiter="minmod")
+        spec["entropy_fix"] = efix
+        qf, info = oracle.advance(spec, q, 1.0)
+        x, _ = W.centers(spec)
+        he, _ = sw_exact(hl, 0.0, hr, 0.0, x / 1.0)
+        near0 = np.abs(x) < 0.2
+        jumps[efix] = np.max(np.abs(np.diff(qf[0, 0][near0])))
+        exact_jump = np.max(np.abs(np.diff(he[near0])))
+        if efix:
+            assert np.max(np.abs(qf[0, 0][near0] - he[near0])) < 0.02
+    assert jumps[1] < 1.3 * exact_jump
+    assert jumps[0] > 2.0 * exact_jump
+
+
+# --------------------------------------------------------------------------
+# P9: the paper's printed post-shock state, and the shock speed in the oracle
+# --------------------------------------------------------------------------
+def test_paper_postshock_state(golden):
+    g = golden("shock_bubble_postshock.txt")
+    mach = W.mach_for_pressure_ratio(g["p"])
+    rho, u, p, S = W.rankine_hugoniot(mach)
+    assert round(rho, 2) == g["rho"]
+    assert round(u, 2) == g["u"]
+    assert p == pytest.approx(g["p"])
+    rho2, u2, p2, S2 = W.rankine_hugoniot(2.0)
+    assert (rho2, p2) == (pytest.approx(8.0 / 3.0), pytest.approx(4.5))
+    assert S2 == pytest.approx(2.366431913240, abs=1e-11)
+    assert u2 == pytest.approx(1.479019945775, abs=1e-11)
+
+
+def test_planar_shock_moves_at_rankine_hugoniot_speed():
+    rho1, u1, p1, S = W.rankine_hugoniot(2.0)
+    n = 400
+    s = dict(ndim=1, num_cells=(n,), lower=(0.0,), upper=(2.0,), scheme="sharpclaw",
+             riemann="euler_hlle", problem_data=[1.4], bc_lower=("dirichlet",),
+             bc_upper=("extrap",), bc_state={"x_lower": [rho1, rho1 * u1, p1 / 0.4 + 0.5 * rho1 * u1 * u1]},
+             cfl_desired=0.5, cfl_max=0.6)
+    x = (np.arange(n) + 0.5) * 2.0 / n
+    q = np.zeros((3, 1, n))
+    behind = x < 0.3
+    q[0, 0] = np.where(behind, rho1, 1.0)
+    q[1, 0] = np.where(behind, rho1 * u1, 0.0)
+    q[2, 0] = np.where(behind, p1 / 0.4 + 0.5 * rho1 * u1 * u1, 2.5)
+    t = 0.5
+    qf, info = oracle.advance(s, q, t)
+    assert info["rc"] == 0
+    # shock position from the mass excess: integral of (rho - 1) = (rho1 - 1)*x_s + inflow
+    mass = np.sum(qf[0, 0]) * 2.0 / n
+    xs = 0.3 + S * t
+    expected = rho1 * xs + 1.0 * (2.0 - xs)
+    assert mass == pytest.approx(expected, abs=1e-10)
+    # the discontinuity itself sits at S t (density midpoint crossing)
+    mid = 0.5 * (rho1 + 1.0)
+    k = np.nonzero(qf[0, 0] < mid)[0][0]
+    assert abs(x[k] - xs) < 3 * 2.0 / n
+    # post-shock plateau holds the Rankine-Hugoniot state
+    # (excluding the start-up entropy wave left at the initial shock position, now at 0.3 + u1 t)
+    # and the slow left-going acoustic start-up wave (speed u1 - c1 ~ -0.06) near the initial position
+    plat = (x > 0.1) & (x < xs - 0.1) & (np.abs(x - (0.3 + u1 * t)) > 0.15) & (np.abs(x - 0.3) > 0.12)
+    np.testing.assert_allclose(qf[0, 0][plat], rho1, rtol=1e-3)
+    np.testing.assert_allclose(qf[1, 0][plat] / qf[0, 0][plat], u1, rtol=1e-3)
+
+
+# --------------------------------------------------------------------------
+# P10: shock-bubble mass budget with inflow while waves stay inside
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("bubble_rho", [1.0, 0.1])
+def test_shock_bubble_inflow_budget(bubble_rho):
+    """Mass enters only through the left (Dirichlet post-shock) boundary at
+    rate rho1*u1*Ly while the other boundaries see still gas.  The start-up
+    disturbance of the discretised initial shock reaches the first cells in
+    exponentially small amounts, so the budget holds to ~1e-7 relative."""
+    spec, q = W.shock_bubble(64, 32, bubble_rho=bubble_rho)
+    rho1, u1, p1, S = W.rankine_hugoniot(2.0)
+    m0 = oracle.totals(spec, q)[0]
+    qf, info = oracle.advance(spec, q, 0.05)
+    m1 = oracle.totals(spec, qf)[0]
+    tol = 1e-6
+    assert m1 - m0 == pytest.approx(rho1 * u1 * 1.0 * 0.05, abs=tol)
+
+
+# --------------------------------------------------------------------------
+# P11 / P12: symmetry and dimensional reduction
+# --------------------------------------------------------------------------
+def test_radial_dam_break_d4_symmetry():
+    spec, q = W.radial_dam_break(48)
+    qf, info = oracle.advance(spec, q, 0.3)
+    h, hu, hv = qf
+    scale = np.max(np.abs(qf), axis=(1, 2))
+    np.testing.assert_allclose(h, h.T, rtol=0, atol=1e-12 * scale[0])
+    np.testing.assert_allclose(h, h[::-1, :], rtol=0, atol=1e-12 * scale[0])
+    np.testing.assert_allclose(h, h[:, ::-1], rtol=0, atol=1e-12 * scale[0])
+    np.testing.assert_allclose(hu, hv.T, rtol=0, atol=1e-12 * scale[1])
+    np.testing.assert_allclose(hu, -hu[:, ::-1], rtol=0, atol=1e-12 * scale[1])
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+def test_2d_uniform_reduces_to_1d(axis):
+    n = 80
+    spec1, q1 = W.dam_break_1d(n)
+    s2 = dict(ndim=2, num_cells=(n, 6) if axis == 0 else (6, n), lower=(-5.0, 0.0) if axis == 0 else (0.0, -5.0),
+              upper=(5.0, 1.0) if axis == 0 else (1.0, 5.0), scheme="classic", riemann="sw_roe",
+              limiter="mc", transverse=2, entropy_fix=1, problem_data=[1.0])
+    q2 = np.zeros((3,) + ((6, n) if axis == 0 else (n, 6)))
+    if axis == 0:
+        q2[0] = q1[0, 0][None, :]
+    else:
+        q2[0] = q1[0, 0][:, None]
+    dt = 0.9 * (10.0 / n) / 2.0
+    for _ in range(30):
+        q1, _ = oracle.step(spec1, q1, dt)
+        q2, _ = oracle.step(s2, q2, dt)
+    mom = 1 if axis == 0 else 2
+    for r in range(6):
+        row_h = q2[0, r, :] if axis == 0 else q2[0, :, r]
+        row_m = q2[mom, r, :] if axis == 0 else q2[mom, :, r]
+        np.testing.assert_allclose(row_h, q1[0, 0], rtol=0, atol=1e-13)
+        np.testing.assert_allclose(row_m, q1[1, 0], rtol=0, atol=1e-13)
+    np.testing.assert_array_equal(q2[3 - mom], 0.0)
+
+
+# --------------------------------------------------------------------------
+# P13: elastic reflection/transmission at one material interface
+# --------------------------------------------------------------------------
+def test_elastic_interface_coefficients():
+    n, ny = 1600, 2
+    rl = (1.0, 2.0, 1.0)
+    rr = (3.0, 6.0, 2.0)
+    Zl = rl[0] * math.sqrt((rl[1] + 2 * rl[2]) / rl[0])
+    Zr = rr[0] * math.sqrt((rr[1] + 2 * rr[2]) / rr[0])
+    s = spec2d("elastic_vc", (n, ny), hi=(2.0, 2.0 * ny / n), limiter="mc",
+               bc_lower=("extrap", "periodic"), bc_upper=("extrap", "periodic"), cfl_desired=0.9)
+    x = (np.arange(n) + 0.5) * 2.0 / n
+    aux = np.zeros((3, ny, n))
+    for k in range(3):
+        aux[k] = np.where(x < 1.0, rl[k], rr[k])[None, :]
+    cpl = math.sqrt((rl[1] + 2 * rl[2]) / rl[0])
+    amp = np.exp(-((x - 0.5) / 0.05) ** 2)
+    r4 = np.array([rl[1] + 2 * rl[2], rl[1], 0, -cpl, 0])   # right-going P wave in the left medium
+    q = np.broadcast_to((amp[None, :] * r4[:, None])[:, None, :], (5, ny, n)).copy()
+    qf, info = oracle.advance(s, q, 0.9 / cpl, aux=aux)
+    s11 = qf[0, 0]
+    dx = 2.0 / n
+    inc = np.sum(amp * r4[0]) * dx
+    refl = np.sum(s11[x < 0.95]) * dx
+    trans = np.sum(s11[x > 1.05]) * dx
+    assert refl / inc == pytest.approx((Zr - Zl) / (Zr + Zl), abs=5e-3)
+    cpr = math.sqrt((rr[1] + 2 * rr[2]) / rr[0])
+    # transmitted pulse is compressed by cp_r/cp_l in space
+    assert trans / inc == pytest.approx(2 * Zr / (Zl + Zr) * cpr / cpl, abs=5e-3)
+    # pure P waves carry s22/s11 = lambda/(lambda + 2 mu) of their own medium
+    s22 = qf[1, 0]
+    assert np.sum(s22[x > 1.05]) * dx / trans == pytest.approx(rr[1] / (rr[1] + 2 * rr[2]), rel=1e-6)
+    assert np.sum(s22[x < 0.95]) * dx / refl == pytest.approx(rl[1] / (rl[1] + 2 * rl[2]), rel=1e-6)
+
+
+# --------------------------------------------------------------------------
+# P17: controller -- rejection of an oversized first step, clipping at t_end
+# --------------------------------------------------------------------------
+def test_controller_rejects_then_accepts_and_lands_on_t_end():
+    spec, q = W.dam_break_1d(16)
+    qf, info = oracle.advance(spec, q, 0.5, dt=1.0)
+    assert info["acc"][0] == 0 and info["rejected"] >= 1
+    assert info["t"] == 0.5
+    assert info["max_courant"] <= 1.0
+    assert np.all(info["dts"][info["acc"] == 1] > 0)
+    assert info["dts"][info["acc"] == 1].sum() == pytest.approx(0.5, abs=1e-15)
+    # replaying the accepted dts step by step reproduces the controller's result bit for bit
+    qr = q
+    for dt, ok in zip(info["dts"], info["acc"]):
+        if ok:
+            qr, _ = oracle.step(spec, qr, dt)
+    np.testing.assert_array_equal(qr, qf)
