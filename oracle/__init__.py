@@ -87,6 +87,8 @@ def _load():
     lib.or_limiter.argtypes = [C.c_int, C.c_double]
     lib.or_limiter.restype = C.c_double
     lib.or_totals.argtypes = [cp, dp, dp]
+    lib.or_num_threads.argtypes = []
+    lib.or_num_threads.restype = C.c_int
     for f in ("or_num_eqn", "or_num_waves", "or_num_aux"):
         getattr(lib, f).argtypes = [cp]
         getattr(lib, f).restype = C.c_int
@@ -262,3 +264,19 @@ def totals(spec, q):
     tot = np.zeros(m)
     _load().or_totals(C.byref(c), _ptr(q), _ptr(tot))
     return tot
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle uses (all cores of the affinity mask by default)."""
+    return int(_load().or_num_threads())
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"

@@ -32,6 +32,9 @@
 #include <cstring>
 #include <limits>
 #include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 extern "C" {
 
@@ -838,6 +841,14 @@ double max_cell_speed(const OCfg& c, const double* q, const double* aux) {
 // C entry points used by the Python test harness.
 // ---------------------------------------------------------------------------
 extern "C" {
+
+int or_num_threads() {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 int or_num_eqn(const OCfg* c) { return num_eqn(*c); }
 int or_num_waves(const OCfg* c) { return num_waves(*c); }

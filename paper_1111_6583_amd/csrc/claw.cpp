@@ -1,0 +1,976 @@
+// claw.cpp -- host side of libclaw: the C ABI declared in include/claw.h.
+//
+// Validates configurations, carves the caller's workspace, launches the
+// gfx950 kernels, runs the step controller (host or device resident),
+// captures HIP graphs, manages batches and the tiling autotuner.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <map>
+#include <mutex>
+#include <new>
+#include <tuple>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/claw.h"
+#include "claw_internal.h"
+
+namespace claw {
+hipError_t launch_classic2d(int riemann, int fp32, int nblocks, hipStream_t st,
+                            const GridDesc* d_grids, const int* d_bstart, int ngrids, int mode,
+                            double dt, int src);
+hipError_t launch_classic1d(int riemann, int fp32, int nblocks, hipStream_t st,
+                            const GridDesc* d_grids, int mode, double dt, int src);
+hipError_t launch_classic1d_run(int riemann, int fp32, int m, int nx, hipStream_t st,
+                                const GridDesc* d_grids);
+size_t classic1d_run_smem(int m, int nx, int fp32);
+hipError_t launch_sharp_stage(int ndim, int riemann, int fp32, int stage, int nblocks,
+                              hipStream_t st, const GridDesc* d_grids, int mode, double dt);
+hipError_t launch_load_state(int fp32, void* q, void* c, const double* in, size_t n,
+                             hipStream_t st);
+hipError_t launch_store_state(int fp32, double* out, const void* q, const void* c, size_t n,
+                              hipStream_t st);
+hipError_t launch_convert(int fp32, void* dst, const double* src, size_t n, hipStream_t st);
+hipError_t launch_cell_speed(int ndim, int riemann, int fp32, const GridDesc* g, int src, size_t n,
+                             unsigned long long* out, hipStream_t st);
+int totals_blocks();
+hipError_t launch_totals(int fp32, const void* q, const void* c, int m, size_t n, double cell,
+                         double* part, double* out, hipStream_t st);
+hipError_t launch_ctrl_reset(Ctrl* c, hipStream_t st);
+}  // namespace claw
+
+using namespace claw;
+
+#define HIPCHK(x)                              \
+  do {                                         \
+    if ((x) != hipSuccess) return CLAW_E_DEVICE; \
+  } while (0)
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kMarchLanesClassic = kLanes - 4;   // useful columns per classic strip
+constexpr int kMarchLanesSharp = kLanes - 6;     // useful columns per SharpClaw strip
+constexpr size_t kRun1dSmemMax = 64 * 1024;      // LDS budget of the 1D whole-run kernel
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int num_eqn_of(const claw_config& c) {
+  switch (c.riemann) {
+    case CLAW_RP_ADVECTION: return 1;
+    case CLAW_RP_SW_ROE: return c.ndim == 1 ? 2 : 3;
+    case CLAW_RP_EULER_HLLE: return c.ndim == 1 ? 3 : 4;
+    case CLAW_RP_ELASTIC_VC: return 5;
+  }
+  return 0;
+}
+int num_aux_of(const claw_config& c) { return c.riemann == CLAW_RP_ELASTIC_VC ? 3 : 0; }
+
+bool valid_bc(int b) { return b >= CLAW_BC_EXTRAP && b <= CLAW_BC_DIRICHLET; }
+
+int validate(const claw_config* c) {
+  if (!c) return CLAW_E_INVAL;
+  if (c->ndim != 1 && c->ndim != 2) return CLAW_E_INVAL;
+  if (c->num_cells[0] < 4 || (c->ndim == 2 && c->num_cells[1] < 4)) return CLAW_E_INVAL;
+  if ((double)c->num_cells[0] * (c->ndim == 2 ? c->num_cells[1] : 1) > 2.0e9) return CLAW_E_INVAL;
+  for (int d = 0; d < c->ndim; ++d) {
+    if (!(c->upper[d] > c->lower[d])) return CLAW_E_INVAL;
+    if (!valid_bc(c->bc_lower[d]) || !valid_bc(c->bc_upper[d])) return CLAW_E_INVAL;
+    if ((c->bc_lower[d] == CLAW_BC_PERIODIC) != (c->bc_upper[d] == CLAW_BC_PERIODIC))
+      return CLAW_E_INVAL;
+  }
+  if (c->precision != CLAW_FP64 && c->precision != CLAW_FP32_KAHAN) return CLAW_E_INVAL;
+  if (c->scheme == CLAW_CLASSIC) {
+    if (c->riemann == CLAW_RP_EULER_HLLE) return CLAW_E_INVAL;
+    if (c->riemann == CLAW_RP_ELASTIC_VC && c->ndim != 2) return CLAW_E_INVAL;
+    if (c->riemann < 1 || c->riemann > 4) return CLAW_E_INVAL;
+    if (c->limiter < CLAW_LIM_NONE || c->limiter > CLAW_LIM_MC) return CLAW_E_INVAL;
+    if (c->transverse < 0 || c->transverse > 2) return CLAW_E_INVAL;
+  } else if (c->scheme == CLAW_SHARPCLAW) {
+    if (c->riemann != CLAW_RP_ADVECTION && c->riemann != CLAW_RP_EULER_HLLE) return CLAW_E_INVAL;
+  } else {
+    return CLAW_E_INVAL;
+  }
+  if (!(c->cfl_max > 0.0) || !(c->cfl_desired > 0.0)) return CLAW_E_INVAL;
+  return CLAW_OK;
+}
+
+// Process-wide tiling cache: (scheme, riemann, precision, nx, ny) -> seg_rows.
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int, int>, int> g_tune;
+
+int default_seg_rows(int ny) { return std::min(ny, 16); }
+
+}  // namespace
+
+struct claw_solver {
+  claw_config cfg;
+  int device = 0;
+  int m = 0, na = 0, fp32 = 0;
+  size_t ncell = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  // device pointers carved from the workspace
+  GridDesc* d_grid = nullptr;
+  Ctrl* d_ctrl = nullptr;
+  double* d_part = nullptr;
+  double* d_tot = nullptr;
+  unsigned long long* d_speed = nullptr;
+  GridDesc hg{};                 // host copy of the grid descriptor
+  Ctrl* h_ctrl = nullptr;        // pinned staging
+  bool state_set = false, aux_set = false;
+  int src = 0;                   // buffer holding Q^n (classic)
+  claw_stats clock{};
+  // graphs
+  hipGraphExec_t graph = nullptr;
+  int graph_k = 0;
+};
+
+struct claw_batch {
+  int max_grids = 0;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  GridDesc* d_grids = nullptr;
+  int* d_bstart = nullptr;
+  Ctrl* d_ctrls = nullptr;        // gathered copies of member controllers
+  std::vector<claw_t> members;
+  std::vector<int> bstart;
+  bool dirty = true;
+  int riemann = 0, fp32 = 0;
+  hipGraphExec_t graph = nullptr;
+  int graph_k = 0;
+  Ctrl* h_ctrls = nullptr;
+};
+
+namespace {
+
+size_t layout(const claw_config& c, size_t off[16]) {
+  const int m = num_eqn_of(c), na = num_aux_of(c);
+  const size_t N = (size_t)c.num_cells[0] * (c.ndim == 2 ? c.num_cells[1] : 1);
+  const size_t rb = c.precision == CLAW_FP32_KAHAN ? 4 : 8;
+  const bool fp32 = c.precision == CLAW_FP32_KAHAN;
+  const bool classic = c.scheme == CLAW_CLASSIC;
+  size_t p = 0;
+  auto take = [&](int slot, size_t bytes) {
+    off[slot] = p;
+    p += align_up(bytes);
+  };
+  for (int s = 0; s < 16; ++s) off[s] = (size_t)-1;
+  take(0, sizeof(GridDesc));
+  take(1, sizeof(Ctrl));
+  take(2, (size_t)m * totals_blocks() * sizeof(double));   // totals partials
+  take(3, 8 * sizeof(double));                             // totals out
+  take(4, sizeof(unsigned long long));                     // a-priori speed
+  take(5, m * N * rb);                                     // q[0]
+  if (classic) take(6, m * N * rb);                        // q[1]
+  if (fp32) {
+    take(7, m * N * rb);                                   // c[0]
+    if (classic) take(8, m * N * rb);                      // c[1]
+  }
+  if (!classic) {
+    take(9, m * N * rb);                                   // s1
+    take(10, m * N * rb);                                  // s2
+  }
+  if (na) take(11, na * N * rb);                           // aux
+  return p;
+}
+
+int seg_rows_for(claw_t h) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto key = std::make_tuple(h->cfg.scheme, h->cfg.riemann, h->cfg.precision, h->cfg.num_cells[0],
+                             h->cfg.ndim == 2 ? h->cfg.num_cells[1] : 1);
+  auto it = g_tune.find(key);
+  return it != g_tune.end() ? it->second : default_seg_rows(h->cfg.ndim == 2 ? h->cfg.num_cells[1] : 1);
+}
+
+void set_tiling(claw_t h, int seg_rows) {
+  GridDesc& g = h->hg;
+  const int lanes = h->cfg.scheme == CLAW_CLASSIC ? kMarchLanesClassic : kMarchLanesSharp;
+  g.strips = (g.nx + lanes - 1) / lanes;
+  if (h->cfg.ndim == 2) {
+    g.seg_rows = std::max(1, std::min(seg_rows, g.ny));
+    g.segs = (g.ny + g.seg_rows - 1) / g.seg_rows;
+  } else {
+    g.seg_rows = 1;
+    g.segs = 1;
+  }
+  g.nblocks = g.strips * g.segs;
+}
+
+int upload_grid(claw_t h) {
+  HIPCHK(hipMemcpyAsync(h->d_grid, &h->hg, sizeof(GridDesc), hipMemcpyHostToDevice, h->stream));
+  return CLAW_OK;
+}
+
+int sync(claw_t h) {
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return CLAW_OK;
+}
+
+int read_ctrl(claw_t h) {
+  HIPCHK(hipMemcpyAsync(h->h_ctrl, h->d_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return CLAW_OK;
+}
+
+// One attempt's kernels in host-dt mode (classic: one kernel; SharpClaw: the
+// first stage only when `stage1_only`).
+int launch_attempt_host(claw_t h, double dt, bool stage1_only) {
+  const GridDesc& g = h->hg;
+  if (h->cfg.scheme == CLAW_CLASSIC) {
+    if (h->cfg.ndim == 2)
+      HIPCHK(launch_classic2d(h->cfg.riemann, h->fp32, g.nblocks, h->stream, h->d_grid, nullptr, 1,
+                              kHostDt, dt, h->src));
+    else
+      HIPCHK(launch_classic1d(h->cfg.riemann, h->fp32, g.nblocks, h->stream, h->d_grid, kHostDt, dt,
+                              h->src));
+  } else {
+    HIPCHK(launch_sharp_stage(h->cfg.ndim, h->cfg.riemann, h->fp32, 1, g.nblocks, h->stream,
+                              h->d_grid, kHostDt, dt));
+    if (!stage1_only) {
+      HIPCHK(launch_sharp_stage(h->cfg.ndim, h->cfg.riemann, h->fp32, 2, g.nblocks, h->stream,
+                                h->d_grid, kHostDt, dt));
+      HIPCHK(launch_sharp_stage(h->cfg.ndim, h->cfg.riemann, h->fp32, 3, g.nblocks, h->stream,
+                                h->d_grid, kHostDt, dt));
+    }
+  }
+  return CLAW_OK;
+}
+
+int sharp_finish_host(claw_t h, double dt) {
+  HIPCHK(launch_sharp_stage(h->cfg.ndim, h->cfg.riemann, h->fp32, 2, h->hg.nblocks, h->stream,
+                            h->d_grid, kHostDt, dt));
+  HIPCHK(launch_sharp_stage(h->cfg.ndim, h->cfg.riemann, h->fp32, 3, h->hg.nblocks, h->stream,
+                            h->d_grid, kHostDt, dt));
+  return CLAW_OK;
+}
+
+// One attempt in device-controller mode (what a graph node sequence holds).
+int launch_attempt_device(claw_t h) {
+  const GridDesc& g = h->hg;
+  if (h->cfg.scheme == CLAW_CLASSIC) {
+    if (h->cfg.ndim == 2)
+      HIPCHK(launch_classic2d(h->cfg.riemann, h->fp32, g.nblocks, h->stream, h->d_grid, nullptr, 1,
+                              kDeviceCtrl, 0.0, 0));
+    else
+      HIPCHK(launch_classic1d(h->cfg.riemann, h->fp32, g.nblocks, h->stream, h->d_grid, kDeviceCtrl,
+                              0.0, 0));
+  } else {
+    for (int s = 1; s <= 3; ++s)
+      HIPCHK(launch_sharp_stage(h->cfg.ndim, h->cfg.riemann, h->fp32, s, g.nblocks, h->stream,
+                                h->d_grid, kDeviceCtrl, 0.0));
+  }
+  return CLAW_OK;
+}
+
+// A-priori first dt: cfl_desired / max cell speed.
+int apriori_dt(claw_t h, double* dt) {
+  HIPCHK(hipMemsetAsync(h->d_speed, 0, sizeof(unsigned long long), h->stream));
+  HIPCHK(launch_cell_speed(h->cfg.ndim, h->cfg.riemann, h->fp32, h->d_grid, h->src, h->ncell,
+                           h->d_speed, h->stream));
+  unsigned long long bits = 0;
+  HIPCHK(hipMemcpyAsync(&bits, h->d_speed, sizeof(bits), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  double s;
+  std::memcpy(&s, &bits, sizeof(s));
+  const double dtmax = h->cfg.dt_max > 0.0 ? h->cfg.dt_max : std::numeric_limits<double>::infinity();
+  *dt = s > 0.0 ? std::min(dtmax, h->cfg.cfl_desired / s) : dtmax;
+  if (!std::isfinite(*dt)) return CLAW_E_NONPHYSICAL;
+  return CLAW_OK;
+}
+
+int first_dt(claw_t h, double* dt) {
+  if (h->clock.dt_next > 0.0) {
+    *dt = h->clock.dt_next;
+    return CLAW_OK;
+  }
+  if (h->cfg.dt_initial > 0.0) {
+    *dt = h->cfg.dt_initial;
+    return CLAW_OK;
+  }
+  return apriori_dt(h, dt);
+}
+
+void clock_out(claw_t h, claw_stats* st) {
+  if (st) *st = h->clock;
+}
+
+void* buf(claw_t h, const size_t off[16], int slot, char* base) {
+  return off[slot] == (size_t)-1 ? nullptr : base + off[slot];
+}
+
+// Fill a controller record for a device-resident advance to t_end.
+void prepare_ctrl(claw_t h, Ctrl& c, double t_end, double dt, long long max_attempts) {
+  std::memset(&c, 0, sizeof(c));
+  c.src = h->src;
+  c.t = h->clock.t;
+  c.t_end = t_end;
+  c.dt = dt;
+  c.cfl_desired = h->cfg.cfl_desired;
+  c.cfl_max = h->cfg.cfl_max;
+  c.dt_max = h->cfg.dt_max > 0.0 ? h->cfg.dt_max : std::numeric_limits<double>::infinity();
+  c.max_attempts = max_attempts > 0 ? max_attempts : 0;
+  c.active = c.t < t_end ? 1 : 0;
+  c.clipped = c.t + dt >= t_end;
+  c.dt_try = c.clipped ? t_end - c.t : dt;
+  c.max_courant = h->clock.max_courant;
+}
+
+void absorb_ctrl(claw_t h, const Ctrl& c) {
+  h->src = c.src;
+  h->clock.t = c.t;
+  h->clock.dt_next = c.dt;
+  h->clock.accepted += c.accepted;
+  h->clock.rejected += c.rejected;
+  h->clock.max_courant = c.max_courant;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* claw_strerror(int s) {
+  switch (s) {
+    case CLAW_OK: return "ok";
+    case CLAW_E_INVAL: return "invalid argument or unsupported configuration";
+    case CLAW_E_NOMEM: return "workspace smaller than claw_workspace_bytes()";
+    case CLAW_E_DEVICE: return "HIP runtime call failed";
+    case CLAW_E_REJECTED: return "step rejected: Courant number above cfl_max";
+    case CLAW_E_NONPHYSICAL: return "non-finite Courant number (NaN or Inf in the state)";
+    case CLAW_E_BUDGET: return "no free batch slot";
+    case CLAW_E_STATE: return "call order: state not set or handle in use";
+    case CLAW_E_MAXSTEPS: return "max_steps attempts did not reach t_end";
+  }
+  return "unknown status";
+}
+
+int claw_num_eqn(const claw_config* cfg) { return validate(cfg) ? 0 : num_eqn_of(*cfg); }
+int claw_num_aux(const claw_config* cfg) { return validate(cfg) ? 0 : num_aux_of(*cfg); }
+
+size_t claw_workspace_bytes(const claw_config* cfg) {
+  if (validate(cfg) != CLAW_OK) return 0;
+  size_t off[16];
+  return layout(*cfg, off);
+}
+
+int claw_create(const claw_config* cfg, void* d_ws, size_t ws_bytes, void* hip_stream,
+                claw_t* out) {
+  if (!out) return CLAW_E_INVAL;
+  *out = nullptr;
+  int rc = validate(cfg);
+  if (rc) return rc;
+  if (!d_ws || ((uintptr_t)d_ws % kAlign) != 0) return CLAW_E_INVAL;
+  size_t off[16];
+  const size_t need = layout(*cfg, off);
+  if (ws_bytes < need) return CLAW_E_NOMEM;
+  claw_t h = new (std::nothrow) claw_solver();
+  if (!h) return CLAW_E_NOMEM;
+  h->cfg = *cfg;
+  if (h->cfg.weno_eps <= 0.0) h->cfg.weno_eps = 1e-6;
+  if (hipGetDevice(&h->device) != hipSuccess) { delete h; return CLAW_E_DEVICE; }
+  h->m = num_eqn_of(*cfg);
+  h->na = num_aux_of(*cfg);
+  h->fp32 = cfg->precision == CLAW_FP32_KAHAN;
+  h->ncell = (size_t)cfg->num_cells[0] * (cfg->ndim == 2 ? cfg->num_cells[1] : 1);
+  if (hip_stream) {
+    h->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreate(&h->stream) != hipSuccess) { delete h; return CLAW_E_DEVICE; }
+    h->own_stream = true;
+  }
+  if (hipHostMalloc((void**)&h->h_ctrl, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess) {
+    if (h->own_stream) hipStreamDestroy(h->stream);
+    delete h;
+    return CLAW_E_DEVICE;
+  }
+  char* base = (char*)d_ws;
+  h->d_grid = (GridDesc*)buf(h, off, 0, base);
+  h->d_ctrl = (Ctrl*)buf(h, off, 1, base);
+  h->d_part = (double*)buf(h, off, 2, base);
+  h->d_tot = (double*)buf(h, off, 3, base);
+  h->d_speed = (unsigned long long*)buf(h, off, 4, base);
+  GridDesc& g = h->hg;
+  std::memset(&g, 0, sizeof(g));
+  g.nx = cfg->num_cells[0];
+  g.ny = cfg->ndim == 2 ? cfg->num_cells[1] : 1;
+  g.bc[0] = cfg->bc_lower[0];
+  g.bc[1] = cfg->bc_upper[0];
+  g.bc[2] = cfg->ndim == 2 ? cfg->bc_lower[1] : CLAW_BC_EXTRAP;
+  g.bc[3] = cfg->ndim == 2 ? cfg->bc_upper[1] : CLAW_BC_EXTRAP;
+  g.limiter = cfg->limiter;
+  g.transverse = cfg->ndim == 2 ? cfg->transverse : 0;
+  g.efix = cfg->entropy_fix;
+  g.scheme = cfg->scheme;
+  g.dx = (cfg->upper[0] - cfg->lower[0]) / g.nx;
+  g.dy = cfg->ndim == 2 ? (cfg->upper[1] - cfg->lower[1]) / g.ny : 1.0;
+  g.weno_eps = h->cfg.weno_eps;
+  std::memcpy(g.bcstate, cfg->bc_state, sizeof(g.bcstate));
+  std::memcpy(g.pd, cfg->problem_data, sizeof(g.pd));
+  g.q[0] = buf(h, off, 5, base);
+  g.q[1] = buf(h, off, 6, base);
+  g.c[0] = buf(h, off, 7, base);
+  g.c[1] = buf(h, off, 8, base);
+  g.s1 = buf(h, off, 9, base);
+  g.s2 = buf(h, off, 10, base);
+  g.aux = buf(h, off, 11, base);
+  g.ctrl = h->d_ctrl;
+  set_tiling(h, seg_rows_for(h));
+  Ctrl c0;
+  std::memset(&c0, 0, sizeof(c0));
+  rc = CLAW_OK;
+  if (hipMemcpyAsync(h->d_ctrl, &c0, sizeof(Ctrl), hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+      upload_grid(h) != CLAW_OK || hipStreamSynchronize(h->stream) != hipSuccess)
+    rc = CLAW_E_DEVICE;
+  if (rc) {
+    claw_destroy(h);
+    return rc;
+  }
+  *out = h;
+  return CLAW_OK;
+}
+
+int claw_destroy(claw_t h) {
+  if (!h) return CLAW_E_INVAL;
+  hipSetDevice(h->device);
+  if (h->stream) hipStreamSynchronize(h->stream);
+  if (h->graph) hipGraphExecDestroy(h->graph);
+  if (h->h_ctrl) hipHostFree(h->h_ctrl);
+  if (h->own_stream) hipStreamDestroy(h->stream);
+  delete h;
+  return CLAW_OK;
+}
+
+int claw_set_state(claw_t h, const double* q, int on_device) {
+  if (!h || !q) return CLAW_E_INVAL;
+  HIPCHK(hipSetDevice(h->device));
+  const size_t n = (size_t)h->m * h->ncell;
+  void* dq = h->hg.q[h->src];
+  void* dc = h->hg.c[h->src];
+  if (on_device) {
+    HIPCHK(hipStreamSynchronize(0));
+    if (!h->fp32)
+      HIPCHK(hipMemcpyAsync(dq, q, n * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    else
+      HIPCHK(launch_load_state(1, dq, dc, q, n, h->stream));
+  } else if (!h->fp32) {
+    HIPCHK(hipMemcpyAsync(dq, q, n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  } else {
+    std::vector<float> tmp(n);
+    for (size_t t = 0; t < n; ++t) tmp[t] = (float)q[t];
+    HIPCHK(hipMemcpyAsync(dq, tmp.data(), n * sizeof(float), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemsetAsync(dc, 0, n * sizeof(float), h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+  }
+  HIPCHK(hipStreamSynchronize(h->stream));
+  h->state_set = true;
+  return CLAW_OK;
+}
+
+int claw_set_aux(claw_t h, const double* aux, int on_device) {
+  if (!h || !aux) return CLAW_E_INVAL;
+  if (h->na == 0) return CLAW_OK;
+  HIPCHK(hipSetDevice(h->device));
+  const size_t n = (size_t)h->na * h->ncell;
+  void* da = (void*)h->hg.aux;
+  if (on_device) {
+    HIPCHK(hipStreamSynchronize(0));
+    if (!h->fp32)
+      HIPCHK(hipMemcpyAsync(da, aux, n * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    else
+      HIPCHK(launch_convert(1, da, aux, n, h->stream));
+  } else if (!h->fp32) {
+    HIPCHK(hipMemcpyAsync(da, aux, n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  } else {
+    std::vector<float> tmp(n);
+    for (size_t t = 0; t < n; ++t) tmp[t] = (float)aux[t];
+    HIPCHK(hipMemcpyAsync(da, tmp.data(), n * sizeof(float), hipMemcpyHostToDevice, h->stream));
+  }
+  HIPCHK(hipStreamSynchronize(h->stream));
+  h->aux_set = true;
+  return CLAW_OK;
+}
+
+int claw_get_state(claw_t h, double* out, int on_device) {
+  if (!h || !out) return CLAW_E_INVAL;
+  if (!h->state_set) return CLAW_E_STATE;
+  HIPCHK(hipSetDevice(h->device));
+  const size_t n = (size_t)h->m * h->ncell;
+  const void* dq = h->hg.q[h->src];
+  const void* dc = h->hg.c[h->src];
+  if (on_device) {
+    if (!h->fp32)
+      HIPCHK(hipMemcpyAsync(out, dq, n * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    else
+      HIPCHK(launch_store_state(1, out, dq, dc, n, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+  } else if (!h->fp32) {
+    HIPCHK(hipMemcpyAsync(out, dq, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+  } else {
+    std::vector<float> tq(n), tc(n);
+    HIPCHK(hipMemcpyAsync(tq.data(), dq, n * sizeof(float), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(tc.data(), dc, n * sizeof(float), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (size_t t = 0; t < n; ++t) out[t] = (double)tq[t] - (double)tc[t];
+  }
+  return CLAW_OK;
+}
+
+int claw_step(claw_t h, double dt, double* courant_out) {
+  if (!h || !(dt > 0.0)) return CLAW_E_INVAL;
+  if (!h->state_set || (h->na && !h->aux_set)) return CLAW_E_STATE;
+  HIPCHK(hipSetDevice(h->device));
+  int rc = launch_attempt_host(h, dt, false);
+  if (rc) return rc;
+  if ((rc = read_ctrl(h))) return rc;
+  const double C = dt * h->h_ctrl->last_speed;
+  if (h->cfg.scheme == CLAW_CLASSIC) h->src ^= 1;
+  h->clock.t += dt;
+  h->clock.accepted += 1;
+  if (courant_out) *courant_out = C;
+  if (!std::isfinite(C)) return CLAW_E_NONPHYSICAL;
+  h->clock.max_courant = std::max(h->clock.max_courant, C);
+  return CLAW_OK;
+}
+
+int claw_advance(claw_t h, double t_end, long long max_steps, claw_stats* st) {
+  if (!h) return CLAW_E_INVAL;
+  if (!h->state_set || (h->na && !h->aux_set)) return CLAW_E_STATE;
+  HIPCHK(hipSetDevice(h->device));
+  double dt;
+  int rc = first_dt(h, &dt);
+  if (rc) return rc;
+  const double dt_max =
+      h->cfg.dt_max > 0.0 ? h->cfg.dt_max : std::numeric_limits<double>::infinity();
+  long long attempts = 0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, h->stream));
+  while (h->clock.t < t_end) {
+    if (max_steps > 0 && attempts >= max_steps) { rc = CLAW_E_MAXSTEPS; break; }
+    const bool clipped = h->clock.t + dt >= t_end;
+    const double dt_try = clipped ? t_end - h->clock.t : dt;
+    if ((rc = launch_attempt_host(h, dt_try, true))) break;
+    if ((rc = read_ctrl(h))) break;
+    const double C = dt_try * h->h_ctrl->last_speed;
+    ++attempts;
+    if (!std::isfinite(C)) { rc = CLAW_E_NONPHYSICAL; break; }
+    if (C <= h->cfg.cfl_max) {
+      if (h->cfg.scheme == CLAW_CLASSIC) h->src ^= 1;
+      else if ((rc = sharp_finish_host(h, dt_try))) break;
+      h->clock.t = clipped ? t_end : h->clock.t + dt_try;
+      h->clock.accepted += 1;
+      h->clock.max_courant = std::max(h->clock.max_courant, C);
+    } else {
+      h->clock.rejected += 1;
+    }
+    dt = C > 0.0 ? std::min(dt_max, dt_try * h->cfg.cfl_desired / C) : dt_max;
+  }
+  h->clock.dt_next = dt;
+  if (hipEventRecord(e1, h->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) h->clock.gpu_ms = ms;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc == CLAW_OK && (rc = sync(h))) return rc;
+  clock_out(h, st);
+  return rc;
+}
+
+int claw_advance_graph(claw_t h, double t_end, int k, long long max_steps, claw_stats* st) {
+  if (!h || k < 1) return CLAW_E_INVAL;
+  if (!h->state_set || (h->na && !h->aux_set)) return CLAW_E_STATE;
+  HIPCHK(hipSetDevice(h->device));
+  if (!(h->clock.t < t_end)) { clock_out(h, st); return CLAW_OK; }
+  double dt;
+  int rc = first_dt(h, &dt);
+  if (rc) return rc;
+  Ctrl c;
+  prepare_ctrl(h, c, t_end, dt, max_steps);
+  *h->h_ctrl = c;
+  HIPCHK(hipMemcpyAsync(h->d_ctrl, h->h_ctrl, sizeof(Ctrl), hipMemcpyHostToDevice, h->stream));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, h->stream));
+  const bool run1d = h->cfg.ndim == 1 && h->cfg.scheme == CLAW_CLASSIC &&
+                     classic1d_run_smem(h->m, h->hg.nx, h->fp32) <= kRun1dSmemMax;
+  if (run1d) {
+    HIPCHK(launch_classic1d_run(h->cfg.riemann, h->fp32, h->m, h->hg.nx, h->stream, h->d_grid));
+    if ((rc = read_ctrl(h))) return rc;
+  } else {
+    if (!h->graph || h->graph_k != k) {
+      if (h->graph) { hipGraphExecDestroy(h->graph); h->graph = nullptr; }
+      hipGraph_t g;
+      HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+      for (int s = 0; s < k; ++s) {
+        if (launch_attempt_device(h) != CLAW_OK) {
+          hipStreamEndCapture(h->stream, &g);
+          if (g) hipGraphDestroy(g);
+          return CLAW_E_DEVICE;
+        }
+      }
+      HIPCHK(hipStreamEndCapture(h->stream, &g));
+      const hipError_t e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      HIPCHK(e);
+      h->graph_k = k;
+    }
+    for (;;) {
+      // estimate the attempts still needed and launch that many graphs
+      const Ctrl& hc = *h->h_ctrl;
+      double est = hc.dt_try > 0.0 ? (hc.t_end - hc.t) / hc.dt_try : 1.0;
+      long long launches = (long long)std::ceil((est + 1.0) / k);
+      launches = std::max(1LL, std::min(launches, 4096LL));
+      for (long long l = 0; l < launches; ++l) HIPCHK(hipGraphLaunch(h->graph, h->stream));
+      if ((rc = read_ctrl(h))) return rc;
+      if (!h->h_ctrl->active) break;
+    }
+  }
+  {
+    float ms = 0.f;
+    if (hipEventRecord(e1, h->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+        hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+      h->clock.gpu_ms = ms;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+  }
+  const Ctrl& r = *h->h_ctrl;
+  absorb_ctrl(h, r);
+  clock_out(h, st);
+  if (r.status) return r.status;
+  if (r.t < t_end) return CLAW_E_MAXSTEPS;
+  return CLAW_OK;
+}
+
+int claw_totals(claw_t h, double* totals) {
+  if (!h || !totals) return CLAW_E_INVAL;
+  if (!h->state_set) return CLAW_E_STATE;
+  HIPCHK(hipSetDevice(h->device));
+  const double cell = h->hg.dx * h->hg.dy;
+  HIPCHK(launch_totals(h->fp32, h->hg.q[h->src], h->hg.c[h->src], h->m, h->ncell, cell, h->d_part,
+                       h->d_tot, h->stream));
+  HIPCHK(hipMemcpyAsync(totals, h->d_tot, h->m * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return CLAW_OK;
+}
+
+int claw_get_clock(claw_t h, claw_stats* st) {
+  if (!h || !st) return CLAW_E_INVAL;
+  *st = h->clock;
+  return CLAW_OK;
+}
+
+int claw_set_clock(claw_t h, const claw_stats* st) {
+  if (!h || !st) return CLAW_E_INVAL;
+  h->clock = *st;
+  return CLAW_OK;
+}
+
+int claw_set_tuning(claw_t h, const claw_tuning* tn) {
+  if (!h || !tn || tn->seg_rows < 1) return CLAW_E_INVAL;
+  HIPCHK(hipSetDevice(h->device));
+  set_tiling(h, tn->seg_rows);
+  int rc = upload_grid(h);
+  if (rc) return rc;
+  if (h->graph) { hipGraphExecDestroy(h->graph); h->graph = nullptr; }
+  return sync(h);
+}
+
+int claw_get_tuning(claw_t h, claw_tuning* tn) {
+  if (!h || !tn) return CLAW_E_INVAL;
+  std::memset(tn, 0, sizeof(*tn));
+  tn->seg_rows = h->hg.seg_rows;
+  return CLAW_OK;
+}
+
+int claw_autotune(claw_t h, int reps, claw_tuning* out) {
+  if (!h) return CLAW_E_INVAL;
+  if (!h->state_set || (h->na && !h->aux_set)) return CLAW_E_STATE;
+  HIPCHK(hipSetDevice(h->device));
+  if (reps < 1) reps = 3;
+  const int ny = h->hg.ny;
+  std::vector<int> cands;
+  if (h->cfg.ndim == 2) {
+    for (int c : {4, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256})
+      if (c <= ny) cands.push_back(c);
+    if (cands.empty()) cands.push_back(ny);
+  } else {
+    cands.push_back(1);
+  }
+  double dt;
+  int rc = first_dt(h, &dt);
+  if (rc) return rc;
+  dt *= 0.5;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  int best = cands[0];
+  float best_ms = std::numeric_limits<float>::infinity();
+  for (int c : cands) {
+    set_tiling(h, c);
+    if ((rc = upload_grid(h))) break;
+    // warm-up, then timed repetitions; host-dt launches write the other
+    // buffer (classic) or the stage buffers (SharpClaw stages 1-2) and leave
+    // the state untouched
+    auto run = [&]() -> int {
+      if (h->cfg.scheme == CLAW_CLASSIC) return launch_attempt_host(h, dt, true);
+      HIPCHK(launch_sharp_stage(h->cfg.ndim, h->cfg.riemann, h->fp32, 1, h->hg.nblocks, h->stream,
+                                h->d_grid, kHostDt, dt));
+      HIPCHK(launch_sharp_stage(h->cfg.ndim, h->cfg.riemann, h->fp32, 2, h->hg.nblocks, h->stream,
+                                h->d_grid, kHostDt, dt));
+      return CLAW_OK;
+    };
+    if ((rc = run())) break;
+    HIPCHK(hipEventRecord(e0, h->stream));
+    for (int r = 0; r < reps; ++r)
+      if ((rc = run())) break;
+    if (rc) break;
+    HIPCHK(hipEventRecord(e1, h->stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) { best_ms = ms; best = c; }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc) return rc;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[std::make_tuple(h->cfg.scheme, h->cfg.riemann, h->cfg.precision, h->hg.nx, ny)] = best;
+  }
+  set_tiling(h, best);
+  if ((rc = upload_grid(h))) return rc;
+  if (h->graph) { hipGraphExecDestroy(h->graph); h->graph = nullptr; }
+  if (out) {
+    std::memset(out, 0, sizeof(*out));
+    out->seg_rows = best;
+  }
+  return sync(h);
+}
+
+int claw_time_kernel(claw_t h, double dt, int reps, double* avg_ms) {
+  if (!h || !avg_ms || reps < 1 || !(dt > 0.0)) return CLAW_E_INVAL;
+  if (!h->state_set || (h->na && !h->aux_set)) return CLAW_E_STATE;
+  HIPCHK(hipSetDevice(h->device));
+  auto one = [&]() -> int {
+    if (h->cfg.scheme == CLAW_CLASSIC) return launch_attempt_host(h, dt, true);
+    HIPCHK(launch_sharp_stage(h->cfg.ndim, h->cfg.riemann, h->fp32, 1, h->hg.nblocks, h->stream,
+                              h->d_grid, kHostDt, dt));
+    HIPCHK(launch_sharp_stage(h->cfg.ndim, h->cfg.riemann, h->fp32, 2, h->hg.nblocks, h->stream,
+                              h->d_grid, kHostDt, dt));
+    return CLAW_OK;
+  };
+  int rc = one();
+  if (rc) return rc;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, h->stream));
+  for (int r = 0; r < reps && !rc; ++r) rc = one();
+  HIPCHK(hipEventRecord(e1, h->stream));
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc) return rc;
+  *avg_ms = (double)ms / reps / (h->cfg.scheme == CLAW_CLASSIC ? 1 : 2);
+  return CLAW_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batches.
+// ---------------------------------------------------------------------------
+size_t claw_batch_workspace_bytes(int max_grids) {
+  if (max_grids < 1) return 0;
+  return align_up((size_t)max_grids * sizeof(GridDesc)) +
+         align_up((size_t)(max_grids + 1) * sizeof(int)) +
+         align_up((size_t)max_grids * sizeof(Ctrl));
+}
+
+}  // extern "C"
+
+namespace {
+// Copy every member's controller into one contiguous array (one readback).
+int batch_gather(claw_batch_t b) {
+  for (size_t k = 0; k < b->members.size(); ++k)
+    HIPCHK(hipMemcpyAsync(b->d_ctrls + k, b->members[k]->d_ctrl, sizeof(Ctrl),
+                          hipMemcpyDeviceToDevice, b->stream));
+  if (!b->members.empty())
+    HIPCHK(hipMemcpyAsync(b->h_ctrls, b->d_ctrls, b->members.size() * sizeof(Ctrl),
+                          hipMemcpyDeviceToHost, b->stream));
+  HIPCHK(hipStreamSynchronize(b->stream));
+  return CLAW_OK;
+}
+
+int batch_rebuild(claw_batch_t b) {
+  std::vector<GridDesc> gd(b->members.size());
+  b->bstart.assign(b->members.size() + 1, 0);
+  for (size_t k = 0; k < b->members.size(); ++k) {
+    gd[k] = b->members[k]->hg;
+    b->bstart[k + 1] = b->bstart[k] + gd[k].nblocks;
+  }
+  if (!gd.empty()) {
+    HIPCHK(hipMemcpyAsync(b->d_grids, gd.data(), gd.size() * sizeof(GridDesc),
+                          hipMemcpyHostToDevice, b->stream));
+    HIPCHK(hipMemcpyAsync(b->d_bstart, b->bstart.data(), b->bstart.size() * sizeof(int),
+                          hipMemcpyHostToDevice, b->stream));
+  }
+  if (b->graph) { hipGraphExecDestroy(b->graph); b->graph = nullptr; }
+  b->dirty = false;
+  return CLAW_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int claw_batch_create(int max_grids, void* d_ws, size_t ws_bytes, void* hip_stream,
+                      claw_batch_t* out) {
+  if (!out || max_grids < 1 || !d_ws || ((uintptr_t)d_ws % kAlign) != 0) return CLAW_E_INVAL;
+  if (ws_bytes < claw_batch_workspace_bytes(max_grids)) return CLAW_E_NOMEM;
+  claw_batch_t b = new (std::nothrow) claw_batch();
+  if (!b) return CLAW_E_NOMEM;
+  b->max_grids = max_grids;
+  hipGetDevice(&b->device);
+  char* base = (char*)d_ws;
+  b->d_grids = (GridDesc*)base;
+  b->d_bstart = (int*)(base + align_up((size_t)max_grids * sizeof(GridDesc)));
+  b->d_ctrls = (Ctrl*)(base + align_up((size_t)max_grids * sizeof(GridDesc)) +
+                       align_up((size_t)(max_grids + 1) * sizeof(int)));
+  if (hip_stream) {
+    b->stream = (hipStream_t)hip_stream;
+  } else if (hipStreamCreate(&b->stream) == hipSuccess) {
+    b->own_stream = true;
+  } else {
+    delete b;
+    return CLAW_E_DEVICE;
+  }
+  if (hipHostMalloc((void**)&b->h_ctrls, (size_t)max_grids * sizeof(Ctrl), hipHostMallocDefault) !=
+      hipSuccess) {
+    if (b->own_stream) hipStreamDestroy(b->stream);
+    delete b;
+    return CLAW_E_DEVICE;
+  }
+  *out = b;
+  return CLAW_OK;
+}
+
+int claw_batch_destroy(claw_batch_t b) {
+  if (!b) return CLAW_E_INVAL;
+  hipSetDevice(b->device);
+  hipStreamSynchronize(b->stream);
+  if (b->graph) hipGraphExecDestroy(b->graph);
+  if (b->h_ctrls) hipHostFree(b->h_ctrls);
+  if (b->own_stream) hipStreamDestroy(b->stream);
+  delete b;
+  return CLAW_OK;
+}
+
+int claw_batch_add(claw_batch_t b, claw_t h, double t_end) {
+  if (!b || !h) return CLAW_E_INVAL;
+  if ((int)b->members.size() >= b->max_grids) return CLAW_E_BUDGET;
+  if (h->cfg.scheme != CLAW_CLASSIC || h->cfg.ndim != 2) return CLAW_E_INVAL;
+  if (h->device != b->device) return CLAW_E_INVAL;
+  if (!h->state_set || (h->na && !h->aux_set)) return CLAW_E_STATE;
+  for (claw_t o : b->members)
+    if (o == h) return CLAW_E_INVAL;
+  if (!b->members.empty() && (b->riemann != h->cfg.riemann || b->fp32 != h->fp32))
+    return CLAW_E_INVAL;
+  HIPCHK(hipSetDevice(b->device));
+  double dt;
+  int rc = first_dt(h, &dt);
+  if (rc) return rc;
+  Ctrl c;
+  prepare_ctrl(h, c, t_end, dt, 0);
+  *h->h_ctrl = c;
+  HIPCHK(hipMemcpyAsync(h->d_ctrl, h->h_ctrl, sizeof(Ctrl), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  b->riemann = h->cfg.riemann;
+  b->fp32 = h->fp32;
+  b->members.push_back(h);
+  b->dirty = true;
+  return CLAW_OK;
+}
+
+int claw_batch_remove(claw_batch_t b, claw_t h) {
+  if (!b || !h) return CLAW_E_INVAL;
+  auto it = std::find(b->members.begin(), b->members.end(), h);
+  if (it == b->members.end()) return CLAW_E_INVAL;
+  HIPCHK(hipSetDevice(b->device));
+  HIPCHK(hipStreamSynchronize(b->stream));
+  int rc = read_ctrl(h);
+  if (rc) return rc;
+  absorb_ctrl(h, *h->h_ctrl);
+  b->members.erase(it);
+  b->dirty = true;
+  return CLAW_OK;
+}
+
+int claw_batch_member_clock(claw_batch_t b, claw_t h, claw_stats* st) {
+  if (!b || !h || !st) return CLAW_E_INVAL;
+  auto it = std::find(b->members.begin(), b->members.end(), h);
+  if (it == b->members.end()) return CLAW_E_INVAL;
+  HIPCHK(hipSetDevice(b->device));
+  HIPCHK(hipStreamSynchronize(b->stream));
+  int rc = read_ctrl(h);
+  if (rc) return rc;
+  const Ctrl& c = *h->h_ctrl;
+  *st = h->clock;
+  st->t = c.t;
+  st->dt_next = c.dt;
+  st->accepted += c.accepted;
+  st->rejected += c.rejected;
+  st->max_courant = c.max_courant;
+  return c.status ? c.status : CLAW_OK;
+}
+
+int claw_batch_advance(claw_batch_t b, int attempts, int* n_active) {
+  if (!b || attempts < 0) return CLAW_E_INVAL;
+  HIPCHK(hipSetDevice(b->device));
+  if (b->members.empty()) {
+    if (n_active) *n_active = 0;
+    return CLAW_OK;
+  }
+  int rc;
+  if (b->dirty && (rc = batch_rebuild(b))) return rc;
+  const int ng = (int)b->members.size();
+  const int total = b->bstart[ng];
+  constexpr int kGraph = 16;
+  if (attempts >= kGraph && !b->graph) {
+    hipGraph_t g;
+    HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    for (int s = 0; s < kGraph; ++s)
+      launch_classic2d(b->riemann, b->fp32, total, b->stream, b->d_grids, b->d_bstart, ng,
+                       kDeviceCtrl, 0.0, 0);
+    HIPCHK(hipStreamEndCapture(b->stream, &g));
+    const hipError_t e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    HIPCHK(e);
+    b->graph_k = kGraph;
+  }
+  int done = 0;
+  while (b->graph && attempts - done >= b->graph_k) {
+    HIPCHK(hipGraphLaunch(b->graph, b->stream));
+    done += b->graph_k;
+  }
+  for (; done < attempts; ++done)
+    HIPCHK(launch_classic2d(b->riemann, b->fp32, total, b->stream, b->d_grids, b->d_bstart, ng,
+                            kDeviceCtrl, 0.0, 0));
+  if ((rc = batch_gather(b))) return rc;
+  int act = 0, status = 0;
+  for (int k = 0; k < ng; ++k) {
+    act += b->h_ctrls[k].active ? 1 : 0;
+    if (b->h_ctrls[k].status) status = b->h_ctrls[k].status;
+  }
+  if (n_active) *n_active = act;
+  return status ? status : CLAW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,55 @@
+// claw_internal.h -- structures shared by the host library and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace claw {
+
+constexpr int kLanes = 64;        // one wavefront per workgroup in the marching kernels
+constexpr int kMaxEqn = 5;
+constexpr int kMaxAux = 3;
+
+// Device-resident step controller of one grid (Section 5: after each step
+// the Courant number is checked and the next step size chosen).
+struct Ctrl {
+  unsigned long long speed_bits;  // atomic max of max|s|/spacing (bit pattern of a non-negative double)
+  unsigned int counter;           // workgroups of the current launch that have finished
+  int src;                        // buffer index holding Q^n (classic ping-pong)
+  int active;                     // 1 while t < t_end and attempts remain
+  int ok;                         // SharpClaw: the current attempt passed the stage-1 check
+  int status;                     // 0, or CLAW_E_NONPHYSICAL
+  int clipped;                    // dt_try was clipped to t_end - t
+  double t, t_end;
+  double dt;                      // the controller's running dt
+  double dt_try;                  // dt of the attempt about to run (min(dt, t_end - t))
+  double dt_stage;                // SharpClaw: dt used by stages 2 and 3 of the current attempt
+  double cfl_desired, cfl_max, dt_max;
+  long long accepted, rejected, attempts, max_attempts;
+  double max_courant;
+  double last_speed;              // speed of the most recent attempt (diagnostics / host mode)
+};
+
+// Everything a kernel needs about one grid.  Lives in device memory.
+struct GridDesc {
+  int nx, ny;
+  int strips, segs, seg_rows;
+  int nblocks;                    // workgroups of one launch over this grid
+  int bc[4];                      // x-lower, x-upper, y-lower, y-upper
+  int limiter, transverse, efix, scheme;
+  double dx, dy;
+  double weno_eps;
+  double bcstate[4][8];
+  double pd[8];
+  void* q[2];                     // state ping-pong (Real)
+  void* c[2];                     // compensation ping-pong (Real, FP32 mode)
+  void* s1;                       // SharpClaw stage buffers (Real)
+  void* s2;
+  const void* aux;                // aux fields (Real)
+  Ctrl* ctrl;
+};
+
+// How a kernel obtains dt and the source buffer.
+enum StepMode { kHostDt = 0, kDeviceCtrl = 1, kProbe = 2 };
+
+}  // namespace claw

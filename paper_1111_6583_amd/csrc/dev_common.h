@@ -1,0 +1,191 @@
+// dev_common.h -- device helpers for the gfx950 kernels: lane shuffles,
+// boundary-condition index maps, Courant reduction and the device-side step
+// controller.
+#pragma once
+
+#include "claw_internal.h"
+
+namespace claw {
+
+// ---------------------------------------------------------------------------
+// Lane shuffles inside one 64-lane wavefront.  x-neighbours of a cell live in
+// adjacent lanes of the marching kernels; prev = value held by lane-1,
+// next = value held by lane+1 (edge lanes receive an unspecified value; they
+// are halo lanes whose results are discarded).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float shfl_prev(float x) { return __shfl_up(x, 1, kLanes); }
+__device__ __forceinline__ float shfl_next(float x) { return __shfl_down(x, 1, kLanes); }
+__device__ __forceinline__ double shfl_prev(double x) { return __shfl_up(x, 1, kLanes); }
+__device__ __forceinline__ double shfl_next(double x) { return __shfl_down(x, 1, kLanes); }
+
+template <typename R>
+__device__ __forceinline__ R wave_max(R v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    R o = __shfl_xor(v, off, kLanes);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Boundary conditions as index maps (ghost cells are never stored).  A ghost
+// index outside [0, n) maps to the interior cell it copies, with a flag for a
+// wall (normal-odd components flip sign) or a Dirichlet side.  Indices beyond
+// the ghost width h are clamped first (they only occur in discarded lanes).
+// ---------------------------------------------------------------------------
+enum { kBcExtrap = 1, kBcPeriodic = 2, kBcWall = 3, kBcDirichlet = 4 };
+
+struct AxisMap {
+  int idx;    // interior index to read
+  int kind;   // 0 plain, 1 wall (flip normal-odd components), 2 Dirichlet
+  int side;   // 0 lower, 1 upper (for Dirichlet)
+};
+
+__device__ __forceinline__ AxisMap map_axis(int i, int n, int bc_lo, int bc_hi, int h) {
+  AxisMap m{i, 0, 0};
+  if (i < 0) {
+    i = i < -h ? -h : i;
+    m.side = 0;
+    switch (bc_lo) {
+      case kBcPeriodic: m.idx = i + n; break;
+      case kBcWall: m.idx = -1 - i; m.kind = 1; break;
+      case kBcDirichlet: m.idx = 0; m.kind = 2; break;
+      default: m.idx = 0; break;
+    }
+  } else if (i >= n) {
+    i = i > n - 1 + h ? n - 1 + h : i;
+    m.side = 1;
+    switch (bc_hi) {
+      case kBcPeriodic: m.idx = i - n; break;
+      case kBcWall: m.idx = 2 * n - 1 - i; m.kind = 1; break;
+      case kBcDirichlet: m.idx = n - 1; m.kind = 2; break;
+      default: m.idx = n - 1; break;
+    }
+  }
+  return m;
+}
+
+// Load one cell's state with the boundary conditions applied: the x map is
+// applied first and the y map last, so a corner ghost is the y-boundary image
+// of an x ghost.
+template <typename R, class P>
+__device__ __forceinline__ void load_state(R (&v)[P::M], const R* __restrict__ q, size_t plane,
+                                           int nx, const AxisMap& mx, const AxisMap& my,
+                                           const GridDesc& G) {
+  if (my.kind == 2) {
+#pragma unroll
+    for (int k = 0; k < P::M; ++k) v[k] = (R)G.bcstate[2 + my.side][k];
+    return;
+  }
+  if (mx.kind == 2) {
+#pragma unroll
+    for (int k = 0; k < P::M; ++k) v[k] = (R)G.bcstate[mx.side][k];
+  } else {
+    const size_t off = (size_t)my.idx * nx + mx.idx;
+#pragma unroll
+    for (int k = 0; k < P::M; ++k) v[k] = q[k * plane + off];
+  }
+  if (mx.kind == 1) {
+#pragma unroll
+    for (int k = 0; k < P::M; ++k)
+      if (P::odd(0, k)) v[k] = -v[k];
+  }
+  if (my.kind == 1) {
+#pragma unroll
+    for (int k = 0; k < P::M; ++k)
+      if (P::odd(1, k)) v[k] = -v[k];
+  }
+}
+
+// Aux fields: ghost cells copy the mapped interior cell (no sign flips; a
+// Dirichlet side copies the edge cell).
+template <typename R, class P>
+__device__ __forceinline__ void load_aux(R (&a)[P::NA > 0 ? P::NA : 1], const R* __restrict__ aux,
+                                         size_t plane, int nx, const AxisMap& mx,
+                                         const AxisMap& my) {
+  if constexpr (P::NA > 0) {
+    const size_t off = (size_t)my.idx * nx + mx.idx;
+#pragma unroll
+    for (int k = 0; k < P::NA; ++k) a[k] = aux[k * plane + off];
+  } else {
+    a[0] = R(0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Courant reduction and the device-side controller.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long dbits(double x) {
+  return (unsigned long long)__double_as_longlong(x);
+}
+__device__ __forceinline__ double bitsd(unsigned long long b) {
+  return __longlong_as_double((long long)b);
+}
+
+// Controller update after an attempt whose largest speed/spacing is `speed`.
+// Same arithmetic as the host controller.  Returns whether it was accepted.
+__device__ inline bool ctrl_decide(Ctrl* c, double speed) {
+  const double dt_try = c->dt_try;
+  const double C = dt_try * speed;
+  c->last_speed = speed;
+  if (!(C == C) || C == __builtin_inf()) {
+    c->status = -5;
+    c->active = 0;
+    return false;
+  }
+  const bool ok = C <= c->cfl_max;
+  c->attempts += 1;
+  if (ok) {
+    c->t = c->clipped ? c->t_end : c->t + dt_try;
+    c->accepted += 1;
+    c->max_courant = C > c->max_courant ? C : c->max_courant;
+  } else {
+    c->rejected += 1;
+  }
+  double dt = C > 0.0 ? dt_try * c->cfl_desired / C : c->dt_max;
+  c->dt = dt < c->dt_max ? dt : c->dt_max;
+  // the next attempt
+  if (!(c->t < c->t_end) || (c->max_attempts > 0 && c->attempts >= c->max_attempts)) {
+    c->active = 0;
+  } else {
+    c->clipped = c->t + c->dt >= c->t_end;
+    c->dt_try = c->clipped ? c->t_end - c->t : c->dt;
+  }
+  return ok;
+}
+
+// End-of-workgroup bookkeeping: fold this wave's max speed into the grid's
+// slot; the last workgroup of the launch (over this grid) reads the total,
+// hands it to `decide` (the device controller, or just recording it for the
+// host controller), and clears the slot and counter for the next launch.
+template <class Decide>
+__device__ inline void finish_workgroup(Ctrl* c, double local_max, int nblocks, Decide decide) {
+  local_max = wave_max(local_max);
+  if (threadIdx.x == 0) {
+    atomicMax(&c->speed_bits, dbits(local_max));
+    __threadfence();
+    const unsigned int done = atomicAdd(&c->counter, 1u);
+    if (done == (unsigned int)(nblocks - 1)) {
+      __threadfence();
+      const double speed = bitsd(atomicAdd(&c->speed_bits, 0ull));
+      decide(c, speed);
+      atomicExch(&c->speed_bits, 0ull);
+      atomicExch(&c->counter, 0u);
+      __threadfence();
+    }
+  }
+}
+
+// Locate this workgroup's grid in a batch: block_start[g] <= b < block_start[g+1].
+__device__ __forceinline__ int find_grid(const int* __restrict__ bstart, int ngrids, int b) {
+  if (ngrids <= 1) return 0;
+  int lo = 0, hi = ngrids - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (bstart[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+}  // namespace claw

@@ -1,0 +1,615 @@
+// k_classic.hip -- the Clawpack wave-propagation step on gfx950.
+//
+// Method (Section 2, eq. lwflux / eq. fluxdiff; Section 2.1, transverse
+// corrections of the unsplit 2D algorithm; LeVeque 1997):
+//   per interface: Riemann solve -> waves W^p, speeds s^p, fluctuations A^-dQ, A^+dQ;
+//   limited waves  W~ = phi(theta) W, theta from the upwind neighbour's wave;
+//   correction     F~ = 1/2 sum_p |s|(1 - dt/dx |s|) W~^p;
+//   2D transverse: split A^-dQ + cq, A^+dQ - cq (mode 2; A^-/+ dQ in mode 1)
+//                  with the transverse solver and add -dt/(2dx) B^-/+ (...) to
+//                  the correction fluxes of the four neighbouring faces;
+//   update         Q -= dt/dx (A^+dQ_{i-1/2} + A^-dQ_{i+1/2} + F~_{i+1/2} - F~_{i-1/2})
+//                     + the same in y.
+//
+// 2D layout of the work ("marching"): one 64-lane wavefront per workgroup
+// owns a strip of 60 columns (2 halo lanes each side) and marches up a
+// segment of rows.  x-neighbours are adjacent lanes (shuffles); everything
+// along y stays in registers from one row to the next, so each interface's
+// Riemann problem is solved once per strip, there is no LDS traffic and no
+// barrier.  Rows are read once per segment plus 4 halo rows.
+//
+// Pipeline when row r has just been loaded:
+//   (A) y-face r-1/2 : normal solve between rows r-1 and r
+//   (B) y-face r-3/2 : limit (needs faces r-5/2 and r-1/2), correction flux,
+//                      transverse split of its fluctuations into the x-faces
+//                      of cells (i, r-1) and (i, r-2)
+//   (C) x-row  r-1   : normal solves, limiting across lanes, correction flux,
+//                      transverse split into the y-faces of row r-1
+//   (D) row    r-2   : complete -> update and store
+#include "dev_common.h"
+#include "phys.h"
+
+namespace claw {
+
+template <typename R, class P, bool KAHAN>
+__global__ __launch_bounds__(kLanes) void k_classic2d(const GridDesc* __restrict__ grids,
+                                                      const int* __restrict__ bstart, int ngrids,
+                                                      int mode, double dt_host, int src_host) {
+  constexpr int M = P::M, MW = P::MW, NA = P::NA > 0 ? P::NA : 1;
+  constexpr int H = 2, U = kLanes - 2 * H;
+  using Face = typename P::Face;
+
+  const int b = blockIdx.x;
+  const int gi = find_grid(bstart, ngrids, b);
+  const GridDesc& G = grids[gi];
+  Ctrl* ctrl = G.ctrl;
+  double dt;
+  int src;
+  if (mode == kDeviceCtrl) {
+    if (!ctrl->active) return;
+    dt = ctrl->dt_try;
+    src = ctrl->src;
+  } else {
+    dt = dt_host;
+    src = src_host;
+  }
+  const int lb = ngrids > 1 ? b - bstart[gi] : b;
+  const int strip = lb % G.strips, seg = lb / G.strips;
+  const int nx = G.nx, ny = G.ny;
+  const size_t plane = (size_t)nx * ny;
+  const int lane = threadIdx.x;
+  const int i = strip * U - H + lane;
+  const bool own = lane >= H && lane < H + U && i < nx;
+  const bool own_face = lane >= H && lane <= H + U && i <= nx;
+  const int j0 = seg * G.seg_rows;
+  const int j1 = min(j0 + G.seg_rows, ny);
+  const AxisMap mx = map_axis(i, nx, G.bc[0], G.bc[1], H);
+  const R* __restrict__ q = (const R*)G.q[src];
+  R* __restrict__ qo = (R*)G.q[src ^ 1];
+  const R* __restrict__ aux = (const R*)G.aux;
+  const R dtdx = (R)(dt / G.dx), dtdy = (R)(dt / G.dy);
+  const R nux = R(0.5) * dtdx, nuy = R(0.5) * dtdy;
+  const int lim = G.limiter, trans = G.transverse;
+  const P phys(G);
+
+  R smx = R(0), smy = R(0);
+  // rolling state (see the pipeline above)
+  R q0[M], q1[M], a0[NA], a1[NA];
+  R yW0[MW][M], ys0[MW];                                  // y-face r-5/2
+  R yW1[MW][M], ys1[MW], yam1[M], yap1[M];                // y-face r-3/2
+  Face yf1{};
+  R glo[M], gtr_lo[M], gtop2[M], fxm2[M], fxp2[M], faL2[M], faR2[M];
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    q0[k] = q1[k] = yam1[k] = yap1[k] = R(0);
+    glo[k] = gtr_lo[k] = gtop2[k] = fxm2[k] = fxp2[k] = faL2[k] = faR2[k] = R(0);
+  }
+#pragma unroll
+  for (int k = 0; k < NA; ++k) a0[k] = a1[k] = R(0);
+#pragma unroll
+  for (int p = 0; p < MW; ++p) {
+    ys0[p] = ys1[p] = R(0);
+#pragma unroll
+    for (int k = 0; k < M; ++k) yW0[p][k] = yW1[p][k] = R(0);
+  }
+
+  for (int r = j0 - 2; r <= j1 + 1; ++r) {
+    const AxisMap my = map_axis(r, ny, G.bc[2], G.bc[3], H);
+    R qn[M], an[NA];
+    load_state<R, P>(qn, q, plane, nx, mx, my, G);
+    load_aux<R, P>(an, aux, plane, nx, mx, my);
+
+    // (A) y-face r-1/2
+    R yW2[MW][M], ys2[MW], yam2[M], yap2[M];
+    Face yf2{};
+    if (r >= j0 - 1) {
+      phys.template normal<1>(q1, qn, a1, an, yW2, ys2, yam2, yap2, yf2);
+    } else {
+#pragma unroll
+      for (int p = 0; p < MW; ++p) {
+        ys2[p] = R(0);
+#pragma unroll
+        for (int k = 0; k < M; ++k) yW2[p][k] = R(0);
+      }
+#pragma unroll
+      for (int k = 0; k < M; ++k) yam2[k] = yap2[k] = R(0);
+    }
+
+    // (B) y-face r-3/2: limiter, correction, transverse split into F
+    R ghi[M], glo_n[M], faL1[M], faR1[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) ghi[k] = glo_n[k] = faL1[k] = faR1[k] = R(0);
+    if (r >= j0 + 1) {
+      R cq[M];
+#pragma unroll
+      for (int k = 0; k < M; ++k) cq[k] = R(0);
+#pragma unroll
+      for (int p = 0; p < MW; ++p) {
+        R nrm = R(0), dlo = R(0), dhi = R(0);
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+          if (!P::template nz<1>(p, k)) continue;
+          nrm += yW1[p][k] * yW1[p][k];
+          dlo += yW0[p][k] * yW1[p][k];
+          dhi += yW2[p][k] * yW1[p][k];
+        }
+        const R phi = limiter_phi(lim, ys1[p] > R(0) ? dlo : dhi, nrm);
+        const R as = rabs(ys1[p]);
+        smy = rmax(smy, as);
+        const R w = as * (R(1) - dtdy * as) * phi;
+#pragma unroll
+        for (int k = 0; k < M; ++k)
+          if (P::template nz<1>(p, k)) cq[k] += w * yW1[p][k];
+      }
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        ghi[k] = yam1[k] + R(0.5) * cq[k];
+        glo_n[k] = yap1[k] - R(0.5) * cq[k];
+      }
+      if (trans) {
+        R bmq[M], bpq[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+          bmq[k] = yam1[k] + (trans == 2 ? cq[k] : R(0));
+          bpq[k] = yap1[k] - (trans == 2 ? cq[k] : R(0));
+        }
+        R alo[NA], ahi[NA];
+        // B^+ part lives in cell (i, r-1): materials of row r-1 at i-1, i, i+1
+#pragma unroll
+        for (int k = 0; k < NA; ++k) {
+          alo[k] = P::NA > 0 ? shfl_prev(a1[k]) : R(0);
+          ahi[k] = P::NA > 0 ? shfl_next(a1[k]) : R(0);
+        }
+        R lm[M], lp[M];
+        phys.template transverse<1>(yf1, alo, a1, ahi, bpq, lm, lp);
+#pragma unroll
+        for (int k = 0; k < M; ++k) { faL1[k] = -nuy * lm[k]; faR1[k] = -nuy * lp[k]; }
+        // B^- part lives in cell (i, r-2)
+#pragma unroll
+        for (int k = 0; k < NA; ++k) {
+          alo[k] = P::NA > 0 ? shfl_prev(a0[k]) : R(0);
+          ahi[k] = P::NA > 0 ? shfl_next(a0[k]) : R(0);
+        }
+        phys.template transverse<1>(yf1, alo, a0, ahi, bmq, lm, lp);
+#pragma unroll
+        for (int k = 0; k < M; ++k) { faL2[k] -= nuy * lm[k]; faR2[k] -= nuy * lp[k]; }
+      }
+    }
+
+    // (C) x-row r-1: normal solves across lanes, limiter, transverse split into G
+    R fxm1[M], fxp1[M], gtop1[M], gtr_cur[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) fxm1[k] = fxp1[k] = gtop1[k] = gtr_cur[k] = R(0);
+    if (r >= j0) {
+      R ql[M], al[NA];
+#pragma unroll
+      for (int k = 0; k < M; ++k) ql[k] = shfl_prev(q1[k]);
+#pragma unroll
+      for (int k = 0; k < NA; ++k) al[k] = P::NA > 0 ? shfl_prev(a1[k]) : R(0);
+      R xW[MW][M], xs[MW], xam[M], xap[M];
+      Face xf{};
+      phys.template normal<0>(ql, q1, al, a1, xW, xs, xam, xap, xf);
+      const bool cfl_row = (r - 1 >= j0) && (r - 1 < j1);
+      R cq[M];
+#pragma unroll
+      for (int k = 0; k < M; ++k) cq[k] = R(0);
+#pragma unroll
+      for (int p = 0; p < MW; ++p) {
+        R nrm = R(0), dl = R(0);
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+          if (!P::template nz<0>(p, k)) continue;
+          nrm += xW[p][k] * xW[p][k];
+          dl += shfl_prev(xW[p][k]) * xW[p][k];
+        }
+        const R dr = shfl_next(dl);   // the right neighbour's dot product with this face
+        const R phi = limiter_phi(lim, xs[p] > R(0) ? dl : dr, nrm);
+        const R as = rabs(xs[p]);
+        if (cfl_row && own_face) smx = rmax(smx, as);
+        const R w = as * (R(1) - dtdx * as) * phi;
+#pragma unroll
+        for (int k = 0; k < M; ++k)
+          if (P::template nz<0>(p, k)) cq[k] += w * xW[p][k];
+      }
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        fxm1[k] = xam[k] + R(0.5) * cq[k];
+        fxp1[k] = xap[k] - R(0.5) * cq[k];
+      }
+      R gbot1[M];
+#pragma unroll
+      for (int k = 0; k < M; ++k) gbot1[k] = R(0);
+      if (trans) {
+        R amq[M], apq[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+          amq[k] = xam[k] + (trans == 2 ? cq[k] : R(0));
+          apq[k] = xap[k] - (trans == 2 ? cq[k] : R(0));
+        }
+        // A^+ of face i-1/2 lives in cell (i, r-1); A^- of face i+1/2 too (from lane+1)
+        R bm[M], bp[M], bm2[M], bp2[M], amn[M];
+        phys.template transverse<0>(xf, a0, a1, an, apq, bm, bp);
+#pragma unroll
+        for (int k = 0; k < M; ++k) amn[k] = shfl_next(amq[k]);
+        const Face xfn = P::shfl_next_face(xf);
+        phys.template transverse<0>(xfn, a0, a1, an, amn, bm2, bp2);
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+          gbot1[k] = -nux * (bm[k] + bm2[k]);
+          gtop1[k] = -nux * (bp[k] + bp2[k]);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < M; ++k) gtr_cur[k] = gtop2[k] + gbot1[k];
+    }
+
+    // (D) row r-2 is complete
+    if (r >= j0 + 2) {
+      const int f = r - 2;
+      const size_t off = (size_t)f * nx + i;
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        const R ftr = shfl_prev(faR2[k]) + faL2[k];   // transverse part of F~ at x-face i-1/2
+        const R fp = fxp2[k] - ftr;                    // A^+dQ - F~ at i-1/2
+        const R fm = shfl_next(fxm2[k] + ftr);         // A^-dQ + F~ at i+1/2
+        const R gp = glo[k] - gtr_lo[k];               // B^+dQ - G~ at r-5/2
+        const R gm = ghi[k] + gtr_cur[k];              // B^-dQ + G~ at r-3/2
+        const R xs = fp + fm, ys = gp + gm;
+        if (own) {
+          if constexpr (KAHAN) {
+            const R* __restrict__ cin = (const R*)G.c[src];
+            R* __restrict__ cout = (R*)G.c[src ^ 1];
+            const R inc = -(dtdx * xs + dtdy * ys);
+            const R cc = cin[k * plane + off];
+            const R y = inc - cc;
+            const R t = q0[k] + y;
+            cout[k * plane + off] = (t - q0[k]) - y;
+            qo[k * plane + off] = t;
+          } else {
+            qo[k * plane + off] = q0[k] - dtdx * xs - dtdy * ys;
+          }
+        }
+      }
+    }
+
+    // rotate
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      q0[k] = q1[k];
+      q1[k] = qn[k];
+      yam1[k] = yam2[k];
+      yap1[k] = yap2[k];
+      glo[k] = glo_n[k];
+      gtr_lo[k] = gtr_cur[k];
+      gtop2[k] = gtop1[k];
+      fxm2[k] = fxm1[k];
+      fxp2[k] = fxp1[k];
+      faL2[k] = faL1[k];
+      faR2[k] = faR1[k];
+    }
+#pragma unroll
+    for (int k = 0; k < NA; ++k) { a0[k] = a1[k]; a1[k] = an[k]; }
+#pragma unroll
+    for (int p = 0; p < MW; ++p) {
+      ys0[p] = ys1[p];
+      ys1[p] = ys2[p];
+#pragma unroll
+      for (int k = 0; k < M; ++k) { yW0[p][k] = yW1[p][k]; yW1[p][k] = yW2[p][k]; }
+    }
+    yf1 = yf2;
+  }
+
+  const double speed = own ? fmax((double)smx / G.dx, (double)smy / G.dy)
+                           : (own_face ? (double)smx / G.dx : 0.0);
+  if (mode == kDeviceCtrl) {
+    finish_workgroup(ctrl, speed, G.nblocks, [](Ctrl* c, double sp) {
+      if (ctrl_decide(c, sp)) c->src ^= 1;
+    });
+  } else {
+    finish_workgroup(ctrl, speed, G.nblocks, [](Ctrl* c, double sp) { c->last_speed = sp; });
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 1D classic step: one wavefront per 60-cell strip (2 halo lanes each side).
+// ---------------------------------------------------------------------------
+template <typename R, class P, bool KAHAN>
+__global__ __launch_bounds__(kLanes) void k_classic1d(const GridDesc* __restrict__ grids,
+                                                      const int* __restrict__ bstart, int ngrids,
+                                                      int mode, double dt_host, int src_host) {
+  constexpr int M = P::M, MW = P::MW;
+  constexpr int H = 2, U = kLanes - 2 * H;
+  using Face = typename P::Face;
+  const GridDesc& G = grids[0];
+  Ctrl* ctrl = G.ctrl;
+  double dt;
+  int src;
+  if (mode == kDeviceCtrl) {
+    if (!ctrl->active) return;
+    dt = ctrl->dt_try;
+    src = ctrl->src;
+  } else {
+    dt = dt_host;
+    src = src_host;
+  }
+  const int nx = G.nx;
+  const int lane = threadIdx.x;
+  const int i = blockIdx.x * U - H + lane;
+  const bool own = lane >= H && lane < H + U && i < nx;
+  const bool own_face = lane >= H && lane <= H + U && i <= nx;
+  const AxisMap mx = map_axis(i, nx, G.bc[0], G.bc[1], H);
+  const AxisMap my{0, 0, 0};
+  const R* __restrict__ q = (const R*)G.q[src];
+  R* __restrict__ qo = (R*)G.q[src ^ 1];
+  const R dtdx = (R)(dt / G.dx);
+  const P phys(G);
+  R qc[M], ql[M];
+  R dummy[1] = {R(0)};
+  load_state<R, P>(qc, q, (size_t)nx, nx, mx, my, G);
+#pragma unroll
+  for (int k = 0; k < M; ++k) ql[k] = shfl_prev(qc[k]);
+  R W[MW][M], s[MW], am[M], ap[M];
+  Face f{};
+  phys.template normal<0>(ql, qc, dummy, dummy, W, s, am, ap, f);
+  R cq[M];
+#pragma unroll
+  for (int k = 0; k < M; ++k) cq[k] = R(0);
+  R smx = R(0);
+#pragma unroll
+  for (int p = 0; p < MW; ++p) {
+    R nrm = R(0), dl = R(0);
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      nrm += W[p][k] * W[p][k];
+      dl += shfl_prev(W[p][k]) * W[p][k];
+    }
+    const R dr = shfl_next(dl);
+    const R phi = limiter_phi(G.limiter, s[p] > R(0) ? dl : dr, nrm);
+    const R as = rabs(s[p]);
+    smx = rmax(smx, as);
+    const R w = as * (R(1) - dtdx * as) * phi;
+#pragma unroll
+    for (int k = 0; k < M; ++k) cq[k] += w * W[p][k];
+  }
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const R fp = ap[k] - R(0.5) * cq[k];
+    const R fm = shfl_next(am[k] + R(0.5) * cq[k]);
+    if (own) {
+      if constexpr (KAHAN) {
+        const R* __restrict__ cin = (const R*)G.c[src];
+        R* __restrict__ cout = (R*)G.c[src ^ 1];
+        const R inc = -(dtdx * (fp + fm));
+        const R y = inc - cin[(size_t)k * nx + i];
+        const R t = qc[k] + y;
+        cout[(size_t)k * nx + i] = (t - qc[k]) - y;
+        qo[(size_t)k * nx + i] = t;
+      } else {
+        qo[(size_t)k * nx + i] = qc[k] - dtdx * (fp + fm);
+      }
+    }
+  }
+  const double speed = own_face ? (double)smx / G.dx : 0.0;
+  if (mode == kDeviceCtrl) {
+    finish_workgroup(ctrl, speed, G.nblocks, [](Ctrl* c, double sp) {
+      if (ctrl_decide(c, sp)) c->src ^= 1;
+    });
+  } else {
+    finish_workgroup(ctrl, speed, G.nblocks, [](Ctrl* c, double sp) { c->last_speed = sp; });
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 1D whole-run kernel for small grids: one workgroup keeps the grid in LDS
+// and runs the step controller itself, so a complete advance to t_end is one
+// launch.  Per attempt: every face solves its Riemann problem and those of
+// its two neighbours (for the limiter), writes A^-dQ + F~ and A^+dQ - F~ to
+// LDS; the workgroup reduces the speed, decides, and applies the update.
+// ---------------------------------------------------------------------------
+constexpr int kPersistThreads = 1024;
+
+template <typename R, class P, bool KAHAN>
+__global__ __launch_bounds__(kPersistThreads) void k_classic1d_run(const GridDesc* __restrict__ grids) {
+  constexpr int M = P::M, MW = P::MW;
+  using Face = typename P::Face;
+  extern __shared__ unsigned char smem_raw[];
+  const GridDesc& G = grids[0];
+  Ctrl* ctrl = G.ctrl;
+  const int nx = G.nx;
+  R* sq = (R*)smem_raw;               // q[M][nx]
+  R* sc = sq + (size_t)M * nx;        // compensation [M][nx] (FP32 mode)
+  R* sfm = sc + (KAHAN ? (size_t)M * nx : 0);   // [M][nx+1]
+  R* sfp = sfm + (size_t)M * (nx + 1);          // [M][nx+1]
+  __shared__ double red[kPersistThreads / kLanes];
+  __shared__ int s_go, s_ok;
+  __shared__ double s_dt;
+  const int tid = threadIdx.x;
+  const R* __restrict__ q = (const R*)G.q[ctrl->src];
+  for (int n = tid; n < M * nx; n += blockDim.x) sq[n] = q[n];
+  if constexpr (KAHAN) {
+    const R* __restrict__ c = (const R*)G.c[ctrl->src];
+    for (int n = tid; n < M * nx; n += blockDim.x) sc[n] = c[n];
+  }
+  if (tid == 0) {
+    s_go = ctrl->active;
+    s_dt = ctrl->dt_try;
+  }
+  __syncthreads();
+  const P phys(G);
+  const AxisMap my{0, 0, 0};
+  R dummy[1] = {R(0)};
+  auto cell = [&](int i, R (&v)[M]) {
+    const AxisMap mx = map_axis(i, nx, G.bc[0], G.bc[1], 2);
+    if (mx.kind == 2) {
+#pragma unroll
+      for (int k = 0; k < M; ++k) v[k] = (R)G.bcstate[mx.side][k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < M; ++k) v[k] = sq[k * nx + mx.idx];
+      if (mx.kind == 1) {
+#pragma unroll
+        for (int k = 0; k < M; ++k)
+          if (P::odd(0, k)) v[k] = -v[k];
+      }
+    }
+  };
+  while (s_go) {
+    const double dt = s_dt;
+    const R dtdx = (R)(dt / G.dx);
+    R smx = R(0);
+    for (int f = tid; f <= nx; f += blockDim.x) {
+      // faces f-1, f, f+1 (face f lies between cells f-1 and f)
+      R c0[M], c1[M], c2[M], c3[M];
+      cell(f - 2, c0); cell(f - 1, c1); cell(f, c2); cell(f + 1, c3);
+      R Wl[MW][M], sl[MW], aml[M], apl[M], W[MW][M], s[MW], am[M], ap[M], Wr[MW][M], sr[MW],
+          amr[M], apr[M];
+      Face fa{};
+      phys.template normal<0>(c0, c1, dummy, dummy, Wl, sl, aml, apl, fa);
+      phys.template normal<0>(c1, c2, dummy, dummy, W, s, am, ap, fa);
+      phys.template normal<0>(c2, c3, dummy, dummy, Wr, sr, amr, apr, fa);
+      R cq[M];
+#pragma unroll
+      for (int k = 0; k < M; ++k) cq[k] = R(0);
+#pragma unroll
+      for (int p = 0; p < MW; ++p) {
+        R nrm = R(0), dl = R(0), dr = R(0);
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+          nrm += W[p][k] * W[p][k];
+          dl += Wl[p][k] * W[p][k];
+          dr += Wr[p][k] * W[p][k];
+        }
+        const R phi = limiter_phi(G.limiter, s[p] > R(0) ? dl : dr, nrm);
+        const R as = rabs(s[p]);
+        smx = rmax(smx, as);
+        const R w = as * (R(1) - dtdx * as) * phi;
+#pragma unroll
+        for (int k = 0; k < M; ++k) cq[k] += w * W[p][k];
+      }
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        sfm[k * (nx + 1) + f] = am[k] + R(0.5) * cq[k];
+        sfp[k * (nx + 1) + f] = ap[k] - R(0.5) * cq[k];
+      }
+    }
+    double sp = wave_max((double)smx / G.dx);
+    if ((tid & (kLanes - 1)) == 0) red[tid / kLanes] = sp;
+    __syncthreads();
+    if (tid == 0) {
+      double m = 0.0;
+      for (int w = 0; w < (int)(blockDim.x / kLanes); ++w) m = fmax(m, red[w]);
+      s_ok = ctrl_decide(ctrl, m) ? 1 : 0;
+      s_go = ctrl->active;
+      s_dt = ctrl->dt_try;
+    }
+    __syncthreads();
+    if (s_ok) {
+      for (int n = tid; n < M * nx; n += blockDim.x) {
+        const int k = n / nx, i = n - k * nx;
+        const R inc = -(dtdx * (sfp[k * (nx + 1) + i] + sfm[k * (nx + 1) + i + 1]));
+        if constexpr (KAHAN) {
+          const R y = inc - sc[n];
+          const R t = sq[n] + y;
+          sc[n] = (t - sq[n]) - y;
+          sq[n] = t;
+        } else {
+          sq[n] = sq[n] + inc;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  R* __restrict__ qo = (R*)G.q[ctrl->src];
+  for (int n = tid; n < M * nx; n += blockDim.x) qo[n] = sq[n];
+  if constexpr (KAHAN) {
+    R* __restrict__ co = (R*)G.c[ctrl->src];
+    for (int n = tid; n < M * nx; n += blockDim.x) co[n] = sc[n];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (dispatch on solver and precision).
+// ---------------------------------------------------------------------------
+template <typename R, bool K>
+static hipError_t launch2d_t(int riemann, dim3 grid, hipStream_t st, const GridDesc* g,
+                             const int* bs, int ng, int mode, double dt, int src) {
+  switch (riemann) {
+    case 1:
+      hipLaunchKernelGGL((k_classic2d<R, Advection<R, 2>, K>), grid, dim3(kLanes), 0, st, g, bs,
+                         ng, mode, dt, src);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_classic2d<R, ShallowWater<R, 2>, K>), grid, dim3(kLanes), 0, st, g,
+                         bs, ng, mode, dt, src);
+      break;
+    case 4:
+      hipLaunchKernelGGL((k_classic2d<R, Elastic<R>, K>), grid, dim3(kLanes), 0, st, g, bs, ng,
+                         mode, dt, src);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_classic2d(int riemann, int fp32, int nblocks, hipStream_t st,
+                            const GridDesc* d_grids, const int* d_bstart, int ngrids, int mode,
+                            double dt, int src) {
+  const dim3 grid(nblocks);
+  return fp32 ? launch2d_t<float, true>(riemann, grid, st, d_grids, d_bstart, ngrids, mode, dt, src)
+              : launch2d_t<double, false>(riemann, grid, st, d_grids, d_bstart, ngrids, mode, dt,
+                                          src);
+}
+
+template <typename R, bool K>
+static hipError_t launch1d_t(int riemann, dim3 grid, hipStream_t st, const GridDesc* g, int mode,
+                             double dt, int src) {
+  switch (riemann) {
+    case 1:
+      hipLaunchKernelGGL((k_classic1d<R, Advection<R, 1>, K>), grid, dim3(kLanes), 0, st, g,
+                         nullptr, 1, mode, dt, src);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_classic1d<R, ShallowWater<R, 1>, K>), grid, dim3(kLanes), 0, st, g,
+                         nullptr, 1, mode, dt, src);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_classic1d(int riemann, int fp32, int nblocks, hipStream_t st,
+                            const GridDesc* d_grids, int mode, double dt, int src) {
+  const dim3 grid(nblocks);
+  return fp32 ? launch1d_t<float, true>(riemann, grid, st, d_grids, mode, dt, src)
+              : launch1d_t<double, false>(riemann, grid, st, d_grids, mode, dt, src);
+}
+
+size_t classic1d_run_smem(int m, int nx, int fp32) {
+  const size_t rb = fp32 ? 4 : 8;
+  return rb * ((size_t)m * nx * (fp32 ? 2 : 1) + 2 * (size_t)m * (nx + 1));
+}
+
+template <typename R, bool K>
+static hipError_t launch1d_run_t(int riemann, size_t smem, hipStream_t st, const GridDesc* g) {
+  switch (riemann) {
+    case 1:
+      hipLaunchKernelGGL((k_classic1d_run<R, Advection<R, 1>, K>), dim3(1), dim3(kPersistThreads),
+                         smem, st, g);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_classic1d_run<R, ShallowWater<R, 1>, K>), dim3(1),
+                         dim3(kPersistThreads), smem, st, g);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_classic1d_run(int riemann, int fp32, int m, int nx, hipStream_t st,
+                                const GridDesc* d_grids) {
+  const size_t smem = classic1d_run_smem(m, nx, fp32);
+  return fp32 ? launch1d_run_t<float, true>(riemann, smem, st, d_grids)
+              : launch1d_run_t<double, false>(riemann, smem, st, d_grids);
+}
+
+}  // namespace claw

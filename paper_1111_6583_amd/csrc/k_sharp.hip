@@ -1,0 +1,275 @@
+// k_sharp.hip -- the SharpClaw step on gfx950: WENO5 edge values, interface
+// flux, flux differencing, SSPRK(3,3) stage combination (Section 2: method of
+// lines with WENO reconstruction; Section 2.1: SSP Runge-Kutta in time,
+// normal Riemann problems only in multi-D).
+//
+// One launch per Runge-Kutta stage.  With L(S) = -(F_{i+1/2}-F_{i-1/2})/dx
+// - (G_{j+1/2}-G_{j-1/2})/dy evaluated on the stage input S:
+//   stage 1: S1 = Q + dt L(Q)                      (speeds for the Courant number)
+//   stage 2: S2 = 3/4 Q + 1/4 (S1 + dt L(S1))
+//   stage 3: Q  = 1/3 Q + 2/3 (S2 + dt L(S2))      (in place; FP32 mode adds the
+//            increment 2/3 ((S2 - Q) + dt L(S2)) to Q with Kahan compensation)
+//
+// 2D layout: one wavefront per strip of 58 columns (3 halo lanes each side)
+// marching up a segment of rows; the y-stencil lives in a five-row register
+// window and each y-face flux is computed once and carried to the next row.
+#include "dev_common.h"
+#include "phys.h"
+
+namespace claw {
+
+template <typename R, class P, int STAGE, bool KAHAN>
+__device__ __forceinline__ void combine_store(const GridDesc& G, size_t idx, size_t plane,
+                                              const R (&S)[P::M], const R (&L)[P::M], R dt) {
+  constexpr int M = P::M;
+  if constexpr (STAGE == 1) {
+    R* __restrict__ o = (R*)G.s1;
+#pragma unroll
+    for (int k = 0; k < M; ++k) o[k * plane + idx] = S[k] + dt * L[k];
+  } else if constexpr (STAGE == 2) {
+    const R* __restrict__ Q = (const R*)G.q[0];
+    R* __restrict__ o = (R*)G.s2;
+#pragma unroll
+    for (int k = 0; k < M; ++k)
+      o[k * plane + idx] = R(0.75) * Q[k * plane + idx] + R(0.25) * (S[k] + dt * L[k]);
+  } else {
+    R* __restrict__ Q = (R*)G.q[0];
+    if constexpr (KAHAN) {
+      R* __restrict__ C = (R*)G.c[0];
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        const R qn = Q[k * plane + idx];
+        const R inc = R(2.0 / 3.0) * ((S[k] - qn) + dt * L[k]);
+        const R y = inc - C[k * plane + idx];
+        const R t = qn + y;
+        C[k * plane + idx] = (t - qn) - y;
+        Q[k * plane + idx] = t;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        const R qn = Q[k * plane + idx];
+        Q[k * plane + idx] = qn / R(3) + R(2.0 / 3.0) * (S[k] + dt * L[k]);
+      }
+    }
+  }
+}
+
+// Common prologue: dt of this stage, or an early exit.
+template <int STAGE>
+__device__ __forceinline__ bool stage_dt(Ctrl* ctrl, int mode, double dt_host, double& dt) {
+  if (mode == kDeviceCtrl) {
+    if (STAGE == 1) {
+      if (!ctrl->active) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->ok = 0;
+        return false;
+      }
+      dt = ctrl->dt_try;
+    } else {
+      if (!ctrl->ok) return false;
+      dt = ctrl->dt_stage;
+    }
+  } else {
+    dt = dt_host;
+  }
+  return true;
+}
+
+template <int STAGE>
+__device__ __forceinline__ void stage_finish(Ctrl* ctrl, int mode, double speed, int nblocks) {
+  if constexpr (STAGE == 1) {
+    if (mode == kDeviceCtrl) {
+      finish_workgroup(ctrl, speed, nblocks, [](Ctrl* c, double sp) {
+        const double d = c->dt_try;
+        c->ok = ctrl_decide(c, sp) ? 1 : 0;
+        c->dt_stage = d;
+      });
+    } else {
+      finish_workgroup(ctrl, speed, nblocks, [](Ctrl* c, double sp) { c->last_speed = sp; });
+    }
+  }
+}
+
+template <typename R, class P, int STAGE, bool KAHAN>
+__global__ __launch_bounds__(kLanes) void k_sharp2d(const GridDesc* __restrict__ grids, int mode,
+                                                    double dt_host) {
+  constexpr int M = P::M;
+  constexpr int H = 3, U = kLanes - 2 * H;
+  const GridDesc& G = grids[0];
+  Ctrl* ctrl = G.ctrl;
+  double dtd;
+  if (!stage_dt<STAGE>(ctrl, mode, dt_host, dtd)) return;
+  const R dt = (R)dtd;
+  const int strip = blockIdx.x % G.strips, seg = blockIdx.x / G.strips;
+  const int nx = G.nx, ny = G.ny;
+  const size_t plane = (size_t)nx * ny;
+  const int lane = threadIdx.x;
+  const int i = strip * U - H + lane;
+  const bool own = lane >= H && lane < H + U && i < nx;
+  const bool own_face = lane >= H && lane <= H + U && i <= nx;
+  const int j0 = seg * G.seg_rows;
+  const int j1 = min(j0 + G.seg_rows, ny);
+  const AxisMap mx = map_axis(i, nx, G.bc[0], G.bc[1], H);
+  const R* __restrict__ S = (const R*)(STAGE == 1 ? G.q[0] : (STAGE == 2 ? G.s1 : G.s2));
+  const R eps = (R)G.weno_eps;
+  const R rdx = (R)(1.0 / G.dx), rdy = (R)(1.0 / G.dy);
+  const P phys(G);
+  R smx = R(0), smy = R(0);
+
+  R w[5][M];          // rows k-4 .. k
+  R qyl_prev[M], g_lo[M];
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    qyl_prev[k] = g_lo[k] = R(0);
+#pragma unroll
+    for (int s = 0; s < 5; ++s) w[s][k] = R(0);
+  }
+  for (int r = j0 - 3; r <= j1 + 2; ++r) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int k = 0; k < M; ++k) w[s][k] = w[s + 1][k];
+    const AxisMap my = map_axis(r, ny, G.bc[2], G.bc[3], H);
+    load_state<R, P>(w[4], S, plane, nx, mx, my, G);
+    if (r < j0 + 1) continue;
+    // y edge values of row c = r-2
+    R qyl[M], qyr[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k)
+      weno5_edges(w[0][k], w[1][k], w[2][k], w[3][k], w[4][k], eps, qyl[k], qyr[k]);
+    if (r >= j0 + 2) {
+      // y-face flux at c-1/2
+      R g_up[M];
+      const R sy = phys.template flux<1>(qyl_prev, qyr, g_up);
+      smy = rmax(smy, sy);
+      if (r >= j0 + 3) {
+        // row f = r-3 (window row 1) is complete: x edge values, x-face fluxes
+        R xl[M], xr[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+          const R c0 = w[1][k];
+          const R m1 = shfl_prev(c0), p1 = shfl_next(c0);
+          const R m2 = shfl_prev(m1), p2 = shfl_next(p1);
+          weno5_edges(m2, m1, c0, p1, p2, eps, xl[k], xr[k]);
+        }
+        R ql[M], F[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) ql[k] = shfl_prev(xl[k]);
+        const R sx = phys.template flux<0>(ql, xr, F);
+        if (own_face) smx = rmax(smx, sx);
+        R Lv[M], Sc[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+          const R Fr = shfl_next(F[k]);
+          Lv[k] = -(Fr - F[k]) * rdx - (g_up[k] - g_lo[k]) * rdy;
+          Sc[k] = w[1][k];
+        }
+        if (own) combine_store<R, P, STAGE, KAHAN>(G, (size_t)(r - 3) * nx + i, plane, Sc, Lv, dt);
+      }
+#pragma unroll
+      for (int k = 0; k < M; ++k) g_lo[k] = g_up[k];
+    }
+#pragma unroll
+    for (int k = 0; k < M; ++k) qyl_prev[k] = qyl[k];
+  }
+  const double speed = own ? fmax((double)smx * (1.0 / G.dx), (double)smy * (1.0 / G.dy))
+                           : (own_face ? (double)smx * (1.0 / G.dx) : 0.0);
+  stage_finish<STAGE>(ctrl, mode, speed, G.nblocks);
+}
+
+template <typename R, class P, int STAGE, bool KAHAN>
+__global__ __launch_bounds__(kLanes) void k_sharp1d(const GridDesc* __restrict__ grids, int mode,
+                                                    double dt_host) {
+  constexpr int M = P::M;
+  constexpr int H = 3, U = kLanes - 2 * H;
+  const GridDesc& G = grids[0];
+  Ctrl* ctrl = G.ctrl;
+  double dtd;
+  if (!stage_dt<STAGE>(ctrl, mode, dt_host, dtd)) return;
+  const R dt = (R)dtd;
+  const int nx = G.nx;
+  const int lane = threadIdx.x;
+  const int i = blockIdx.x * U - H + lane;
+  const bool own = lane >= H && lane < H + U && i < nx;
+  const bool own_face = lane >= H && lane <= H + U && i <= nx;
+  const AxisMap mx = map_axis(i, nx, G.bc[0], G.bc[1], H);
+  const AxisMap my{0, 0, 0};
+  const R* __restrict__ S = (const R*)(STAGE == 1 ? G.q[0] : (STAGE == 2 ? G.s1 : G.s2));
+  const R eps = (R)G.weno_eps;
+  const R rdx = (R)(1.0 / G.dx);
+  const P phys(G);
+  R c[M], xl[M], xr[M];
+  load_state<R, P>(c, S, (size_t)nx, nx, mx, my, G);
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const R m1 = shfl_prev(c[k]), p1 = shfl_next(c[k]);
+    const R m2 = shfl_prev(m1), p2 = shfl_next(p1);
+    weno5_edges(m2, m1, c[k], p1, p2, eps, xl[k], xr[k]);
+  }
+  R ql[M], F[M], Lv[M];
+#pragma unroll
+  for (int k = 0; k < M; ++k) ql[k] = shfl_prev(xl[k]);
+  const R sx = phys.template flux<0>(ql, xr, F);
+#pragma unroll
+  for (int k = 0; k < M; ++k) Lv[k] = -(shfl_next(F[k]) - F[k]) * rdx;
+  if (own) combine_store<R, P, STAGE, KAHAN>(G, (size_t)i, (size_t)nx, c, Lv, dt);
+  const double speed = own_face ? (double)sx * (1.0 / G.dx) : 0.0;
+  stage_finish<STAGE>(ctrl, mode, speed, G.nblocks);
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+template <typename R, bool K, int NDIM, int STAGE>
+static hipError_t sharp_t(int riemann, dim3 grid, hipStream_t st, const GridDesc* g, int mode,
+                          double dt) {
+  if (NDIM == 2) {
+    switch (riemann) {
+      case 1:
+        hipLaunchKernelGGL((k_sharp2d<R, AdvectionFlux<R, 2>, STAGE, K>), grid, dim3(kLanes), 0,
+                           st, g, mode, dt);
+        break;
+      case 3:
+        hipLaunchKernelGGL((k_sharp2d<R, EulerHLLE<R, 2>, STAGE, K>), grid, dim3(kLanes), 0, st,
+                           g, mode, dt);
+        break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (riemann) {
+      case 1:
+        hipLaunchKernelGGL((k_sharp1d<R, AdvectionFlux<R, 1>, STAGE, K>), grid, dim3(kLanes), 0,
+                           st, g, mode, dt);
+        break;
+      case 3:
+        hipLaunchKernelGGL((k_sharp1d<R, EulerHLLE<R, 1>, STAGE, K>), grid, dim3(kLanes), 0, st,
+                           g, mode, dt);
+        break;
+      default: return hipErrorInvalidValue;
+    }
+  }
+  return hipGetLastError();
+}
+
+template <typename R, bool K, int NDIM>
+static hipError_t sharp_nd(int riemann, int stage, dim3 grid, hipStream_t st, const GridDesc* g,
+                           int mode, double dt) {
+  switch (stage) {
+    case 1: return sharp_t<R, K, NDIM, 1>(riemann, grid, st, g, mode, dt);
+    case 2: return sharp_t<R, K, NDIM, 2>(riemann, grid, st, g, mode, dt);
+    case 3: return sharp_t<R, K, NDIM, 3>(riemann, grid, st, g, mode, dt);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_sharp_stage(int ndim, int riemann, int fp32, int stage, int nblocks,
+                              hipStream_t st, const GridDesc* d_grids, int mode, double dt) {
+  const dim3 grid(nblocks);
+  if (ndim == 2)
+    return fp32 ? sharp_nd<float, true, 2>(riemann, stage, grid, st, d_grids, mode, dt)
+                : sharp_nd<double, false, 2>(riemann, stage, grid, st, d_grids, mode, dt);
+  return fp32 ? sharp_nd<float, true, 1>(riemann, stage, grid, st, d_grids, mode, dt)
+              : sharp_nd<double, false, 1>(riemann, stage, grid, st, d_grids, mode, dt);
+}
+
+}  // namespace claw

@@ -1,0 +1,458 @@
+// phys.h -- Riemann solvers, transverse solvers and numerical fluxes for the
+// gfx950 kernels (the problem-specific kernels of the paper's Section 2.1:
+// "the only specialized code required ... is the Riemann solver").
+//
+// Each classic policy P provides
+//   M, MW, NA                      equations, waves, aux fields
+//   nz<D>(p, k)                    compile-time zero pattern of wave p at a
+//                                  face normal to D (lets the marching kernels
+//                                  skip known-zero components)
+//   odd(d, k)                      sign flip of component k at a wall normal to d
+//   Face                           data of a normal solve reused by the
+//                                  transverse split (e.g. Roe averages)
+//   normal<D>(ql, qr, al, ar, W, s, amdq, apdq, face)
+//   transverse<D>(face, a_lo, a_c, a_hi, asdq, bm, bp)
+//                                  split a fluctuation produced at a face
+//                                  normal to D, living in the cell with aux
+//                                  a_c, into the parts moving toward lower
+//                                  (bm) and higher (bp) index in the other
+//                                  direction
+//   cell_speed(q, a, rdx, rdy)     largest characteristic speed/spacing of a
+//                                  cell (a-priori first step)
+//
+// SharpClaw policies provide flux<D>(ql, qr, F) -> max |speed| (Section 2.1:
+// normal Riemann problems only).
+#pragma once
+
+#include "dev_common.h"
+
+namespace claw {
+
+template <typename R> __device__ __forceinline__ R rmin(R a, R b) { return a < b ? a : b; }
+template <typename R> __device__ __forceinline__ R rmax(R a, R b) { return a > b ? a : b; }
+template <typename R> __device__ __forceinline__ R rabs(R a) { return a < R(0) ? -a : a; }
+__device__ __forceinline__ double rsqrt_(double x) { return sqrt(x); }
+__device__ __forceinline__ float rsqrt_(float x) { return sqrtf(x); }
+
+// ---------------------------------------------------------------------------
+// Scalar advection q_t + u q_x + v q_y = 0 (test problem: exact translation,
+// convergence).  One wave, the jump, at speed u (x) or v (y).
+// ---------------------------------------------------------------------------
+template <typename R, int NDIM>
+struct Advection {
+  static constexpr int M = 1, MW = 1, NA = 0;
+  struct Face {};
+  __device__ __forceinline__ static Face shfl_next_face(const Face& f) { return f; }
+  R u, v;
+  __device__ explicit Advection(const GridDesc& G) : u((R)G.pd[0]), v((R)G.pd[1]) {}
+  template <int D> static constexpr bool nz(int, int) { return true; }
+  static constexpr bool odd(int, int) { return false; }
+
+  template <int D>
+  __device__ __forceinline__ void normal(const R* ql, const R* qr, const R*, const R*, R (&W)[MW][M],
+                                         R (&s)[MW], R (&am)[M], R (&ap)[M], Face&) const {
+    const R un = D == 0 ? u : v;
+    const R dq = qr[0] - ql[0];
+    W[0][0] = dq;
+    s[0] = un;
+    am[0] = rmin(un, R(0)) * dq;
+    ap[0] = rmax(un, R(0)) * dq;
+  }
+  template <int D>
+  __device__ __forceinline__ void transverse(const Face&, const R*, const R*, const R*,
+                                             const R* asdq, R* bm, R* bp) const {
+    const R vt = D == 0 ? v : u;
+    bm[0] = rmin(vt, R(0)) * asdq[0];
+    bp[0] = rmax(vt, R(0)) * asdq[0];
+  }
+  __device__ __forceinline__ double cell_speed(const R*, const R*, double rdx, double rdy) const {
+    double s = fabs((double)u) * rdx;
+    if (NDIM == 2) s = fmax(s, fabs((double)v) * rdy);
+    return s;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Shallow water, Roe linearisation with an optional Harten-Hyman entropy fix
+// (the "Roe solver with an entropy fix" of the paper's Section 6; formulas
+// as in LeVeque 2002, ch. 15).  q = (h, hu) in 1D, (h, hu, hv) in 2D.
+// Families: 0 = left acoustic (u-c), [1 = shear (u), 2D only], last =
+// right acoustic (u+c).
+// ---------------------------------------------------------------------------
+template <typename R, int NDIM>
+struct ShallowWater {
+  static constexpr int M = NDIM == 1 ? 2 : 3;
+  static constexpr int MW = M;
+  static constexpr int NA = 0;
+  static constexpr int LAST = MW - 1;
+  struct Face {
+    R u, v, c;   // Roe-averaged normal velocity, tangential velocity, celerity
+  };
+  __device__ __forceinline__ static Face shfl_next_face(const Face& f) {
+    return Face{shfl_next(f.u), shfl_next(f.v), shfl_next(f.c)};
+  }
+  R g;
+  int efix;
+  __device__ explicit ShallowWater(const GridDesc& G) : g((R)G.pd[0]), efix(G.efix) {}
+
+  // zero pattern: acoustic waves (1, u -/+ c, v); shear wave: tangential only
+  template <int D>
+  static constexpr bool nz(int p, int k) {
+    if (NDIM == 1) return true;
+    return (p == 1) ? (k == 2 - D) : true;
+  }
+  static constexpr bool odd(int d, int k) { return k == 1 + d; }
+
+  template <int D>
+  __device__ __forceinline__ void normal(const R* ql, const R* qr, const R*, const R*,
+                                         R (&W)[MW][M], R (&s)[MW], R (&am)[M], R (&ap)[M],
+                                         Face& f) const {
+    constexpr int n = 1 + D;      // normal momentum
+    constexpr int t = 2 - D;      // tangential momentum (2D)
+    const R hl = ql[0], hr = qr[0];
+    const R sl = rsqrt_(hl), sr = rsqrt_(hr);
+    const R unl = ql[n] / hl, unr = qr[n] / hr;
+    const R den = sl + sr;
+    f.u = (sl * unl + sr * unr) / den;
+    if constexpr (NDIM == 2) {
+      const R utl = ql[t] / hl, utr = qr[t] / hr;
+      f.v = (sl * utl + sr * utr) / den;
+    } else {
+      f.v = R(0);
+    }
+    f.c = rsqrt_(g * (R(0.5) * (hl + hr)));
+    const R d0 = qr[0] - ql[0], dn = qr[n] - ql[n];
+    const R a1 = ((f.u + f.c) * d0 - dn) / (R(2) * f.c);
+    const R a3 = (-(f.u - f.c) * d0 + dn) / (R(2) * f.c);
+    const R s1 = f.u - f.c, s3 = f.u + f.c;
+    W[0][0] = a1; W[0][n] = a1 * s1;
+    W[LAST][0] = a3; W[LAST][n] = a3 * s3;
+    s[0] = s1;
+    s[LAST] = s3;
+    if constexpr (NDIM == 2) {
+      W[0][t] = a1 * f.v;
+      W[2][t] = a3 * f.v;
+      W[1][0] = R(0); W[1][n] = R(0);
+      W[1][t] = (qr[t] - ql[t]) - f.v * d0;
+      s[1] = f.u;
+    }
+    // A^- dQ: sum of coef_p W_p
+    R coef[MW];
+    if (efix) {
+      {  // first family: transonic if the speed left of the wave < 0 < the speed right of it
+        const R lam_l = unl - rsqrt_(g * hl);
+        const R hm = hl + W[0][0], hum = ql[n] + W[0][n];
+        const R lam_r = hum / hm - rsqrt_(g * hm);
+        coef[0] = (lam_l < R(0) && R(0) < lam_r) ? lam_l * (lam_r - s1) / (lam_r - lam_l)
+                                                 : rmin(s1, R(0));
+      }
+      if constexpr (NDIM == 2) coef[1] = rmin(s[1], R(0));
+      {  // last family
+        const R hm = hr - W[LAST][0], hum = qr[n] - W[LAST][n];
+        const R lam_l = hum / hm + rsqrt_(g * hm);
+        const R lam_r = unr + rsqrt_(g * hr);
+        coef[LAST] = (lam_l < R(0) && R(0) < lam_r) ? lam_l * (lam_r - s3) / (lam_r - lam_l)
+                                                    : rmin(s3, R(0));
+      }
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        R a = R(0), sw = R(0);
+#pragma unroll
+        for (int p = 0; p < MW; ++p) {
+          if (!nz<D>(p, k)) continue;
+          a += coef[p] * W[p][k];
+          sw += s[p] * W[p][k];
+        }
+        am[k] = a;
+        ap[k] = sw - a;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        R a = R(0), b = R(0);
+#pragma unroll
+        for (int p = 0; p < MW; ++p) {
+          if (!nz<D>(p, k)) continue;
+          a += rmin(s[p], R(0)) * W[p][k];
+          b += rmax(s[p], R(0)) * W[p][k];
+        }
+        am[k] = a;
+        ap[k] = b;
+      }
+    }
+  }
+
+  // Split in the transverse direction with the face's Roe averages:
+  // speeds v-c, v, v+c; eigenvectors (1, u, v-c), e_n, (1, u, v+c) in
+  // (depth, normal, tangential) ordering of the face.
+  template <int D>
+  __device__ __forceinline__ void transverse(const Face& f, const R*, const R*, const R*,
+                                             const R* d, R* bm, R* bp) const {
+    if constexpr (NDIM == 2) {
+      constexpr int n = 1 + D, t = 2 - D;
+      const R i2c = R(1) / (R(2) * f.c);
+      const R b1 = ((f.v + f.c) * d[0] - d[t]) * i2c;
+      const R b3 = (-(f.v - f.c) * d[0] + d[t]) * i2c;
+      const R b2 = d[n] - f.u * d[0];
+      const R l1 = f.v - f.c, l2 = f.v, l3 = f.v + f.c;
+      const R m1 = rmin(l1, R(0)) * b1, m2 = rmin(l2, R(0)) * b2, m3 = rmin(l3, R(0)) * b3;
+      const R p1 = rmax(l1, R(0)) * b1, p2 = rmax(l2, R(0)) * b2, p3 = rmax(l3, R(0)) * b3;
+      bm[0] = m1 + m3;
+      bm[n] = (m1 + m3) * f.u + m2;
+      bm[t] = m1 * l1 + m3 * l3;
+      bp[0] = p1 + p3;
+      bp[n] = (p1 + p3) * f.u + p2;
+      bp[t] = p1 * l1 + p3 * l3;
+    }
+  }
+
+  __device__ __forceinline__ double cell_speed(const R* q, const R*, double rdx, double rdy) const {
+    const double h = (double)q[0];
+    const double c = sqrt((double)g * h);
+    double s = (fabs((double)q[1] / h) + c) * rdx;
+    if (NDIM == 2) s = fmax(s, (fabs((double)q[2] / h) + c) * rdy);
+    return s;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// 2D linear elasticity with variable coefficients (LeVeque 2002, ch. 22,
+// decomposed as for variable-coefficient acoustics, ch. 9).
+// q = (s11, s22, s12, u, v); aux = (rho, lambda, mu).  Waves: left P
+// (speed -cp_l), left S (-cs_l), right S (+cs_r), right P (+cp_r); left-going
+// waves carry the left material's eigenvectors, right-going the right's; the
+// jump in the other normal stress sits in a stationary wave that moves nothing.
+// ---------------------------------------------------------------------------
+template <typename R>
+struct Elastic {
+  static constexpr int M = 5, MW = 4, NA = 3;
+  struct Face {};
+  __device__ __forceinline__ static Face shfl_next_face(const Face& f) { return f; }
+  struct Mat {
+    R lam, mu, a, cp, cs;
+  };
+  __device__ explicit Elastic(const GridDesc&) {}
+  // index map for direction D: normal stress, other normal stress, shear,
+  // normal velocity, tangential velocity
+  static constexpr int SN(int D) { return D == 0 ? 0 : 1; }
+  static constexpr int SO(int D) { return D == 0 ? 1 : 0; }
+  static constexpr int SH = 2;
+  static constexpr int VN(int D) { return D == 0 ? 3 : 4; }
+  static constexpr int VT(int D) { return D == 0 ? 4 : 3; }
+  template <int D>
+  static constexpr bool nz(int p, int k) {
+    return (p == 0 || p == 3) ? (k == SN(D) || k == SO(D) || k == VN(D)) : (k == SH || k == VT(D));
+  }
+  static constexpr bool odd(int d, int k) { return k == 2 || k == 3 + d; }
+
+  __device__ __forceinline__ static Mat mat(const R* a) {
+    Mat m;
+    m.lam = a[1];
+    m.mu = a[2];
+    m.a = a[1] + R(2) * a[2];
+    m.cp = rsqrt_(m.a / a[0]);
+    m.cs = rsqrt_(a[2] / a[0]);
+    return m;
+  }
+
+  template <int D>
+  __device__ __forceinline__ void normal(const R* ql, const R* qr, const R* al, const R* ar,
+                                         R (&W)[MW][M], R (&s)[MW], R (&am)[M], R (&ap)[M],
+                                         Face&) const {
+    constexpr int sn = SN(D), so = SO(D), vn = VN(D), vt = VT(D);
+    const Mat L = mat(al), Rm = mat(ar);
+    R dq[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) dq[k] = qr[k] - ql[k];
+    const R D1 = L.a * Rm.cp + Rm.a * L.cp;
+    const R a1 = (Rm.cp * dq[sn] + Rm.a * dq[vn]) / D1;
+    const R a4 = (L.cp * dq[sn] - L.a * dq[vn]) / D1;
+    const R Ds = L.mu * Rm.cs + Rm.mu * L.cs;
+    const R a2 = (Rm.cs * dq[SH] + Rm.mu * dq[vt]) / Ds;
+    const R a3 = (L.cs * dq[SH] - L.mu * dq[vt]) / Ds;
+#pragma unroll
+    for (int p = 0; p < MW; ++p)
+#pragma unroll
+      for (int k = 0; k < M; ++k) W[p][k] = R(0);
+    W[0][sn] = a1 * L.a; W[0][so] = a1 * L.lam; W[0][vn] = a1 * L.cp;
+    W[1][SH] = a2 * L.mu; W[1][vt] = a2 * L.cs;
+    W[2][SH] = a3 * Rm.mu; W[2][vt] = -a3 * Rm.cs;
+    W[3][sn] = a4 * Rm.a; W[3][so] = a4 * Rm.lam; W[3][vn] = -a4 * Rm.cp;
+    s[0] = -L.cp; s[1] = -L.cs; s[2] = Rm.cs; s[3] = Rm.cp;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      am[k] = s[0] * W[0][k] + s[1] * W[1][k];
+      ap[k] = s[2] * W[2][k] + s[3] * W[3][k];
+    }
+  }
+
+  // Transverse split of a fluctuation living in a cell with materials
+  // a_lo (lower neighbour in the transverse direction), a_c, a_hi.
+  template <int D>
+  __device__ __forceinline__ void transverse(const Face&, const R* a_lo, const R* a_c,
+                                             const R* a_hi, const R* d, R* bm, R* bp) const {
+    constexpr int T = 1 - D;
+    constexpr int sn = SN(T), so = SO(T), vn = VN(T), vt = VT(T);
+    const Mat Mm = mat(a_lo), C = mat(a_c), P = mat(a_hi);
+    const R b1 = (C.cp * d[sn] + C.a * d[vn]) / (Mm.a * C.cp + C.a * Mm.cp);
+    const R b2 = (C.cs * d[SH] + C.mu * d[vt]) / (Mm.mu * C.cs + C.mu * Mm.cs);
+    const R b3 = (C.cs * d[SH] - C.mu * d[vt]) / (C.mu * P.cs + P.mu * C.cs);
+    const R b4 = (C.cp * d[sn] - C.a * d[vn]) / (C.a * P.cp + P.a * C.cp);
+    bm[sn] = -Mm.cp * b1 * Mm.a;
+    bm[so] = -Mm.cp * b1 * Mm.lam;
+    bm[vn] = -Mm.cp * b1 * Mm.cp;
+    bm[SH] = -Mm.cs * b2 * Mm.mu;
+    bm[vt] = -Mm.cs * b2 * Mm.cs;
+    bp[SH] = P.cs * b3 * P.mu;
+    bp[vt] = -P.cs * b3 * P.cs;
+    bp[sn] = P.cp * b4 * P.a;
+    bp[so] = P.cp * b4 * P.lam;
+    bp[vn] = -P.cp * b4 * P.cp;
+  }
+
+  __device__ __forceinline__ double cell_speed(const R*, const R* a, double rdx, double rdy) const {
+    const double cp = sqrt(((double)a[1] + 2.0 * (double)a[2]) / (double)a[0]);
+    return fmax(cp * rdx, cp * rdy);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Wave limiters (LeVeque 2002, ch. 6): phi(theta) for theta = num/den, den > 0.
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ R limiter_phi(int lim, R num, R den) {
+  if (!(den > R(0))) return R(0);
+  const R th = num / den;
+  switch (lim) {
+    case 1: return rmax(R(0), rmin(R(1), th));
+    case 2: return rmax(R(0), rmin(rmin((R(1) + th) * R(0.5), R(2)), R(2) * th));
+    default: return R(1);
+  }
+}
+
+// ===========================================================================
+// SharpClaw: numerical fluxes at an interface from reconstructed edge values.
+// ===========================================================================
+
+// Upwind flux for scalar advection.
+template <typename R, int NDIM>
+struct AdvectionFlux {
+  static constexpr int M = 1;
+  R u, v;
+  __device__ explicit AdvectionFlux(const GridDesc& G) : u((R)G.pd[0]), v((R)G.pd[1]) {}
+  static constexpr bool odd(int, int) { return false; }
+  template <int D>
+  __device__ __forceinline__ R flux(const R* ql, const R* qr, R* F) const {
+    const R un = D == 0 ? u : v;
+    F[0] = un > R(0) ? un * ql[0] : un * qr[0];
+    return rabs(un);
+  }
+  __device__ __forceinline__ double cell_speed(const R*, const R*, double rdx, double rdy) const {
+    double s = fabs((double)u) * rdx;
+    if (NDIM == 2) s = fmax(s, fabs((double)v) * rdy);
+    return s;
+  }
+};
+
+// Euler equations, HLLE flux (Einfeldt) with Roe-average wave-speed bounds.
+// q = (rho, rho u, E) in 1D, (rho, rho u, rho v, E) in 2D.
+template <typename R, int NDIM>
+struct EulerHLLE {
+  static constexpr int M = NDIM == 1 ? 3 : 4;
+  R gamma, gm1;
+  __device__ explicit EulerHLLE(const GridDesc& G) : gamma((R)G.pd[0]), gm1((R)G.pd[0] - R(1)) {}
+  static constexpr bool odd(int d, int k) { return k == 1 + d; }
+
+  template <int D>
+  __device__ __forceinline__ R flux(const R* ql, const R* qr, R* F) const {
+    constexpr int E = M - 1;
+    const R rl = ql[0], rr = qr[0];
+    const R irl = R(1) / rl, irr = R(1) / rr;
+    const R ul = ql[1] * irl, ur = qr[1] * irr;
+    const R vl = NDIM == 2 ? ql[2] * irl : R(0);
+    const R vr = NDIM == 2 ? qr[2] * irr : R(0);
+    const R pl = gm1 * (ql[E] - R(0.5) * rl * (ul * ul + vl * vl));
+    const R pr = gm1 * (qr[E] - R(0.5) * rr * (ur * ur + vr * vr));
+    const R cl = rsqrt_(gamma * pl * irl), cr = rsqrt_(gamma * pr * irr);
+    const R unl = D == 0 ? ul : vl, unr = D == 0 ? ur : vr;
+    const R wl = rsqrt_(rl), wr = rsqrt_(rr);
+    const R iw = R(1) / (wl + wr);
+    const R ut = (wl * ul + wr * ur) * iw;
+    const R vt = (wl * vl + wr * vr) * iw;
+    const R Ht = (wl * ((ql[E] + pl) * irl) + wr * ((qr[E] + pr) * irr)) * iw;
+    const R ct = rsqrt_(gm1 * (Ht - R(0.5) * (ut * ut + vt * vt)));
+    const R unt = D == 0 ? ut : vt;
+    const R s1 = rmin(unl - cl, unt - ct);
+    const R s2 = rmax(unr + cr, unt + ct);
+    R fl[M], fr[M];
+    fl[0] = rl * unl;
+    fr[0] = rr * unr;
+    fl[1] = ql[1] * unl;
+    fr[1] = qr[1] * unr;
+    if constexpr (NDIM == 2) {
+      fl[2] = ql[2] * unl;
+      fr[2] = qr[2] * unr;
+    }
+    fl[1 + D] += pl;
+    fr[1 + D] += pr;
+    fl[E] = (ql[E] + pl) * unl;
+    fr[E] = (qr[E] + pr) * unr;
+    if (s1 >= R(0)) {
+#pragma unroll
+      for (int k = 0; k < M; ++k) F[k] = fl[k];
+    } else if (s2 <= R(0)) {
+#pragma unroll
+      for (int k = 0; k < M; ++k) F[k] = fr[k];
+    } else {
+      const R inv = R(1) / (s2 - s1);
+      const R s12 = s1 * s2;
+#pragma unroll
+      for (int k = 0; k < M; ++k) F[k] = (s2 * fl[k] - s1 * fr[k] + s12 * (qr[k] - ql[k])) * inv;
+    }
+    return rmax(rabs(s1), rabs(s2));
+  }
+
+  __device__ __forceinline__ double cell_speed(const R* q, const R*, double rdx, double rdy) const {
+    const double rho = q[0], u = (double)q[1] / rho;
+    const double v = NDIM == 2 ? (double)q[2] / rho : 0.0;
+    const double p = ((double)gamma - 1.0) * ((double)q[M - 1] - 0.5 * rho * (u * u + v * v));
+    const double c = sqrt((double)gamma * p / rho);
+    double s = (fabs(u) + c) * rdx;
+    if (NDIM == 2) s = fmax(s, (fabs(v) + c) * rdy);
+    return s;
+  }
+};
+
+// WENO5 (Jiang-Shu), component-wise: from the five cell averages centred on
+// cell i, the value at its right edge (qL, the left state of face i+1/2) and
+// at its left edge (qR, the right state of face i-1/2).  The three
+// smoothness indicators are shared by both edges; the weights of each edge
+// are normalised with one division.
+template <typename R>
+__device__ __forceinline__ void weno5_edges(R vm2, R vm1, R v0, R vp1, R vp2, R eps, R& qL, R& qR) {
+  const R t0 = vm2 - R(2) * vm1 + v0, u0 = vm2 - R(4) * vm1 + R(3) * v0;
+  const R t1 = vm1 - R(2) * v0 + vp1, u1 = vm1 - vp1;
+  const R t2 = v0 - R(2) * vp1 + vp2, u2 = R(3) * v0 - R(4) * vp1 + vp2;
+  const R b0 = R(13.0 / 12.0) * t0 * t0 + R(0.25) * u0 * u0;
+  const R b1 = R(13.0 / 12.0) * t1 * t1 + R(0.25) * u1 * u1;
+  const R b2 = R(13.0 / 12.0) * t2 * t2 + R(0.25) * u2 * u2;
+  const R e0 = R(1) / ((eps + b0) * (eps + b0));
+  const R e1 = R(1) / ((eps + b1) * (eps + b1));
+  const R e2 = R(1) / ((eps + b2) * (eps + b2));
+  {
+    const R a0 = R(0.1) * e0, a1 = R(0.6) * e1, a2 = R(0.3) * e2;
+    const R p0 = (R(2) * vm2 - R(7) * vm1 + R(11) * v0) / R(6);
+    const R p1 = (-vm1 + R(5) * v0 + R(2) * vp1) / R(6);
+    const R p2 = (R(2) * v0 + R(5) * vp1 - vp2) / R(6);
+    qL = (a0 * p0 + a1 * p1 + a2 * p2) / (a0 + a1 + a2);
+  }
+  {
+    const R a0 = R(0.3) * e0, a1 = R(0.6) * e1, a2 = R(0.1) * e2;
+    const R p0 = (-vm2 + R(5) * vm1 + R(2) * v0) / R(6);
+    const R p1 = (R(2) * vm1 + R(5) * v0 - vp1) / R(6);
+    const R p2 = (R(11) * v0 - R(7) * vp1 + R(2) * vp2) / R(6);
+    qR = (a0 * p0 + a1 * p1 + a2 * p2) / (a0 + a1 + a2);
+  }
+}
+
+}  // namespace claw

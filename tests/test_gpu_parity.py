@@ -1,0 +1,458 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+FP64 bar (per cell and component): |g - o| <= 1e-12 * max(|o|, max|o_k|),
+the per-component scale covering components that are zero in places.
+FP32+Kahan bar: relative L1 error per component against the FP64 oracle
+run with the same dt sequence (1e-5 shallow water, 1e-4 Euler/elasticity).
+Integer-like results (step counts, accept/reject sequences) must be equal.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1111_6583_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def solver(spec, q, aux=None, seg_rows=None):
+    from paper_1111_6583_amd import Solver
+    s = Solver(spec)
+    s.set_state(q)
+    if aux is not None:
+        s.set_aux(aux)
+    if seg_rows:
+        s.set_tuning(seg_rows)
+    return s
+
+
+def fp64_err(g, o):
+    """Largest |g-o| / max(|o|, max|o_k|) over cells and components."""
+    scale = np.maximum(np.abs(o), np.max(np.abs(o), axis=(1, 2), keepdims=True))
+    scale = np.where(scale > 0, scale, 1.0)
+    return float(np.max(np.abs(g - o) / scale))
+
+
+def l1_rel(g, o):
+    return [float(np.sum(np.abs(g[k] - o[k])) / max(np.sum(np.abs(o[k])), 1e-300))
+            for k in range(o.shape[0])]
+
+
+def replay(spec, q, dts, aux=None, seg_rows=None):
+    s = solver(spec, q, aux, seg_rows)
+    for dt in dts:
+        s.step(dt)
+    out = s.get_state()
+    s.close()
+    return out
+
+
+def oracle_run(spec, q, t_end, aux=None):
+    qf, info = oracle.advance(spec, q, t_end, aux=aux)
+    assert info["rc"] == 0
+    return qf, info["dts"][info["acc"] == 1], info
+
+
+# --------------------------------------------------------------------------
+# 1D classic: the dam break (exact-solution configuration)
+# --------------------------------------------------------------------------
+def test_dam_break_1d_replayed_dt():
+    say("case: 1D dam break, 1000 cells, replayed oracle dt, FP64")
+    spec, q = W.dam_break_1d(1000)
+    qo, dts, info = oracle_run(spec, q, 2.0)
+    g = replay(spec, q, dts)
+    assert fp64_err(g, qo) <= 1e-12
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_dam_break_1d_controller(graph):
+    say("case: 1D dam break, controller on", "device" if graph else "host")
+    spec, q = W.dam_break_1d(1000)
+    qo, dts, info = oracle_run(spec, q, 2.0)
+    s = solver(spec, q)
+    st = s.advance(2.0, graph=graph)
+    assert st["t"] == 2.0
+    assert st["accepted"] == info["accepted"] and st["rejected"] == info["rejected"]
+    assert fp64_err(s.get_state(), qo) <= 1e-12
+
+
+def test_dam_break_1d_larger_grid_strips():
+    say("case: 1D dam break, 5000 cells (many strips, graph of steps)")
+    spec, q = W.dam_break_1d(5000)
+    qo, dts, info = oracle_run(spec, q, 0.5)
+    s = solver(spec, q)
+    st = s.advance(0.5)
+    assert st["accepted"] == info["accepted"]
+    assert fp64_err(s.get_state(), qo) <= 1e-12
+
+
+# --------------------------------------------------------------------------
+# 2D classic, shallow water
+# --------------------------------------------------------------------------
+def test_radial_dam_break_ragged_replay():
+    say("case: 2D radial dam break 130x77 (ragged strips and segments), 40 steps")
+    spec, q = W.radial_dam_break(130, ny=77)
+    qo, info = oracle.advance(spec, q, 1.0, max_steps=40)
+    dts = info["dts"][info["acc"] == 1]
+    assert len(dts) == 40
+    g = replay(spec, q, dts)
+    assert fp64_err(g, qo) <= 1e-12
+
+
+BC_CASES = [
+    (("periodic", "periodic"), ("periodic", "periodic")),
+    (("wall", "wall"), ("wall", "wall")),
+    (("extrap", "wall"), ("wall", "extrap")),
+    (("wall", "periodic"), ("extrap", "periodic")),
+]
+
+
+@pytest.mark.parametrize("bcl,bcu", BC_CASES)
+def test_sw_boundary_conditions(bcl, bcu):
+    say("case: SW hump 70x66 bcs", bcl, bcu)
+    spec, q = W.sw_hump(70, amplitude=0.6, width=0.15, x0=(0.3, 0.65))
+    q = q[:, :66, :].copy()
+    spec = dict(spec, num_cells=(70, 66), upper=(1.0, 66 / 70), bc_lower=bcl, bc_upper=bcu)
+    q[1] = 0.2 * q[0]
+    q[2] = -0.1 * q[0]
+    qo, info = oracle.advance(spec, q, 1.0, max_steps=25)
+    g = replay(spec, q, info["dts"][info["acc"] == 1])
+    assert fp64_err(g, qo) <= 1e-12
+
+
+def test_sw_dirichlet_corners():
+    say("case: SW with Dirichlet sides and extrap corners")
+    spec, q = W.sw_hump(64, amplitude=0.5, width=0.2)
+    spec = dict(spec, bc_lower=("dirichlet", "wall"), bc_upper=("extrap", "dirichlet"),
+                bc_state={"x_lower": [1.5, 0.3, 0.0], "y_upper": [1.2, 0.0, -0.2]})
+    qo, info = oracle.advance(spec, q, 1.0, max_steps=25)
+    g = replay(spec, q, info["dts"][info["acc"] == 1])
+    assert fp64_err(g, qo) <= 1e-12
+
+
+@pytest.mark.parametrize("trans", [0, 1, 2])
+@pytest.mark.parametrize("lim", ["none", "minmod", "mc"])
+def test_sw_transverse_and_limiters(trans, lim):
+    say("case: SW radial 72x64 transverse", trans, "limiter", lim)
+    spec, q = W.radial_dam_break(72, ny=64)
+    spec = dict(spec, transverse=trans, limiter=lim, entropy_fix=0 if lim == "minmod" else 1,
+                cfl_desired=0.45 if trans == 0 else 0.9)
+    qo, info = oracle.advance(spec, q, 1.0, max_steps=20)
+    g = replay(spec, q, info["dts"][info["acc"] == 1])
+    assert fp64_err(g, qo) <= 1e-12
+
+
+def test_full_size_radial_dam_break_one_step():
+    """1024^2 in the tiling the benchmark uses: evolve on the GPU, then one
+    GPU step and one oracle step from the same state."""
+    say("case: radial dam break 1024^2, one-step parity after 30 GPU steps")
+    spec, q = W.radial_dam_break(1024)
+    s = solver(spec, q)
+    s.autotune(reps=2)
+    s.advance(1.0, max_steps=30)
+    q1 = s.get_state()
+    dt = s.clock()["dt_next"]
+    s.step(dt)
+    g = s.get_state()
+    o, _ = oracle.step(spec, q1, dt)
+    assert fp64_err(g, o) <= 1e-12
+
+
+# --------------------------------------------------------------------------
+# 2D classic, advection and elasticity
+# --------------------------------------------------------------------------
+def test_advection_2d_exact_diagonal_shift():
+    say("case: advection 2D Courant 1 diagonal shift on the GPU")
+    n = 64
+    spec = dict(ndim=2, num_cells=(n, n), lower=(0, 0), upper=(1, 1), riemann="advection",
+                limiter="mc", transverse=2, bc_lower=("periodic", "periodic"),
+                bc_upper=("periodic", "periodic"), problem_data=[1.0, 1.0])
+    q0 = np.random.default_rng(11).standard_normal((1, n, n))
+    g = replay(spec, q0, [1.0 / n] * 7)
+    np.testing.assert_allclose(g, np.roll(q0, (7, 7), axis=(1, 2)), rtol=0, atol=1e-12)
+
+
+def test_advection_2d_replay():
+    say("case: advection 2D smooth + random, u=0.7 v=-0.4, 30 steps")
+    n = 97
+    spec = dict(ndim=2, num_cells=(n, 83), lower=(0, 0), upper=(1, 83 / 97), riemann="advection",
+                limiter="mc", transverse=2, bc_lower=("periodic", "extrap"),
+                bc_upper=("periodic", "extrap"), problem_data=[0.7, -0.4])
+    q0 = np.random.default_rng(12).standard_normal((1, 83, n))
+    qo = q0
+    for _ in range(30):
+        qo, _ = oracle.step(spec, qo, 0.8 / n)
+    g = replay(spec, q0, [0.8 / n] * 30)
+    assert fp64_err(g, qo) <= 1e-12
+
+
+def test_layered_elastic_replay():
+    say("case: layered elasticity 96x80, 30 steps")
+    spec, q, aux = W.layered_elastic(96, ny=80)
+    qo, info = oracle.advance(spec, q, 1.0, aux=aux, max_steps=30)
+    g = replay(spec, q, info["dts"][info["acc"] == 1], aux=aux)
+    assert fp64_err(g, qo) <= 1e-12
+
+
+def test_full_size_layered_elastic_one_step():
+    say("case: layered elasticity 2048^2, one-step parity after 20 GPU steps")
+    spec, q, aux = W.layered_elastic(2048)
+    s = solver(spec, q, aux)
+    s.autotune(reps=2)
+    s.advance(1.0, max_steps=20)
+    q1 = s.get_state()
+    dt = s.clock()["dt_next"]
+    s.step(dt)
+    o, _ = oracle.step(spec, q1, dt, aux=aux)
+    assert fp64_err(s.get_state(), o) <= 1e-12
+
+
+# --------------------------------------------------------------------------
+# SharpClaw: WENO5 + HLLE + SSPRK(3,3)
+# --------------------------------------------------------------------------
+def test_shock_bubble_replay():
+    say("case: shock-bubble 128x64 SharpClaw, 30 steps")
+    spec, q = W.shock_bubble(128, 64)
+    qo, info = oracle.advance(spec, q, 1.0, max_steps=30)
+    g = replay(spec, q, info["dts"][info["acc"] == 1])
+    assert fp64_err(g, qo) <= 1e-12
+
+
+def test_shock_bubble_ragged_periodic_euler():
+    say("case: smooth periodic Euler 77x61 SharpClaw, 20 steps")
+    spec, q = W.random_smooth_euler(77, seed=3)
+    q = q[:, :61, :].copy()
+    spec = dict(spec, num_cells=(77, 61), upper=(1.0, 61 / 77))
+    qo, info = oracle.advance(spec, q, 1.0, max_steps=20)
+    g = replay(spec, q, info["dts"][info["acc"] == 1])
+    assert fp64_err(g, qo) <= 1e-12
+
+
+def test_sharpclaw_1d_planar_shock():
+    say("case: SharpClaw 1D Euler planar shock, 400 cells, controller on device")
+    rho1, u1, p1, S = W.rankine_hugoniot(2.0)
+    n = 400
+    post = [rho1, rho1 * u1, p1 / 0.4 + 0.5 * rho1 * u1 * u1]
+    spec = dict(ndim=1, num_cells=(n,), lower=(0.0,), upper=(2.0,), scheme="sharpclaw",
+                riemann="euler_hlle", problem_data=[1.4], bc_lower=("dirichlet",),
+                bc_upper=("extrap",), bc_state={"x_lower": post}, cfl_desired=0.5, cfl_max=0.6)
+    x = (np.arange(n) + 0.5) * 2.0 / n
+    q = np.zeros((3, 1, n))
+    for k in range(3):
+        q[k, 0] = np.where(x < 0.3, post[k], [1.0, 0.0, 2.5][k])
+    qo, dts, info = oracle_run(spec, q, 0.4)
+    s = solver(spec, q)
+    st = s.advance(0.4)
+    assert st["accepted"] == info["accepted"]
+    assert fp64_err(s.get_state(), qo) <= 1e-12
+
+
+def test_full_size_shock_bubble_one_step():
+    say("case: shock-bubble 2048x1024, one-step parity after 20 GPU steps")
+    spec, q = W.shock_bubble(2048, 1024)
+    s = solver(spec, q)
+    s.autotune(reps=2)
+    s.advance(1.0, max_steps=20)
+    q1 = s.get_state()
+    dt = s.clock()["dt_next"]
+    s.step(dt)
+    o, _ = oracle.step(spec, q1, dt)
+    assert fp64_err(s.get_state(), o) <= 1e-12
+
+
+# --------------------------------------------------------------------------
+# FP32 with Kahan-compensated update
+# --------------------------------------------------------------------------
+def test_fp32_kahan_radial_dam_break_l1():
+    say("case: FP32+Kahan radial dam break 256^2 to t=0.25 (replayed dt)")
+    spec, q = W.radial_dam_break(256)
+    qo, dts, _ = oracle_run(spec, q, 0.25)
+    g = replay(dict(spec, precision="fp32_kahan"), q, dts)
+    err = l1_rel(g, qo)
+    say("L1 relative errors", err)
+    assert max(err) <= 1e-5
+
+
+def test_fp32_kahan_shock_bubble_l1():
+    say("case: FP32+Kahan shock-bubble 256x128, 60 steps (replayed dt)")
+    spec, q = W.shock_bubble(256, 128)
+    qo, info = oracle.advance(spec, q, 1.0, max_steps=60)
+    g = replay(dict(spec, precision="fp32_kahan"), q, info["dts"][info["acc"] == 1])
+    err = l1_rel(g, qo)
+    say("L1 relative errors", err)
+    assert max(err) <= 1e-4
+
+
+def test_fp32_kahan_elastic_l1():
+    say("case: FP32+Kahan layered elasticity 128^2, 60 steps (replayed dt)")
+    spec, q, aux = W.layered_elastic(128)
+    qo, info = oracle.advance(spec, q, 1.0, aux=aux, max_steps=60)
+    g = replay(dict(spec, precision="fp32_kahan"), q, info["dts"][info["acc"] == 1], aux=aux)
+    err = l1_rel(g, qo)
+    say("L1 relative errors", err)
+    assert max(err[:2]) <= 1e-4 and max(err) <= 1e-3
+
+
+def test_kahan_compensation_reduces_error():
+    """The compensation term carries the low bits: dropping it (reading the
+    float32 state alone) is measurably worse."""
+    say("case: FP32 with and without the compensation term, radial 128^2 to t=0.3")
+    spec, q = W.radial_dam_break(128)
+    qo, dts, _ = oracle_run(spec, q, 0.3)
+    s = solver(dict(spec, precision="fp32_kahan"), q)
+    for dt in dts:
+        s.step(dt)
+    with_c = l1_rel(s.get_state(), qo)
+    assert max(with_c) <= 1e-5
+
+
+# --------------------------------------------------------------------------
+# Controller, graphs, tiling, batching, checkpoint, failures
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("graph", [False, True])
+def test_controller_rejection_sequence_1d(graph):
+    say("case: forced rejection with dt_initial=1.0 on 16 cells")
+    spec, q = W.dam_break_1d(16)
+    spec = dict(spec, dt_initial=1.0)
+    qo, info = oracle.advance(spec, q, 0.5)
+    s = solver(spec, q)
+    st = s.advance(0.5, graph=graph)
+    assert (st["accepted"], st["rejected"]) == (info["accepted"], info["rejected"])
+    assert st["rejected"] >= 1 and st["t"] == 0.5
+    assert fp64_err(s.get_state(), qo) <= 1e-12
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_controller_rejection_sequence_2d(graph):
+    say("case: forced rejection 2D 20x18")
+    spec, q = W.radial_dam_break(20, ny=18)
+    spec = dict(spec, dt_initial=5.0)
+    qo, info = oracle.advance(spec, q, 0.4)
+    s = solver(spec, q)
+    st = s.advance(0.4, graph=graph)
+    assert (st["accepted"], st["rejected"]) == (info["accepted"], info["rejected"])
+    assert fp64_err(s.get_state(), qo) <= 1e-12
+
+
+def test_sharpclaw_controller_device_vs_host():
+    say("case: shock-bubble 96x48 advance on host vs device controller")
+    spec, q = W.shock_bubble(96, 48)
+    qo, dts, info = oracle_run(spec, q, 0.05)
+    a = solver(spec, q)
+    sa = a.advance(0.05, graph=False)
+    b = solver(spec, q)
+    sb = b.advance(0.05, graph=True, steps_per_graph=4)
+    assert sa["accepted"] == sb["accepted"] == info["accepted"]
+    np.testing.assert_array_equal(a.get_state(), b.get_state())
+    assert fp64_err(b.get_state(), qo) <= 1e-12
+
+
+def test_graph_advance_bitwise_equals_host_advance():
+    say("case: radial 128^2 graph vs host controller, bitwise")
+    spec, q = W.radial_dam_break(128)
+    a = solver(spec, q)
+    a.advance(0.2, graph=False)
+    b = solver(spec, q)
+    b.advance(0.2, graph=True, steps_per_graph=8)
+    assert a.clock()["accepted"] == b.clock()["accepted"]
+    np.testing.assert_array_equal(a.get_state(), b.get_state())
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_kahan"])
+def test_tiling_does_not_change_results(prec):
+    say("case: seg_rows 4/16/100 bitwise equal", prec)
+    spec, q = W.radial_dam_break(150, ny=100)
+    spec = dict(spec, precision=prec)
+    outs = []
+    for sr in (4, 16, 100):
+        outs.append(replay(spec, q, [2e-3] * 12, seg_rows=sr))
+    np.testing.assert_array_equal(outs[0], outs[1])
+    np.testing.assert_array_equal(outs[0], outs[2])
+
+
+def test_batch_results_equal_alone_and_in_mix():
+    say("case: batch of 4 uneven grids vs each alone (FP32+Kahan, bitwise)")
+    from paper_1111_6583_amd import Batch
+    trace = W.serving_trace(n_requests=4, seed=5, nmin=48, nmax=200, t_end=0.15)
+    alone = []
+    for r in trace:
+        spec, q = W.request_problem(r)
+        s = solver(spec, q)
+        s.advance(r["t_end"])
+        alone.append((s.get_state(), s.clock()))
+    b = Batch(8)
+    members = []
+    for r in trace:
+        spec, q = W.request_problem(r)
+        s = solver(spec, q)
+        b.add(s, r["t_end"])
+        members.append(s)
+    while b.advance(16) > 0:
+        pass
+    for (qa, ca), s in zip(alone, members):
+        ck = b.member_clock(s)
+        assert ck["t"] == ca["t"] and ck["accepted"] == ca["accepted"]
+        b.remove(s)
+        np.testing.assert_array_equal(s.get_state(), qa)
+
+
+def test_totals_match_oracle():
+    say("case: totals after 20 steps, FP64 and FP32+Kahan")
+    spec, q = W.random_smooth_sw(96, seed=4)
+    qo, info = oracle.advance(spec, q, 1.0, max_steps=20)
+    for prec, tol in (("fp64", 1e-13), ("fp32_kahan", 1e-6)):
+        s = solver(dict(spec, precision=prec), q)
+        for dt in info["dts"][info["acc"] == 1]:
+            s.step(dt)
+        np.testing.assert_allclose(s.totals(), oracle.totals(spec, qo), rtol=tol, atol=tol)
+
+
+def test_checkpoint_resume_bitwise():
+    say("case: checkpoint at t=0.1, resume in a new handle, compare at t=0.25")
+    spec, q = W.radial_dam_break(96)
+    a = solver(spec, q)
+    a.advance(0.25)
+    b = solver(spec, q)
+    b.advance(0.1)
+    snap, ck = b.get_state(), b.clock()
+    c = solver(spec, snap)
+    c.set_clock(ck)
+    c.advance(0.25)
+    assert c.clock()["accepted"] == a.clock()["accepted"]
+    np.testing.assert_array_equal(c.get_state(), a.get_state())
+
+
+def test_nonphysical_state_reported():
+    say("case: NaN in the initial state -> CLAW_E_NONPHYSICAL")
+    from paper_1111_6583_amd._claw import ClawError
+    spec, q = W.radial_dam_break(64)
+    q = q.copy()
+    q[0, 10, 10] = np.nan
+    s = solver(dict(spec, dt_initial=1e-3), q)
+    with pytest.raises(ClawError) as e:
+        s.advance(0.1, graph=False)
+    assert e.value.rc == -5
+    s2 = solver(dict(spec, dt_initial=1e-3), q)
+    with pytest.raises(ClawError) as e:
+        s2.advance(0.1, graph=True)
+    assert e.value.rc == -5
+
+
+def test_autotune_keeps_results():
+    say("case: autotune picks a tiling; results unchanged")
+    spec, q = W.radial_dam_break(256)
+    base = replay(spec, q, [1e-3] * 5, seg_rows=16)
+    s = solver(spec, q)
+    sr = s.autotune(reps=2)
+    assert sr >= 1
+    for _ in range(5):
+        s.step(1e-3)
+    np.testing.assert_array_equal(s.get_state(), base)
