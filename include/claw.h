@@ -229,6 +229,10 @@ int claw_batch_remove(claw_batch_t b, claw_t h);
  * that reached t_end idle); *n_active (may be NULL) receives the number of
  * members still short of their t_end.  Synchronises the batch stream. */
 int claw_batch_advance(claw_batch_t b, int attempts, int* n_active);
+/* Members whose controller has stopped (reached t_end or failed) as of
+ * the last claw_batch_advance: up to `cap` handles into out[], count in
+ * *n_out.  They stay members until claw_batch_remove. */
+int claw_batch_finished(claw_batch_t b, claw_t* out, int cap, int* n_out);
 /* Clock of one member (synchronised). */
 int claw_batch_member_clock(claw_batch_t b, claw_t h, claw_stats* st);
 int claw_batch_destroy(claw_batch_t b);

@@ -107,6 +107,7 @@ def load_library():
         "claw_batch_remove": ([vp, vp], C.c_int),
         "claw_batch_advance": ([vp, C.c_int, ip], C.c_int),
         "claw_batch_member_clock": ([vp, vp, stp], C.c_int),
+        "claw_batch_finished": ([vp, C.POINTER(vp), C.c_int, ip], C.c_int),
         "claw_batch_destroy": ([vp], C.c_int),
     }
     for name, (args, res) in sig.items():

@@ -144,6 +144,7 @@ struct claw_batch {
   hipGraphExec_t graph = nullptr;
   int graph_k = 0;
   Ctrl* h_ctrls = nullptr;
+  int gathered = -1;              // members covered by h_ctrls (-1: stale)
 };
 
 namespace {
@@ -807,6 +808,7 @@ int batch_gather(claw_batch_t b) {
     HIPCHK(hipMemcpyAsync(b->h_ctrls, b->d_ctrls, b->members.size() * sizeof(Ctrl),
                           hipMemcpyDeviceToHost, b->stream));
   HIPCHK(hipStreamSynchronize(b->stream));
+  b->gathered = (int)b->members.size();
   return CLAW_OK;
 }
 
@@ -896,6 +898,7 @@ int claw_batch_add(claw_batch_t b, claw_t h, double t_end) {
   b->fp32 = h->fp32;
   b->members.push_back(h);
   b->dirty = true;
+  b->gathered = -1;
   return CLAW_OK;
 }
 
@@ -910,6 +913,7 @@ int claw_batch_remove(claw_batch_t b, claw_t h) {
   absorb_ctrl(h, *h->h_ctrl);
   b->members.erase(it);
   b->dirty = true;
+  b->gathered = -1;
   return CLAW_OK;
 }
 
@@ -929,6 +933,20 @@ int claw_batch_member_clock(claw_batch_t b, claw_t h, claw_stats* st) {
   st->rejected += c.rejected;
   st->max_courant = c.max_courant;
   return c.status ? c.status : CLAW_OK;
+}
+
+int claw_batch_finished(claw_batch_t b, claw_t* out, int cap, int* n_out) {
+  if (!b || !n_out || (cap > 0 && !out)) return CLAW_E_INVAL;
+  int n = 0;
+  if (b->gathered == (int)b->members.size()) {
+    for (size_t k = 0; k < b->members.size(); ++k)
+      if (!b->h_ctrls[k].active) {
+        if (n < cap) out[n] = b->members[k];
+        ++n;
+      }
+  }
+  *n_out = std::min(n, cap);
+  return CLAW_OK;
 }
 
 int claw_batch_advance(claw_batch_t b, int attempts, int* n_active) {

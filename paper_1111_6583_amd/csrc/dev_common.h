@@ -8,25 +8,66 @@
 namespace claw {
 
 // ---------------------------------------------------------------------------
-// Lane shuffles inside one 64-lane wavefront.  x-neighbours of a cell live in
+// Lane shifts inside one 64-lane wavefront.  x-neighbours of a cell live in
 // adjacent lanes of the marching kernels; prev = value held by lane-1,
-// next = value held by lane+1 (edge lanes receive an unspecified value; they
-// are halo lanes whose results are discarded).
+// next = value held by lane+1.  They are DPP wavefront shifts (wave_shr:1 /
+// wave_shl:1, one VALU move per 32 bits, no LDS); edge lanes receive 0 and
+// are halo lanes whose results are discarded.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float shfl_prev(float x) { return __shfl_up(x, 1, kLanes); }
-__device__ __forceinline__ float shfl_next(float x) { return __shfl_down(x, 1, kLanes); }
-__device__ __forceinline__ double shfl_prev(double x) { return __shfl_up(x, 1, kLanes); }
-__device__ __forceinline__ double shfl_next(double x) { return __shfl_down(x, 1, kLanes); }
+constexpr int kDppWaveShr1 = 0x138;   // lane l reads lane l-1
+constexpr int kDppWaveShl1 = 0x130;   // lane l reads lane l+1
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ float shfl_prev(float x) { return dpp_f<kDppWaveShr1>(x); }
+__device__ __forceinline__ float shfl_next(float x) { return dpp_f<kDppWaveShl1>(x); }
+__device__ __forceinline__ double shfl_prev(double x) { return dpp_d<kDppWaveShr1>(x); }
+__device__ __forceinline__ double shfl_next(double x) { return dpp_d<kDppWaveShl1>(x); }
+
+// Maximum that keeps a NaN (so a non-finite state reaches the Courant check).
+template <typename R>
+__device__ __forceinline__ R max_nan(R a, R b) { return (b > a || b != b) ? b : a; }
 
 template <typename R>
 __device__ __forceinline__ R wave_max(R v) {
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    R o = __shfl_xor(v, off, kLanes);
-    v = o > v ? o : v;
-  }
+  for (int off = 32; off >= 1; off >>= 1) v = max_nan(v, __shfl_xor(v, off, kLanes));
   return v;
 }
+
+// ---------------------------------------------------------------------------
+// Reciprocal and reciprocal square root: the hardware estimate refined by two
+// Newton steps (FP64: relative error at the level of a few ulp, far inside
+// the 1e-12 parity bar; far cheaper than the IEEE-exact expansions).  FP32
+// uses the single-instruction estimates (about 1 ulp).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double frcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double frsq(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = y * __builtin_fma(-h, y * y, 1.5);
+  return y * __builtin_fma(-h, y * y, 1.5);
+}
+__device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
+// sqrt(x) for x > 0
+__device__ __forceinline__ double fsqrt(double x) { return x * frsq(x); }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // ---------------------------------------------------------------------------
 // Boundary conditions as index maps (ghost cells are never stored).  A ghost
@@ -161,7 +202,7 @@ __device__ inline bool ctrl_decide(Ctrl* c, double speed) {
 // host controller), and clears the slot and counter for the next launch.
 template <class Decide>
 __device__ inline void finish_workgroup(Ctrl* c, double local_max, int nblocks, Decide decide) {
-  local_max = wave_max(local_max);
+  local_max = wave_max(local_max);   // NaN-preserving: NaN bits compare above every finite speed
   if (threadIdx.x == 0) {
     atomicMax(&c->speed_bits, dbits(local_max));
     __threadfence();

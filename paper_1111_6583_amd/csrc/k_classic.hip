@@ -72,9 +72,11 @@ __global__ __launch_bounds__(kLanes) void k_classic2d(const GridDesc* __restrict
   const int lim = G.limiter, trans = G.transverse;
   const P phys(G);
 
+  using Cell = typename P::Cell;
   R smx = R(0), smy = R(0);
   // rolling state (see the pipeline above)
-  R q0[M], q1[M], a0[NA], a1[NA];
+  R q0[M], q1[M];
+  Cell c0{}, c1{};                                        // cell data of rows r-2, r-1
   R yW0[MW][M], ys0[MW];                                  // y-face r-5/2
   R yW1[MW][M], ys1[MW], yam1[M], yap1[M];                // y-face r-3/2
   Face yf1{};
@@ -85,25 +87,37 @@ __global__ __launch_bounds__(kLanes) void k_classic2d(const GridDesc* __restrict
     glo[k] = gtr_lo[k] = gtop2[k] = fxm2[k] = fxp2[k] = faL2[k] = faR2[k] = R(0);
   }
 #pragma unroll
-  for (int k = 0; k < NA; ++k) a0[k] = a1[k] = R(0);
-#pragma unroll
   for (int p = 0; p < MW; ++p) {
     ys0[p] = ys1[p] = R(0);
 #pragma unroll
     for (int k = 0; k < M; ++k) yW0[p][k] = yW1[p][k] = R(0);
   }
 
+  // row r+1 is loaded while row r is processed (software pipelining)
+  R qpre[M], apre[NA];
+  {
+    const AxisMap my = map_axis(j0 - 2, ny, G.bc[2], G.bc[3], H);
+    load_state<R, P>(qpre, q, plane, nx, mx, my, G);
+    load_aux<R, P>(apre, aux, plane, nx, mx, my);
+  }
   for (int r = j0 - 2; r <= j1 + 1; ++r) {
-    const AxisMap my = map_axis(r, ny, G.bc[2], G.bc[3], H);
     R qn[M], an[NA];
-    load_state<R, P>(qn, q, plane, nx, mx, my, G);
-    load_aux<R, P>(an, aux, plane, nx, mx, my);
+#pragma unroll
+    for (int k = 0; k < M; ++k) qn[k] = qpre[k];
+#pragma unroll
+    for (int k = 0; k < NA; ++k) an[k] = apre[k];
+    if (r + 1 <= j1 + 1) {
+      const AxisMap my = map_axis(r + 1, ny, G.bc[2], G.bc[3], H);
+      load_state<R, P>(qpre, q, plane, nx, mx, my, G);
+      load_aux<R, P>(apre, aux, plane, nx, mx, my);
+    }
+    const Cell cn = phys.cell(qn, an);
 
     // (A) y-face r-1/2
     R yW2[MW][M], ys2[MW], yam2[M], yap2[M];
     Face yf2{};
     if (r >= j0 - 1) {
-      phys.template normal<1>(q1, qn, a1, an, yW2, ys2, yam2, yap2, yf2);
+      phys.template normal<1>(q1, qn, c1, cn, yW2, ys2, yam2, yap2, yf2);
     } else {
 #pragma unroll
       for (int p = 0; p < MW; ++p) {
@@ -135,7 +149,7 @@ __global__ __launch_bounds__(kLanes) void k_classic2d(const GridDesc* __restrict
         }
         const R phi = limiter_phi(lim, ys1[p] > R(0) ? dlo : dhi, nrm);
         const R as = rabs(ys1[p]);
-        smy = rmax(smy, as);
+        smy = max_nan(smy, as);
         const R w = as * (R(1) - dtdy * as) * phi;
 #pragma unroll
         for (int k = 0; k < M; ++k)
@@ -153,24 +167,15 @@ __global__ __launch_bounds__(kLanes) void k_classic2d(const GridDesc* __restrict
           bmq[k] = yam1[k] + (trans == 2 ? cq[k] : R(0));
           bpq[k] = yap1[k] - (trans == 2 ? cq[k] : R(0));
         }
-        R alo[NA], ahi[NA];
-        // B^+ part lives in cell (i, r-1): materials of row r-1 at i-1, i, i+1
-#pragma unroll
-        for (int k = 0; k < NA; ++k) {
-          alo[k] = P::NA > 0 ? shfl_prev(a1[k]) : R(0);
-          ahi[k] = P::NA > 0 ? shfl_next(a1[k]) : R(0);
-        }
+        // B^+ part lives in cell (i, r-1): its x-neighbours' cell data
         R lm[M], lp[M];
-        phys.template transverse<1>(yf1, alo, a1, ahi, bpq, lm, lp);
+        phys.template transverse<1>(yf1, P::shfl_prev_cell(c1), c1, P::shfl_next_cell(c1), bpq,
+                                    lm, lp);
 #pragma unroll
         for (int k = 0; k < M; ++k) { faL1[k] = -nuy * lm[k]; faR1[k] = -nuy * lp[k]; }
         // B^- part lives in cell (i, r-2)
-#pragma unroll
-        for (int k = 0; k < NA; ++k) {
-          alo[k] = P::NA > 0 ? shfl_prev(a0[k]) : R(0);
-          ahi[k] = P::NA > 0 ? shfl_next(a0[k]) : R(0);
-        }
-        phys.template transverse<1>(yf1, alo, a0, ahi, bmq, lm, lp);
+        phys.template transverse<1>(yf1, P::shfl_prev_cell(c0), c0, P::shfl_next_cell(c0), bmq,
+                                    lm, lp);
 #pragma unroll
         for (int k = 0; k < M; ++k) { faL2[k] -= nuy * lm[k]; faR2[k] -= nuy * lp[k]; }
       }
@@ -181,14 +186,12 @@ __global__ __launch_bounds__(kLanes) void k_classic2d(const GridDesc* __restrict
 #pragma unroll
     for (int k = 0; k < M; ++k) fxm1[k] = fxp1[k] = gtop1[k] = gtr_cur[k] = R(0);
     if (r >= j0) {
-      R ql[M], al[NA];
+      R ql[M];
 #pragma unroll
       for (int k = 0; k < M; ++k) ql[k] = shfl_prev(q1[k]);
-#pragma unroll
-      for (int k = 0; k < NA; ++k) al[k] = P::NA > 0 ? shfl_prev(a1[k]) : R(0);
       R xW[MW][M], xs[MW], xam[M], xap[M];
       Face xf{};
-      phys.template normal<0>(ql, q1, al, a1, xW, xs, xam, xap, xf);
+      phys.template normal<0>(ql, q1, P::shfl_prev_cell(c1), c1, xW, xs, xam, xap, xf);
       const bool cfl_row = (r - 1 >= j0) && (r - 1 < j1);
       R cq[M];
 #pragma unroll
@@ -205,7 +208,7 @@ __global__ __launch_bounds__(kLanes) void k_classic2d(const GridDesc* __restrict
         const R dr = shfl_next(dl);   // the right neighbour's dot product with this face
         const R phi = limiter_phi(lim, xs[p] > R(0) ? dl : dr, nrm);
         const R as = rabs(xs[p]);
-        if (cfl_row && own_face) smx = rmax(smx, as);
+        if (cfl_row && own_face) smx = max_nan(smx, as);
         const R w = as * (R(1) - dtdx * as) * phi;
 #pragma unroll
         for (int k = 0; k < M; ++k)
@@ -228,11 +231,11 @@ __global__ __launch_bounds__(kLanes) void k_classic2d(const GridDesc* __restrict
         }
         // A^+ of face i-1/2 lives in cell (i, r-1); A^- of face i+1/2 too (from lane+1)
         R bm[M], bp[M], bm2[M], bp2[M], amn[M];
-        phys.template transverse<0>(xf, a0, a1, an, apq, bm, bp);
+        phys.template transverse<0>(xf, c0, c1, cn, apq, bm, bp);
 #pragma unroll
         for (int k = 0; k < M; ++k) amn[k] = shfl_next(amq[k]);
         const Face xfn = P::shfl_next_face(xf);
-        phys.template transverse<0>(xfn, a0, a1, an, amn, bm2, bp2);
+        phys.template transverse<0>(xfn, c0, c1, cn, amn, bm2, bp2);
 #pragma unroll
         for (int k = 0; k < M; ++k) {
           gbot1[k] = -nux * (bm[k] + bm2[k]);
@@ -287,8 +290,8 @@ __global__ __launch_bounds__(kLanes) void k_classic2d(const GridDesc* __restrict
       faL2[k] = faL1[k];
       faR2[k] = faR1[k];
     }
-#pragma unroll
-    for (int k = 0; k < NA; ++k) { a0[k] = a1[k]; a1[k] = an[k]; }
+    c0 = c1;
+    c1 = cn;
 #pragma unroll
     for (int p = 0; p < MW; ++p) {
       ys0[p] = ys1[p];
@@ -299,7 +302,7 @@ __global__ __launch_bounds__(kLanes) void k_classic2d(const GridDesc* __restrict
     yf1 = yf2;
   }
 
-  const double speed = own ? fmax((double)smx / G.dx, (double)smy / G.dy)
+  const double speed = own ? max_nan((double)smx / G.dx, (double)smy / G.dy)
                            : (own_face ? (double)smx / G.dx : 0.0);
   if (mode == kDeviceCtrl) {
     finish_workgroup(ctrl, speed, G.nblocks, [](Ctrl* c, double sp) {
@@ -343,14 +346,16 @@ __global__ __launch_bounds__(kLanes) void k_classic1d(const GridDesc* __restrict
   R* __restrict__ qo = (R*)G.q[src ^ 1];
   const R dtdx = (R)(dt / G.dx);
   const P phys(G);
+  using Cell = typename P::Cell;
   R qc[M], ql[M];
   R dummy[1] = {R(0)};
   load_state<R, P>(qc, q, (size_t)nx, nx, mx, my, G);
 #pragma unroll
   for (int k = 0; k < M; ++k) ql[k] = shfl_prev(qc[k]);
+  const Cell cc = phys.cell(qc, dummy);
   R W[MW][M], s[MW], am[M], ap[M];
   Face f{};
-  phys.template normal<0>(ql, qc, dummy, dummy, W, s, am, ap, f);
+  phys.template normal<0>(ql, qc, P::shfl_prev_cell(cc), cc, W, s, am, ap, f);
   R cq[M];
 #pragma unroll
   for (int k = 0; k < M; ++k) cq[k] = R(0);
@@ -366,7 +371,7 @@ __global__ __launch_bounds__(kLanes) void k_classic1d(const GridDesc* __restrict
     const R dr = shfl_next(dl);
     const R phi = limiter_phi(G.limiter, s[p] > R(0) ? dl : dr, nrm);
     const R as = rabs(s[p]);
-    smx = rmax(smx, as);
+    smx = max_nan(smx, as);
     const R w = as * (R(1) - dtdx * as) * phi;
 #pragma unroll
     for (int k = 0; k < M; ++k) cq[k] += w * W[p][k];
@@ -461,12 +466,14 @@ __global__ __launch_bounds__(kPersistThreads) void k_classic1d_run(const GridDes
       // faces f-1, f, f+1 (face f lies between cells f-1 and f)
       R c0[M], c1[M], c2[M], c3[M];
       cell(f - 2, c0); cell(f - 1, c1); cell(f, c2); cell(f + 1, c3);
+      const typename P::Cell e0 = phys.cell(c0, dummy), e1 = phys.cell(c1, dummy),
+                             e2 = phys.cell(c2, dummy), e3 = phys.cell(c3, dummy);
       R Wl[MW][M], sl[MW], aml[M], apl[M], W[MW][M], s[MW], am[M], ap[M], Wr[MW][M], sr[MW],
           amr[M], apr[M];
       Face fa{};
-      phys.template normal<0>(c0, c1, dummy, dummy, Wl, sl, aml, apl, fa);
-      phys.template normal<0>(c1, c2, dummy, dummy, W, s, am, ap, fa);
-      phys.template normal<0>(c2, c3, dummy, dummy, Wr, sr, amr, apr, fa);
+      phys.template normal<0>(c0, c1, e0, e1, Wl, sl, aml, apl, fa);
+      phys.template normal<0>(c1, c2, e1, e2, W, s, am, ap, fa);
+      phys.template normal<0>(c2, c3, e2, e3, Wr, sr, amr, apr, fa);
       R cq[M];
 #pragma unroll
       for (int k = 0; k < M; ++k) cq[k] = R(0);
@@ -481,7 +488,7 @@ __global__ __launch_bounds__(kPersistThreads) void k_classic1d_run(const GridDes
         }
         const R phi = limiter_phi(G.limiter, s[p] > R(0) ? dl : dr, nrm);
         const R as = rabs(s[p]);
-        smx = rmax(smx, as);
+        smx = max_nan(smx, as);
         const R w = as * (R(1) - dtdx * as) * phi;
 #pragma unroll
         for (int k = 0; k < M; ++k) cq[k] += w * W[p][k];
@@ -497,7 +504,7 @@ __global__ __launch_bounds__(kPersistThreads) void k_classic1d_run(const GridDes
     __syncthreads();
     if (tid == 0) {
       double m = 0.0;
-      for (int w = 0; w < (int)(blockDim.x / kLanes); ++w) m = fmax(m, red[w]);
+      for (int w = 0; w < (int)(blockDim.x / kLanes); ++w) m = max_nan(m, red[w]);
       s_ok = ctrl_decide(ctrl, m) ? 1 : 0;
       s_go = ctrl->active;
       s_dt = ctrl->dt_try;

@@ -124,13 +124,23 @@ __global__ __launch_bounds__(kLanes) void k_sharp2d(const GridDesc* __restrict__
 #pragma unroll
     for (int s = 0; s < 5; ++s) w[s][k] = R(0);
   }
+  // row r+1 is loaded while row r is processed (software pipelining)
+  R pre[M];
+  {
+    const AxisMap my = map_axis(j0 - 3, ny, G.bc[2], G.bc[3], H);
+    load_state<R, P>(pre, S, plane, nx, mx, my, G);
+  }
   for (int r = j0 - 3; r <= j1 + 2; ++r) {
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int k = 0; k < M; ++k) w[s][k] = w[s + 1][k];
-    const AxisMap my = map_axis(r, ny, G.bc[2], G.bc[3], H);
-    load_state<R, P>(w[4], S, plane, nx, mx, my, G);
+#pragma unroll
+    for (int k = 0; k < M; ++k) w[4][k] = pre[k];
+    if (r + 1 <= j1 + 2) {
+      const AxisMap my = map_axis(r + 1, ny, G.bc[2], G.bc[3], H);
+      load_state<R, P>(pre, S, plane, nx, mx, my, G);
+    }
     if (r < j0 + 1) continue;
     // y edge values of row c = r-2
     R qyl[M], qyr[M];
@@ -141,7 +151,7 @@ __global__ __launch_bounds__(kLanes) void k_sharp2d(const GridDesc* __restrict__
       // y-face flux at c-1/2
       R g_up[M];
       const R sy = phys.template flux<1>(qyl_prev, qyr, g_up);
-      smy = rmax(smy, sy);
+      smy = max_nan(smy, sy);
       if (r >= j0 + 3) {
         // row f = r-3 (window row 1) is complete: x edge values, x-face fluxes
         R xl[M], xr[M];
@@ -156,7 +166,7 @@ __global__ __launch_bounds__(kLanes) void k_sharp2d(const GridDesc* __restrict__
 #pragma unroll
         for (int k = 0; k < M; ++k) ql[k] = shfl_prev(xl[k]);
         const R sx = phys.template flux<0>(ql, xr, F);
-        if (own_face) smx = rmax(smx, sx);
+        if (own_face) smx = max_nan(smx, sx);
         R Lv[M], Sc[M];
 #pragma unroll
         for (int k = 0; k < M; ++k) {
@@ -172,7 +182,7 @@ __global__ __launch_bounds__(kLanes) void k_sharp2d(const GridDesc* __restrict__
 #pragma unroll
     for (int k = 0; k < M; ++k) qyl_prev[k] = qyl[k];
   }
-  const double speed = own ? fmax((double)smx * (1.0 / G.dx), (double)smy * (1.0 / G.dy))
+  const double speed = own ? max_nan((double)smx * (1.0 / G.dx), (double)smy * (1.0 / G.dy))
                            : (own_face ? (double)smx * (1.0 / G.dx) : 0.0);
   stage_finish<STAGE>(ctrl, mode, speed, G.nblocks);
 }

@@ -1,6 +1,6 @@
 // phys.h -- Riemann solvers, transverse solvers and numerical fluxes for the
 // gfx950 kernels (the problem-specific kernels of the paper's Section 2.1:
-// "the only specialized code required ... is the Riemann solver").
+// the Riemann solver is the only problem-specific part of the algorithms).
 //
 // Each classic policy P provides
 //   M, MW, NA                      equations, waves, aux fields
@@ -8,15 +8,19 @@
 //                                  face normal to D (lets the marching kernels
 //                                  skip known-zero components)
 //   odd(d, k)                      sign flip of component k at a wall normal to d
+//   Cell, cell(q, aux)             per-cell quantities computed once per loaded
+//                                  cell and shared by its four faces
+//                                  (velocities, celerity, material speeds)
 //   Face                           data of a normal solve reused by the
 //                                  transverse split (e.g. Roe averages)
-//   normal<D>(ql, qr, al, ar, W, s, amdq, apdq, face)
-//   transverse<D>(face, a_lo, a_c, a_hi, asdq, bm, bp)
+//   normal<D>(ql, qr, cl, cr, W, s, amdq, apdq, face)
+//   transverse<D>(face, c_lo, c_c, c_hi, asdq, bm, bp)
 //                                  split a fluctuation produced at a face
-//                                  normal to D, living in the cell with aux
-//                                  a_c, into the parts moving toward lower
-//                                  (bm) and higher (bp) index in the other
-//                                  direction
+//                                  normal to D, living in cell c_c, into the
+//                                  parts moving toward lower (bm) and higher
+//                                  (bp) index in the other direction; c_lo /
+//                                  c_hi are that cell's neighbours there
+//   shfl_prev_cell / shfl_next_cell / shfl_next_face   lane shifts of these
 //   cell_speed(q, a, rdx, rdy)     largest characteristic speed/spacing of a
 //                                  cell (a-priori first step)
 //
@@ -31,8 +35,6 @@ namespace claw {
 template <typename R> __device__ __forceinline__ R rmin(R a, R b) { return a < b ? a : b; }
 template <typename R> __device__ __forceinline__ R rmax(R a, R b) { return a > b ? a : b; }
 template <typename R> __device__ __forceinline__ R rabs(R a) { return a < R(0) ? -a : a; }
-__device__ __forceinline__ double rsqrt_(double x) { return sqrt(x); }
-__device__ __forceinline__ float rsqrt_(float x) { return sqrtf(x); }
 
 // ---------------------------------------------------------------------------
 // Scalar advection q_t + u q_x + v q_y = 0 (test problem: exact translation,
@@ -41,16 +43,21 @@ __device__ __forceinline__ float rsqrt_(float x) { return sqrtf(x); }
 template <typename R, int NDIM>
 struct Advection {
   static constexpr int M = 1, MW = 1, NA = 0;
+  struct Cell {};
   struct Face {};
-  __device__ __forceinline__ static Face shfl_next_face(const Face& f) { return f; }
   R u, v;
   __device__ explicit Advection(const GridDesc& G) : u((R)G.pd[0]), v((R)G.pd[1]) {}
   template <int D> static constexpr bool nz(int, int) { return true; }
   static constexpr bool odd(int, int) { return false; }
+  __device__ __forceinline__ Cell cell(const R*, const R*) const { return Cell{}; }
+  __device__ __forceinline__ static Cell shfl_prev_cell(const Cell& c) { return c; }
+  __device__ __forceinline__ static Cell shfl_next_cell(const Cell& c) { return c; }
+  __device__ __forceinline__ static Face shfl_next_face(const Face& f) { return f; }
 
   template <int D>
-  __device__ __forceinline__ void normal(const R* ql, const R* qr, const R*, const R*, R (&W)[MW][M],
-                                         R (&s)[MW], R (&am)[M], R (&ap)[M], Face&) const {
+  __device__ __forceinline__ void normal(const R* ql, const R* qr, const Cell&, const Cell&,
+                                         R (&W)[MW][M], R (&s)[MW], R (&am)[M], R (&ap)[M],
+                                         Face&) const {
     const R un = D == 0 ? u : v;
     const R dq = qr[0] - ql[0];
     W[0][0] = dq;
@@ -59,7 +66,7 @@ struct Advection {
     ap[0] = rmax(un, R(0)) * dq;
   }
   template <int D>
-  __device__ __forceinline__ void transverse(const Face&, const R*, const R*, const R*,
+  __device__ __forceinline__ void transverse(const Face&, const Cell&, const Cell&, const Cell&,
                                              const R* asdq, R* bm, R* bp) const {
     const R vt = D == 0 ? v : u;
     bm[0] = rmin(vt, R(0)) * asdq[0];
@@ -74,10 +81,10 @@ struct Advection {
 
 // ---------------------------------------------------------------------------
 // Shallow water, Roe linearisation with an optional Harten-Hyman entropy fix
-// (the "Roe solver with an entropy fix" of the paper's Section 6; formulas
-// as in LeVeque 2002, ch. 15).  q = (h, hu) in 1D, (h, hu, hv) in 2D.
-// Families: 0 = left acoustic (u-c), [1 = shear (u), 2D only], last =
-// right acoustic (u+c).
+// (the Roe solver with an entropy fix of the paper's Section 6; formulas as
+// in LeVeque 2002, ch. 15).  q = (h, hu) in 1D, (h, hu, hv) in 2D.  Families:
+// 0 = left acoustic (u-c), [1 = shear (u), 2D only], last = right acoustic
+// (u+c).
 // ---------------------------------------------------------------------------
 template <typename R, int NDIM>
 struct ShallowWater {
@@ -85,15 +92,16 @@ struct ShallowWater {
   static constexpr int MW = M;
   static constexpr int NA = 0;
   static constexpr int LAST = MW - 1;
-  struct Face {
-    R u, v, c;   // Roe-averaged normal velocity, tangential velocity, celerity
+  struct Cell {
+    R u, v, sh, c;   // velocities, sqrt(h), celerity sqrt(g h)
   };
-  __device__ __forceinline__ static Face shfl_next_face(const Face& f) {
-    return Face{shfl_next(f.u), shfl_next(f.v), shfl_next(f.c)};
-  }
-  R g;
+  struct Face {
+    R u, v, c, i2c;  // Roe-averaged normal / tangential velocity, celerity, 1/(2c)
+  };
+  R g, sg;
   int efix;
-  __device__ explicit ShallowWater(const GridDesc& G) : g((R)G.pd[0]), efix(G.efix) {}
+  __device__ explicit ShallowWater(const GridDesc& G)
+      : g((R)G.pd[0]), sg((R)sqrt(G.pd[0])), efix(G.efix) {}
 
   // zero pattern: acoustic waves (1, u -/+ c, v); shear wave: tangential only
   template <int D>
@@ -103,27 +111,49 @@ struct ShallowWater {
   }
   static constexpr bool odd(int d, int k) { return k == 1 + d; }
 
+  __device__ __forceinline__ Cell cell(const R* q, const R*) const {
+    const R rs = frsq(q[0]);          // 1/sqrt(h)
+    const R rh = rs * rs;             // 1/h
+    Cell c;
+    c.sh = q[0] * rs;
+    c.u = q[1] * rh;
+    c.v = NDIM == 2 ? q[2] * rh : R(0);
+    c.c = sg * c.sh;
+    return c;
+  }
+  __device__ __forceinline__ static Cell shfl_prev_cell(const Cell& c) {
+    return Cell{shfl_prev(c.u), NDIM == 2 ? shfl_prev(c.v) : R(0), shfl_prev(c.sh), shfl_prev(c.c)};
+  }
+  __device__ __forceinline__ static Cell shfl_next_cell(const Cell& c) {
+    return Cell{shfl_next(c.u), NDIM == 2 ? shfl_next(c.v) : R(0), shfl_next(c.sh), shfl_next(c.c)};
+  }
+  __device__ __forceinline__ static Face shfl_next_face(const Face& f) {
+    return Face{shfl_next(f.u), shfl_next(f.v), shfl_next(f.c), shfl_next(f.i2c)};
+  }
+
   template <int D>
-  __device__ __forceinline__ void normal(const R* ql, const R* qr, const R*, const R*,
+  __device__ __forceinline__ void normal(const R* ql, const R* qr, const Cell& cl, const Cell& cr,
                                          R (&W)[MW][M], R (&s)[MW], R (&am)[M], R (&ap)[M],
                                          Face& f) const {
     constexpr int n = 1 + D;      // normal momentum
     constexpr int t = 2 - D;      // tangential momentum (2D)
     const R hl = ql[0], hr = qr[0];
-    const R sl = rsqrt_(hl), sr = rsqrt_(hr);
-    const R unl = ql[n] / hl, unr = qr[n] / hr;
-    const R den = sl + sr;
-    f.u = (sl * unl + sr * unr) / den;
+    const R unl = D == 0 ? cl.u : cl.v, unr = D == 0 ? cr.u : cr.v;
+    const R rden = frcp(cl.sh + cr.sh);
+    f.u = (cl.sh * unl + cr.sh * unr) * rden;
     if constexpr (NDIM == 2) {
-      const R utl = ql[t] / hl, utr = qr[t] / hr;
-      f.v = (sl * utl + sr * utr) / den;
+      const R utl = D == 0 ? cl.v : cl.u, utr = D == 0 ? cr.v : cr.u;
+      f.v = (cl.sh * utl + cr.sh * utr) * rden;
     } else {
       f.v = R(0);
     }
-    f.c = rsqrt_(g * (R(0.5) * (hl + hr)));
+    const R c2 = g * (R(0.5) * (hl + hr));
+    const R rs = frsq(c2);
+    f.c = c2 * rs;
+    f.i2c = R(0.5) * rs;
     const R d0 = qr[0] - ql[0], dn = qr[n] - ql[n];
-    const R a1 = ((f.u + f.c) * d0 - dn) / (R(2) * f.c);
-    const R a3 = (-(f.u - f.c) * d0 + dn) / (R(2) * f.c);
+    const R a1 = ((f.u + f.c) * d0 - dn) * f.i2c;
+    const R a3 = (-(f.u - f.c) * d0 + dn) * f.i2c;
     const R s1 = f.u - f.c, s3 = f.u + f.c;
     W[0][0] = a1; W[0][n] = a1 * s1;
     W[LAST][0] = a3; W[LAST][n] = a3 * s3;
@@ -136,23 +166,31 @@ struct ShallowWater {
       W[1][t] = (qr[t] - ql[t]) - f.v * d0;
       s[1] = f.u;
     }
-    // A^- dQ: sum of coef_p W_p
     R coef[MW];
+#pragma unroll
+    for (int p = 0; p < MW; ++p) coef[p] = rmin(s[p], R(0));
     if (efix) {
-      {  // first family: transonic if the speed left of the wave < 0 < the speed right of it
-        const R lam_l = unl - rsqrt_(g * hl);
+      // Harten-Hyman: an acoustic wave whose left-side characteristic speed is
+      // negative and right-side one positive is a transonic rarefaction; its
+      // contribution to A^-dQ becomes lam_l (lam_r - s) / (lam_r - lam_l) W.
+      // The expensive right/left speed is formed only when a cheap exact test
+      // (u_m > c_m  <=>  hu_m > 0 and hu_m^2 > g h_m^3, for h_m > 0) says the
+      // wave is transonic; the coefficient is continuous where the test flips.
+      {
+        const R lam_l = unl - cl.c;
         const R hm = hl + W[0][0], hum = ql[n] + W[0][n];
-        const R lam_r = hum / hm - rsqrt_(g * hm);
-        coef[0] = (lam_l < R(0) && R(0) < lam_r) ? lam_l * (lam_r - s1) / (lam_r - lam_l)
-                                                 : rmin(s1, R(0));
+        if (lam_l < R(0) && hm > R(0) && hum > R(0) && hum * hum > g * hm * hm * hm) {
+          const R lam_r = hum * frcp(hm) - fsqrt(g * hm);
+          if (R(0) < lam_r) coef[0] = lam_l * (lam_r - s1) * frcp(lam_r - lam_l);
+        }
       }
-      if constexpr (NDIM == 2) coef[1] = rmin(s[1], R(0));
-      {  // last family
+      {
+        const R lam_r = unr + cr.c;
         const R hm = hr - W[LAST][0], hum = qr[n] - W[LAST][n];
-        const R lam_l = hum / hm + rsqrt_(g * hm);
-        const R lam_r = unr + rsqrt_(g * hr);
-        coef[LAST] = (lam_l < R(0) && R(0) < lam_r) ? lam_l * (lam_r - s3) / (lam_r - lam_l)
-                                                    : rmin(s3, R(0));
+        if (lam_r > R(0) && hm > R(0) && hum < R(0) && hum * hum > g * hm * hm * hm) {
+          const R lam_l = hum * frcp(hm) + fsqrt(g * hm);
+          if (lam_l < R(0)) coef[LAST] = lam_l * (lam_r - s3) * frcp(lam_r - lam_l);
+        }
       }
 #pragma unroll
       for (int k = 0; k < M; ++k) {
@@ -173,7 +211,7 @@ struct ShallowWater {
 #pragma unroll
         for (int p = 0; p < MW; ++p) {
           if (!nz<D>(p, k)) continue;
-          a += rmin(s[p], R(0)) * W[p][k];
+          a += coef[p] * W[p][k];
           b += rmax(s[p], R(0)) * W[p][k];
         }
         am[k] = a;
@@ -186,13 +224,12 @@ struct ShallowWater {
   // speeds v-c, v, v+c; eigenvectors (1, u, v-c), e_n, (1, u, v+c) in
   // (depth, normal, tangential) ordering of the face.
   template <int D>
-  __device__ __forceinline__ void transverse(const Face& f, const R*, const R*, const R*,
+  __device__ __forceinline__ void transverse(const Face& f, const Cell&, const Cell&, const Cell&,
                                              const R* d, R* bm, R* bp) const {
     if constexpr (NDIM == 2) {
       constexpr int n = 1 + D, t = 2 - D;
-      const R i2c = R(1) / (R(2) * f.c);
-      const R b1 = ((f.v + f.c) * d[0] - d[t]) * i2c;
-      const R b3 = (-(f.v - f.c) * d[0] + d[t]) * i2c;
+      const R b1 = ((f.v + f.c) * d[0] - d[t]) * f.i2c;
+      const R b3 = (-(f.v - f.c) * d[0] + d[t]) * f.i2c;
       const R b2 = d[n] - f.u * d[0];
       const R l1 = f.v - f.c, l2 = f.v, l3 = f.v + f.c;
       const R m1 = rmin(l1, R(0)) * b1, m2 = rmin(l2, R(0)) * b2, m3 = rmin(l3, R(0)) * b3;
@@ -226,11 +263,10 @@ struct ShallowWater {
 template <typename R>
 struct Elastic {
   static constexpr int M = 5, MW = 4, NA = 3;
-  struct Face {};
-  __device__ __forceinline__ static Face shfl_next_face(const Face& f) { return f; }
-  struct Mat {
-    R lam, mu, a, cp, cs;
+  struct Cell {
+    R lam, mu, a, cp, cs;   // Lame parameters, lambda + 2 mu, P and S speeds
   };
+  struct Face {};
   __device__ explicit Elastic(const GridDesc&) {}
   // index map for direction D: normal stress, other normal stress, shear,
   // normal velocity, tangential velocity
@@ -245,31 +281,38 @@ struct Elastic {
   }
   static constexpr bool odd(int d, int k) { return k == 2 || k == 3 + d; }
 
-  __device__ __forceinline__ static Mat mat(const R* a) {
-    Mat m;
+  __device__ __forceinline__ Cell cell(const R*, const R* a) const {
+    Cell m;
     m.lam = a[1];
     m.mu = a[2];
     m.a = a[1] + R(2) * a[2];
-    m.cp = rsqrt_(m.a / a[0]);
-    m.cs = rsqrt_(a[2] / a[0]);
+    const R ir = frcp(a[0]);
+    m.cp = fsqrt(m.a * ir);
+    m.cs = fsqrt(a[2] * ir);
     return m;
   }
+  __device__ __forceinline__ static Cell shfl_prev_cell(const Cell& c) {
+    return Cell{shfl_prev(c.lam), shfl_prev(c.mu), shfl_prev(c.a), shfl_prev(c.cp), shfl_prev(c.cs)};
+  }
+  __device__ __forceinline__ static Cell shfl_next_cell(const Cell& c) {
+    return Cell{shfl_next(c.lam), shfl_next(c.mu), shfl_next(c.a), shfl_next(c.cp), shfl_next(c.cs)};
+  }
+  __device__ __forceinline__ static Face shfl_next_face(const Face& f) { return f; }
 
   template <int D>
-  __device__ __forceinline__ void normal(const R* ql, const R* qr, const R* al, const R* ar,
+  __device__ __forceinline__ void normal(const R* ql, const R* qr, const Cell& L, const Cell& Rm,
                                          R (&W)[MW][M], R (&s)[MW], R (&am)[M], R (&ap)[M],
                                          Face&) const {
     constexpr int sn = SN(D), so = SO(D), vn = VN(D), vt = VT(D);
-    const Mat L = mat(al), Rm = mat(ar);
     R dq[M];
 #pragma unroll
     for (int k = 0; k < M; ++k) dq[k] = qr[k] - ql[k];
-    const R D1 = L.a * Rm.cp + Rm.a * L.cp;
-    const R a1 = (Rm.cp * dq[sn] + Rm.a * dq[vn]) / D1;
-    const R a4 = (L.cp * dq[sn] - L.a * dq[vn]) / D1;
-    const R Ds = L.mu * Rm.cs + Rm.mu * L.cs;
-    const R a2 = (Rm.cs * dq[SH] + Rm.mu * dq[vt]) / Ds;
-    const R a3 = (L.cs * dq[SH] - L.mu * dq[vt]) / Ds;
+    const R iD1 = frcp(L.a * Rm.cp + Rm.a * L.cp);
+    const R a1 = (Rm.cp * dq[sn] + Rm.a * dq[vn]) * iD1;
+    const R a4 = (L.cp * dq[sn] - L.a * dq[vn]) * iD1;
+    const R iDs = frcp(L.mu * Rm.cs + Rm.mu * L.cs);
+    const R a2 = (Rm.cs * dq[SH] + Rm.mu * dq[vt]) * iDs;
+    const R a3 = (L.cs * dq[SH] - L.mu * dq[vt]) * iDs;
 #pragma unroll
     for (int p = 0; p < MW; ++p)
 #pragma unroll
@@ -286,18 +329,17 @@ struct Elastic {
     }
   }
 
-  // Transverse split of a fluctuation living in a cell with materials
-  // a_lo (lower neighbour in the transverse direction), a_c, a_hi.
+  // Transverse split of a fluctuation living in cell C with neighbours Mm
+  // (lower) and P (upper) in the transverse direction.
   template <int D>
-  __device__ __forceinline__ void transverse(const Face&, const R* a_lo, const R* a_c,
-                                             const R* a_hi, const R* d, R* bm, R* bp) const {
+  __device__ __forceinline__ void transverse(const Face&, const Cell& Mm, const Cell& C,
+                                             const Cell& P, const R* d, R* bm, R* bp) const {
     constexpr int T = 1 - D;
     constexpr int sn = SN(T), so = SO(T), vn = VN(T), vt = VT(T);
-    const Mat Mm = mat(a_lo), C = mat(a_c), P = mat(a_hi);
-    const R b1 = (C.cp * d[sn] + C.a * d[vn]) / (Mm.a * C.cp + C.a * Mm.cp);
-    const R b2 = (C.cs * d[SH] + C.mu * d[vt]) / (Mm.mu * C.cs + C.mu * Mm.cs);
-    const R b3 = (C.cs * d[SH] - C.mu * d[vt]) / (C.mu * P.cs + P.mu * C.cs);
-    const R b4 = (C.cp * d[sn] - C.a * d[vn]) / (C.a * P.cp + P.a * C.cp);
+    const R b1 = (C.cp * d[sn] + C.a * d[vn]) * frcp(Mm.a * C.cp + C.a * Mm.cp);
+    const R b2 = (C.cs * d[SH] + C.mu * d[vt]) * frcp(Mm.mu * C.cs + C.mu * Mm.cs);
+    const R b3 = (C.cs * d[SH] - C.mu * d[vt]) * frcp(C.mu * P.cs + P.mu * C.cs);
+    const R b4 = (C.cp * d[sn] - C.a * d[vn]) * frcp(C.a * P.cp + P.a * C.cp);
     bm[sn] = -Mm.cp * b1 * Mm.a;
     bm[so] = -Mm.cp * b1 * Mm.lam;
     bm[vn] = -Mm.cp * b1 * Mm.cp;
@@ -317,17 +359,23 @@ struct Elastic {
 };
 
 // ---------------------------------------------------------------------------
-// Wave limiters (LeVeque 2002, ch. 6): phi(theta) for theta = num/den, den > 0.
+// Wave limiters (LeVeque 2002, ch. 6): phi(theta) for theta = num/den.
+// den = W.W.  A wave whose W.W is below kTinyNorm (|W| < 1e-100 in FP64,
+// 1e-15 in FP32) is limited to zero: its correction is far below rounding of
+// any state value, and the reciprocal estimate of a subnormal norm would not
+// be finite.
 // ---------------------------------------------------------------------------
+template <typename R> struct TinyNorm;
+template <> struct TinyNorm<double> { static constexpr double v = 1e-200; };
+template <> struct TinyNorm<float> { static constexpr float v = 1e-30f; };
+
 template <typename R>
 __device__ __forceinline__ R limiter_phi(int lim, R num, R den) {
-  if (!(den > R(0))) return R(0);
-  const R th = num / den;
-  switch (lim) {
-    case 1: return rmax(R(0), rmin(R(1), th));
-    case 2: return rmax(R(0), rmin(rmin((R(1) + th) * R(0.5), R(2)), R(2) * th));
-    default: return R(1);
-  }
+  if (lim == 0) return R(1);
+  if (!(den > TinyNorm<R>::v)) return R(0);
+  const R th = num * frcp(den);
+  if (lim == 1) return rmax(R(0), rmin(R(1), th));
+  return rmax(R(0), rmin(rmin((R(1) + th) * R(0.5), R(2)), R(2) * th));
 }
 
 // ===========================================================================
@@ -367,20 +415,22 @@ struct EulerHLLE {
   __device__ __forceinline__ R flux(const R* ql, const R* qr, R* F) const {
     constexpr int E = M - 1;
     const R rl = ql[0], rr = qr[0];
-    const R irl = R(1) / rl, irr = R(1) / rr;
+    // 1/sqrt(rho) gives sqrt(rho) and 1/rho together
+    const R isl = frsq(rl), isr = frsq(rr);
+    const R wl = rl * isl, wr = rr * isr;
+    const R irl = isl * isl, irr = isr * isr;
     const R ul = ql[1] * irl, ur = qr[1] * irr;
     const R vl = NDIM == 2 ? ql[2] * irl : R(0);
     const R vr = NDIM == 2 ? qr[2] * irr : R(0);
     const R pl = gm1 * (ql[E] - R(0.5) * rl * (ul * ul + vl * vl));
     const R pr = gm1 * (qr[E] - R(0.5) * rr * (ur * ur + vr * vr));
-    const R cl = rsqrt_(gamma * pl * irl), cr = rsqrt_(gamma * pr * irr);
+    const R cl = fsqrt(gamma * pl * irl), cr = fsqrt(gamma * pr * irr);
     const R unl = D == 0 ? ul : vl, unr = D == 0 ? ur : vr;
-    const R wl = rsqrt_(rl), wr = rsqrt_(rr);
-    const R iw = R(1) / (wl + wr);
+    const R iw = frcp(wl + wr);
     const R ut = (wl * ul + wr * ur) * iw;
     const R vt = (wl * vl + wr * vr) * iw;
     const R Ht = (wl * ((ql[E] + pl) * irl) + wr * ((qr[E] + pr) * irr)) * iw;
-    const R ct = rsqrt_(gm1 * (Ht - R(0.5) * (ut * ut + vt * vt)));
+    const R ct = fsqrt(gm1 * (Ht - R(0.5) * (ut * ut + vt * vt)));
     const R unt = D == 0 ? ut : vt;
     const R s1 = rmin(unl - cl, unt - ct);
     const R s2 = rmax(unr + cr, unt + ct);
@@ -404,12 +454,12 @@ struct EulerHLLE {
 #pragma unroll
       for (int k = 0; k < M; ++k) F[k] = fr[k];
     } else {
-      const R inv = R(1) / (s2 - s1);
+      const R inv = frcp(s2 - s1);
       const R s12 = s1 * s2;
 #pragma unroll
       for (int k = 0; k < M; ++k) F[k] = (s2 * fl[k] - s1 * fr[k] + s12 * (qr[k] - ql[k])) * inv;
     }
-    return rmax(rabs(s1), rabs(s2));
+    return max_nan(rabs(s1), rabs(s2));
   }
 
   __device__ __forceinline__ double cell_speed(const R* q, const R*, double rdx, double rdy) const {
@@ -425,34 +475,32 @@ struct EulerHLLE {
 
 // WENO5 (Jiang-Shu), component-wise: from the five cell averages centred on
 // cell i, the value at its right edge (qL, the left state of face i+1/2) and
-// at its left edge (qR, the right state of face i-1/2).  The three
-// smoothness indicators are shared by both edges; the weights of each edge
-// are normalised with one division.
+// at its left edge (qR, the right state of face i-1/2).  The smoothness
+// indicators are shared by both edges.  With D_k = (eps + beta_k)^2 the
+// normalised weights d_k/D_k / sum_j d_j/D_j equal d_k P_k / sum_j d_j P_j,
+// P_k = prod_{j != k} D_j, so each edge needs one reciprocal.
 template <typename R>
 __device__ __forceinline__ void weno5_edges(R vm2, R vm1, R v0, R vp1, R vp2, R eps, R& qL, R& qR) {
   const R t0 = vm2 - R(2) * vm1 + v0, u0 = vm2 - R(4) * vm1 + R(3) * v0;
   const R t1 = vm1 - R(2) * v0 + vp1, u1 = vm1 - vp1;
   const R t2 = v0 - R(2) * vp1 + vp2, u2 = R(3) * v0 - R(4) * vp1 + vp2;
-  const R b0 = R(13.0 / 12.0) * t0 * t0 + R(0.25) * u0 * u0;
-  const R b1 = R(13.0 / 12.0) * t1 * t1 + R(0.25) * u1 * u1;
-  const R b2 = R(13.0 / 12.0) * t2 * t2 + R(0.25) * u2 * u2;
-  const R e0 = R(1) / ((eps + b0) * (eps + b0));
-  const R e1 = R(1) / ((eps + b1) * (eps + b1));
-  const R e2 = R(1) / ((eps + b2) * (eps + b2));
-  {
-    const R a0 = R(0.1) * e0, a1 = R(0.6) * e1, a2 = R(0.3) * e2;
-    const R p0 = (R(2) * vm2 - R(7) * vm1 + R(11) * v0) / R(6);
-    const R p1 = (-vm1 + R(5) * v0 + R(2) * vp1) / R(6);
-    const R p2 = (R(2) * v0 + R(5) * vp1 - vp2) / R(6);
-    qL = (a0 * p0 + a1 * p1 + a2 * p2) / (a0 + a1 + a2);
-  }
-  {
-    const R a0 = R(0.3) * e0, a1 = R(0.6) * e1, a2 = R(0.1) * e2;
-    const R p0 = (-vm2 + R(5) * vm1 + R(2) * v0) / R(6);
-    const R p1 = (R(2) * vm1 + R(5) * v0 - vp1) / R(6);
-    const R p2 = (R(11) * v0 - R(7) * vp1 + R(2) * vp2) / R(6);
-    qR = (a0 * p0 + a1 * p1 + a2 * p2) / (a0 + a1 + a2);
-  }
+  const R c13 = R(13.0 / 12.0);
+  const R e0 = eps + (c13 * t0 * t0 + R(0.25) * u0 * u0);
+  const R e1 = eps + (c13 * t1 * t1 + R(0.25) * u1 * u1);
+  const R e2 = eps + (c13 * t2 * t2 + R(0.25) * u2 * u2);
+  const R D0 = e0 * e0, D1 = e1 * e1, D2 = e2 * e2;
+  const R P0 = D1 * D2, P1 = D0 * D2, P2 = D0 * D1;
+  // candidate edge values times 6
+  const R l0 = R(2) * vm2 - R(7) * vm1 + R(11) * v0;
+  const R l1 = -vm1 + R(5) * v0 + R(2) * vp1;
+  const R l2 = R(2) * v0 + R(5) * vp1 - vp2;
+  const R r0 = -vm2 + R(5) * vm1 + R(2) * v0;
+  const R r1 = R(2) * vm1 + R(5) * v0 - vp1;
+  const R r2 = R(11) * v0 - R(7) * vp1 + R(2) * vp2;
+  const R aL0 = R(0.1) * P0, aL1 = R(0.6) * P1, aL2 = R(0.3) * P2;
+  const R aR0 = R(0.3) * P0, aR1 = R(0.6) * P1, aR2 = R(0.1) * P2;
+  qL = (aL0 * l0 + aL1 * l1 + aL2 * l2) * (R(1.0 / 6.0) * frcp(aL0 + aL1 + aL2));
+  qR = (aR0 * r0 + aR1 * r1 + aR2 * r2) * (R(1.0 / 6.0) * frcp(aR0 + aR1 + aR2));
 }
 
 }  // namespace claw

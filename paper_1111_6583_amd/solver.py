@@ -92,8 +92,12 @@ class Solver:
                                              int(max_steps), C.byref(st))
         else:
             rc = self.lib.claw_advance(self.h, float(t_end), int(max_steps), C.byref(st))
+        out = st.as_dict()
+        out["reached"] = rc != -8
+        if rc == -8 and max_steps > 0:
+            return out          # stopped after max_steps attempts, as asked
         check(rc, "claw_advance")
-        return st.as_dict()
+        return out
 
     def totals(self):
         out = np.zeros(self.m)
@@ -173,6 +177,15 @@ class Batch:
         n = C.c_int(0)
         check(self.lib.claw_batch_advance(self.h, int(attempts), C.byref(n)), "claw_batch_advance")
         return n.value
+
+    def finished(self):
+        """Members whose controller stopped as of the last advance()."""
+        cap = max(1, len(self.members))
+        arr = (C.c_void_p * cap)()
+        n = C.c_int(0)
+        check(self.lib.claw_batch_finished(self.h, arr, cap, C.byref(n)), "claw_batch_finished")
+        done = {arr[k] for k in range(n.value)}
+        return [s for s in self.members if s.h.value in done]
 
     def member_clock(self, solver: Solver) -> dict:
         st = ClawStats()

@@ -174,9 +174,14 @@ def layered_elastic(n=2048, ny=None, layers=16, seed=1, width=0.05, amplitude=1.
 # Shallow-water hump (serving requests and smooth tests):
 # h = 1 + A exp(-|x-x0|^2/w^2) on [0,1]^2, hu = hv = 0, g = 1.
 # ---------------------------------------------------------------------------
-def sw_hump(n, amplitude=0.5, width=0.1, x0=(0.5, 0.5), **kw):
-    spec = _base(2, (n, n), (0.0, 0.0), (1.0, 1.0), "sw_roe", entropy_fix=1,
+def sw_hump_spec(n, **kw):
+    """Problem spec of an N x N shallow-water hump on [0,1]^2 (no state)."""
+    return _base(2, (n, n), (0.0, 0.0), (1.0, 1.0), "sw_roe", entropy_fix=1,
                  problem_data=[1.0], transverse=2, cfl_desired=0.9, cfl_max=1.0, **kw)
+
+
+def sw_hump(n, amplitude=0.5, width=0.1, x0=(0.5, 0.5), **kw):
+    spec = sw_hump_spec(n, **kw)
     x, y = centers(spec)
     X, Y = np.meshgrid(x, y)
     q = np.zeros((3, n, n))
