@@ -215,7 +215,8 @@ int claw_destroy(claw_t h);
 /* ---------------------------------------------------------------------------
  * Batching: one launch advances every member grid by one attempt, each with
  * its own clock, dt controller and t_end.  Members must be classic 2D
- * handles with the same riemann solver and precision, created on the same
+ * handles with the same riemann solver, limiter, transverse mode and
+ * precision, created on the same
  * device; each keeps its own workspace.  The batch itself needs
  * claw_batch_workspace_bytes(max_grids) device bytes from the caller.
  * ------------------------------------------------------------------------- */

@@ -19,7 +19,7 @@
 #include "claw_internal.h"
 
 namespace claw {
-hipError_t launch_classic2d(int riemann, int fp32, int nblocks, hipStream_t st,
+hipError_t launch_classic2d(int riemann, int fp32, int lim, int trans, int nblocks, hipStream_t st,
                             const GridDesc* d_grids, const int* d_bstart, int ngrids, int mode,
                             double dt, int src);
 hipError_t launch_classic1d(int riemann, int fp32, int nblocks, hipStream_t st,
@@ -140,7 +140,7 @@ struct claw_batch {
   std::vector<claw_t> members;
   std::vector<int> bstart;
   bool dirty = true;
-  int riemann = 0, fp32 = 0;
+  int riemann = 0, fp32 = 0, limiter = 0, transverse = 0;
   hipGraphExec_t graph = nullptr;
   int graph_k = 0;
   Ctrl* h_ctrls = nullptr;
@@ -224,7 +224,7 @@ int launch_attempt_host(claw_t h, double dt, bool stage1_only) {
   const GridDesc& g = h->hg;
   if (h->cfg.scheme == CLAW_CLASSIC) {
     if (h->cfg.ndim == 2)
-      HIPCHK(launch_classic2d(h->cfg.riemann, h->fp32, g.nblocks, h->stream, h->d_grid, nullptr, 1,
+      HIPCHK(launch_classic2d(h->cfg.riemann, h->fp32, g.limiter, g.transverse, g.nblocks, h->stream, h->d_grid, nullptr, 1,
                               kHostDt, dt, h->src));
     else
       HIPCHK(launch_classic1d(h->cfg.riemann, h->fp32, g.nblocks, h->stream, h->d_grid, kHostDt, dt,
@@ -255,7 +255,7 @@ int launch_attempt_device(claw_t h) {
   const GridDesc& g = h->hg;
   if (h->cfg.scheme == CLAW_CLASSIC) {
     if (h->cfg.ndim == 2)
-      HIPCHK(launch_classic2d(h->cfg.riemann, h->fp32, g.nblocks, h->stream, h->d_grid, nullptr, 1,
+      HIPCHK(launch_classic2d(h->cfg.riemann, h->fp32, g.limiter, g.transverse, g.nblocks, h->stream, h->d_grid, nullptr, 1,
                               kDeviceCtrl, 0.0, 0));
     else
       HIPCHK(launch_classic1d(h->cfg.riemann, h->fp32, g.nblocks, h->stream, h->d_grid, kDeviceCtrl,
@@ -626,8 +626,9 @@ int claw_advance_graph(claw_t h, double t_end, int k, long long max_steps, claw_
     for (;;) {
       // estimate the attempts still needed and launch that many graphs
       const Ctrl& hc = *h->h_ctrl;
-      double est = hc.dt_try > 0.0 ? (hc.t_end - hc.t) / hc.dt_try : 1.0;
-      long long launches = (long long)std::ceil((est + 1.0) / k);
+      double est = hc.dt_try > 0.0 ? (hc.t_end - hc.t) / hc.dt_try + 1.0 : 1.0;
+      if (hc.max_attempts > 0) est = std::min(est, (double)(hc.max_attempts - hc.attempts));
+      long long launches = (long long)std::ceil(est / k);
       launches = std::max(1LL, std::min(launches, 4096LL));
       for (long long l = 0; l < launches; ++l) HIPCHK(hipGraphLaunch(h->graph, h->stream));
       if ((rc = read_ctrl(h))) return rc;
@@ -699,7 +700,7 @@ int claw_autotune(claw_t h, int reps, claw_tuning* out) {
   const int ny = h->hg.ny;
   std::vector<int> cands;
   if (h->cfg.ndim == 2) {
-    for (int c : {4, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256})
+    for (int c : {4, 5, 6, 7, 8, 9, 10, 11, 12, 14, 16, 20, 24, 28, 32, 40, 48, 64, 96, 128})
       if (c <= ny) cands.push_back(c);
     if (cands.empty()) cands.push_back(ny);
   } else {
@@ -883,7 +884,9 @@ int claw_batch_add(claw_batch_t b, claw_t h, double t_end) {
   if (!h->state_set || (h->na && !h->aux_set)) return CLAW_E_STATE;
   for (claw_t o : b->members)
     if (o == h) return CLAW_E_INVAL;
-  if (!b->members.empty() && (b->riemann != h->cfg.riemann || b->fp32 != h->fp32))
+  if (!b->members.empty() &&
+      (b->riemann != h->cfg.riemann || b->fp32 != h->fp32 || b->limiter != h->hg.limiter ||
+       b->transverse != h->hg.transverse))
     return CLAW_E_INVAL;
   HIPCHK(hipSetDevice(b->device));
   double dt;
@@ -896,6 +899,8 @@ int claw_batch_add(claw_batch_t b, claw_t h, double t_end) {
   HIPCHK(hipStreamSynchronize(h->stream));
   b->riemann = h->cfg.riemann;
   b->fp32 = h->fp32;
+  b->limiter = h->hg.limiter;
+  b->transverse = h->hg.transverse;
   b->members.push_back(h);
   b->dirty = true;
   b->gathered = -1;
@@ -965,7 +970,7 @@ int claw_batch_advance(claw_batch_t b, int attempts, int* n_active) {
     hipGraph_t g;
     HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     for (int s = 0; s < kGraph; ++s)
-      launch_classic2d(b->riemann, b->fp32, total, b->stream, b->d_grids, b->d_bstart, ng,
+      launch_classic2d(b->riemann, b->fp32, b->limiter, b->transverse, total, b->stream, b->d_grids, b->d_bstart, ng,
                        kDeviceCtrl, 0.0, 0);
     HIPCHK(hipStreamEndCapture(b->stream, &g));
     const hipError_t e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
@@ -979,7 +984,7 @@ int claw_batch_advance(claw_batch_t b, int attempts, int* n_active) {
     done += b->graph_k;
   }
   for (; done < attempts; ++done)
-    HIPCHK(launch_classic2d(b->riemann, b->fp32, total, b->stream, b->d_grids, b->d_bstart, ng,
+    HIPCHK(launch_classic2d(b->riemann, b->fp32, b->limiter, b->transverse, total, b->stream, b->d_grids, b->d_bstart, ng,
                             kDeviceCtrl, 0.0, 0));
   if ((rc = batch_gather(b))) return rc;
   int act = 0, status = 0;

@@ -84,58 +84,41 @@ struct AxisMap {
 };
 
 __device__ __forceinline__ AxisMap map_axis(int i, int n, int bc_lo, int bc_hi, int h) {
-  AxisMap m{i, 0, 0};
-  if (i < 0) {
-    i = i < -h ? -h : i;
-    m.side = 0;
-    switch (bc_lo) {
-      case kBcPeriodic: m.idx = i + n; break;
-      case kBcWall: m.idx = -1 - i; m.kind = 1; break;
-      case kBcDirichlet: m.idx = 0; m.kind = 2; break;
-      default: m.idx = 0; break;
-    }
-  } else if (i >= n) {
-    i = i > n - 1 + h ? n - 1 + h : i;
-    m.side = 1;
-    switch (bc_hi) {
-      case kBcPeriodic: m.idx = i - n; break;
-      case kBcWall: m.idx = 2 * n - 1 - i; m.kind = 1; break;
-      case kBcDirichlet: m.idx = n - 1; m.kind = 2; break;
-      default: m.idx = n - 1; break;
-    }
-  }
+  // branch-free: every index maps to an interior cell (selects, no jumps)
+  const bool lo = i < 0, hi = i >= n;
+  i = i < -h ? -h : i;
+  i = i > n - 1 + h ? n - 1 + h : i;
+  const int bc = lo ? bc_lo : bc_hi;
+  const int per = lo ? i + n : i - n;
+  const int mir = lo ? -1 - i : 2 * n - 1 - i;
+  const int edge = lo ? 0 : n - 1;
+  const int gidx = bc == kBcPeriodic ? per : (bc == kBcWall ? mir : edge);
+  AxisMap m;
+  m.idx = (lo || hi) ? gidx : i;
+  m.kind = (lo || hi) ? (bc == kBcWall ? 1 : (bc == kBcDirichlet ? 2 : 0)) : 0;
+  m.side = hi ? 1 : 0;
   return m;
 }
 
 // Load one cell's state with the boundary conditions applied: the x map is
 // applied first and the y map last, so a corner ghost is the y-boundary image
-// of an x ghost.
+// of an x ghost.  Branch-free: the mapped index is always an interior cell,
+// Dirichlet states and wall sign flips are selected afterwards.
 template <typename R, class P>
 __device__ __forceinline__ void load_state(R (&v)[P::M], const R* __restrict__ q, size_t plane,
                                            int nx, const AxisMap& mx, const AxisMap& my,
                                            const GridDesc& G) {
-  if (my.kind == 2) {
+  const size_t off = (size_t)my.idx * nx + mx.idx;
 #pragma unroll
-    for (int k = 0; k < P::M; ++k) v[k] = (R)G.bcstate[2 + my.side][k];
-    return;
-  }
-  if (mx.kind == 2) {
-#pragma unroll
-    for (int k = 0; k < P::M; ++k) v[k] = (R)G.bcstate[mx.side][k];
-  } else {
-    const size_t off = (size_t)my.idx * nx + mx.idx;
-#pragma unroll
-    for (int k = 0; k < P::M; ++k) v[k] = q[k * plane + off];
-  }
-  if (mx.kind == 1) {
-#pragma unroll
-    for (int k = 0; k < P::M; ++k)
-      if (P::odd(0, k)) v[k] = -v[k];
-  }
-  if (my.kind == 1) {
-#pragma unroll
-    for (int k = 0; k < P::M; ++k)
-      if (P::odd(1, k)) v[k] = -v[k];
+  for (int k = 0; k < P::M; ++k) {
+    R x = q[k * plane + off];
+    const R xd = (R)(mx.side ? G.bcstate[1][k] : G.bcstate[0][k]);
+    x = mx.kind == 2 ? xd : x;
+    if (P::odd(0, k)) x = mx.kind == 1 ? -x : x;
+    const R yd = (R)(my.side ? G.bcstate[3][k] : G.bcstate[2][k]);
+    if (P::odd(1, k)) x = my.kind == 1 ? -x : x;
+    x = my.kind == 2 ? yd : x;
+    v[k] = x;
   }
 }
 

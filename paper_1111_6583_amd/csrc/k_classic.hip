@@ -31,7 +31,7 @@
 
 namespace claw {
 
-template <typename R, class P, bool KAHAN>
+template <typename R, class P, bool KAHAN, int LIM, int TRANS>
 __global__ __launch_bounds__(kLanes) void k_classic2d(const GridDesc* __restrict__ grids,
                                                       const int* __restrict__ bstart, int ngrids,
                                                       int mode, double dt_host, int src_host) {
@@ -69,7 +69,7 @@ __global__ __launch_bounds__(kLanes) void k_classic2d(const GridDesc* __restrict
   const R* __restrict__ aux = (const R*)G.aux;
   const R dtdx = (R)(dt / G.dx), dtdy = (R)(dt / G.dy);
   const R nux = R(0.5) * dtdx, nuy = R(0.5) * dtdy;
-  const int lim = G.limiter, trans = G.transverse;
+  constexpr int trans = TRANS;
   const P phys(G);
 
   using Cell = typename P::Cell;
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(kLanes) void k_classic2d(const GridDesc* __restrict
   // rolling state (see the pipeline above)
   R q0[M], q1[M];
   Cell c0{}, c1{};                                        // cell data of rows r-2, r-1
-  R yW0[MW][M], ys0[MW];                                  // y-face r-5/2
+  R ydl1[MW];                                             // W_p(r-5/2) . W_p(r-3/2)
   R yW1[MW][M], ys1[MW], yam1[M], yap1[M];                // y-face r-3/2
   Face yf1{};
   R glo[M], gtr_lo[M], gtop2[M], fxm2[M], fxp2[M], faL2[M], faR2[M];
@@ -88,9 +88,9 @@ __global__ __launch_bounds__(kLanes) void k_classic2d(const GridDesc* __restrict
   }
 #pragma unroll
   for (int p = 0; p < MW; ++p) {
-    ys0[p] = ys1[p] = R(0);
+    ydl1[p] = ys1[p] = R(0);
 #pragma unroll
-    for (int k = 0; k < M; ++k) yW0[p][k] = yW1[p][k] = R(0);
+    for (int k = 0; k < M; ++k) yW1[p][k] = R(0);
   }
 
   // row r+1 is loaded while row r is processed (software pipelining)
@@ -129,6 +129,19 @@ __global__ __launch_bounds__(kLanes) void k_classic2d(const GridDesc* __restrict
       for (int k = 0; k < M; ++k) yam2[k] = yap2[k] = R(0);
     }
 
+    // dot products of the new face's waves with those of the face below: the
+    // face below needs them now (its upper neighbour), the new face later
+    // (its lower neighbour)
+    R ydl2[MW];
+#pragma unroll
+    for (int p = 0; p < MW; ++p) {
+      R d = R(0);
+#pragma unroll
+      for (int k = 0; k < M; ++k)
+        if (P::template nz<1>(p, k)) d += yW1[p][k] * yW2[p][k];
+      ydl2[p] = d;
+    }
+
     // (B) y-face r-3/2: limiter, correction, transverse split into F
     R ghi[M], glo_n[M], faL1[M], faR1[M];
 #pragma unroll
@@ -139,15 +152,11 @@ __global__ __launch_bounds__(kLanes) void k_classic2d(const GridDesc* __restrict
       for (int k = 0; k < M; ++k) cq[k] = R(0);
 #pragma unroll
       for (int p = 0; p < MW; ++p) {
-        R nrm = R(0), dlo = R(0), dhi = R(0);
+        R nrm = R(0);
 #pragma unroll
-        for (int k = 0; k < M; ++k) {
-          if (!P::template nz<1>(p, k)) continue;
-          nrm += yW1[p][k] * yW1[p][k];
-          dlo += yW0[p][k] * yW1[p][k];
-          dhi += yW2[p][k] * yW1[p][k];
-        }
-        const R phi = limiter_phi(lim, ys1[p] > R(0) ? dlo : dhi, nrm);
+        for (int k = 0; k < M; ++k)
+          if (P::template nz<1>(p, k)) nrm += yW1[p][k] * yW1[p][k];
+        const R phi = limiter_phi_t<LIM>(ys1[p] > R(0) ? ydl1[p] : ydl2[p], nrm);
         const R as = rabs(ys1[p]);
         smy = max_nan(smy, as);
         const R w = as * (R(1) - dtdy * as) * phi;
@@ -206,7 +215,7 @@ __global__ __launch_bounds__(kLanes) void k_classic2d(const GridDesc* __restrict
           dl += shfl_prev(xW[p][k]) * xW[p][k];
         }
         const R dr = shfl_next(dl);   // the right neighbour's dot product with this face
-        const R phi = limiter_phi(lim, xs[p] > R(0) ? dl : dr, nrm);
+        const R phi = limiter_phi_t<LIM>(xs[p] > R(0) ? dl : dr, nrm);
         const R as = rabs(xs[p]);
         if (cfl_row && own_face) smx = max_nan(smx, as);
         const R w = as * (R(1) - dtdx * as) * phi;
@@ -294,10 +303,10 @@ __global__ __launch_bounds__(kLanes) void k_classic2d(const GridDesc* __restrict
     c1 = cn;
 #pragma unroll
     for (int p = 0; p < MW; ++p) {
-      ys0[p] = ys1[p];
       ys1[p] = ys2[p];
+      ydl1[p] = ydl2[p];
 #pragma unroll
-      for (int k = 0; k < M; ++k) { yW0[p][k] = yW1[p][k]; yW1[p][k] = yW2[p][k]; }
+      for (int k = 0; k < M; ++k) yW1[p][k] = yW2[p][k];
     }
     yf1 = yf2;
   }
@@ -537,34 +546,60 @@ __global__ __launch_bounds__(kPersistThreads) void k_classic1d_run(const GridDes
 // ---------------------------------------------------------------------------
 // Host-side launchers (dispatch on solver and precision).
 // ---------------------------------------------------------------------------
-template <typename R, bool K>
-static hipError_t launch2d_t(int riemann, dim3 grid, hipStream_t st, const GridDesc* g,
-                             const int* bs, int ng, int mode, double dt, int src) {
+template <typename R, bool K, int LIM, int TRANS>
+static hipError_t launch2d_lt(int riemann, dim3 grid, hipStream_t st, const GridDesc* g,
+                              const int* bs, int ng, int mode, double dt, int src) {
   switch (riemann) {
     case 1:
-      hipLaunchKernelGGL((k_classic2d<R, Advection<R, 2>, K>), grid, dim3(kLanes), 0, st, g, bs,
-                         ng, mode, dt, src);
+      hipLaunchKernelGGL((k_classic2d<R, Advection<R, 2>, K, LIM, TRANS>), grid, dim3(kLanes), 0,
+                         st, g, bs, ng, mode, dt, src);
       break;
     case 2:
-      hipLaunchKernelGGL((k_classic2d<R, ShallowWater<R, 2>, K>), grid, dim3(kLanes), 0, st, g,
-                         bs, ng, mode, dt, src);
+      hipLaunchKernelGGL((k_classic2d<R, ShallowWater<R, 2>, K, LIM, TRANS>), grid, dim3(kLanes),
+                         0, st, g, bs, ng, mode, dt, src);
       break;
     case 4:
-      hipLaunchKernelGGL((k_classic2d<R, Elastic<R>, K>), grid, dim3(kLanes), 0, st, g, bs, ng,
-                         mode, dt, src);
+      hipLaunchKernelGGL((k_classic2d<R, Elastic<R>, K, LIM, TRANS>), grid, dim3(kLanes), 0, st, g,
+                         bs, ng, mode, dt, src);
       break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_classic2d(int riemann, int fp32, int nblocks, hipStream_t st,
+template <typename R, bool K, int LIM>
+static hipError_t launch2d_l(int riemann, int trans, dim3 grid, hipStream_t st, const GridDesc* g,
+                             const int* bs, int ng, int mode, double dt, int src) {
+  switch (trans) {
+    case 0: return launch2d_lt<R, K, LIM, 0>(riemann, grid, st, g, bs, ng, mode, dt, src);
+    case 1: return launch2d_lt<R, K, LIM, 1>(riemann, grid, st, g, bs, ng, mode, dt, src);
+    case 2: return launch2d_lt<R, K, LIM, 2>(riemann, grid, st, g, bs, ng, mode, dt, src);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename R, bool K>
+static hipError_t launch2d_t(int riemann, int lim, int trans, dim3 grid, hipStream_t st,
+                             const GridDesc* g, const int* bs, int ng, int mode, double dt,
+                             int src) {
+  switch (lim) {
+    case 0: return launch2d_l<R, K, 0>(riemann, trans, grid, st, g, bs, ng, mode, dt, src);
+    case 1: return launch2d_l<R, K, 1>(riemann, trans, grid, st, g, bs, ng, mode, dt, src);
+    case 2: return launch2d_l<R, K, 2>(riemann, trans, grid, st, g, bs, ng, mode, dt, src);
+  }
+  return hipErrorInvalidValue;
+}
+
+// limiter and transverse mode are compile-time in the 2D kernel (no branches
+// in the marching loop); every member of a batch shares them
+hipError_t launch_classic2d(int riemann, int fp32, int lim, int trans, int nblocks, hipStream_t st,
                             const GridDesc* d_grids, const int* d_bstart, int ngrids, int mode,
                             double dt, int src) {
   const dim3 grid(nblocks);
-  return fp32 ? launch2d_t<float, true>(riemann, grid, st, d_grids, d_bstart, ngrids, mode, dt, src)
-              : launch2d_t<double, false>(riemann, grid, st, d_grids, d_bstart, ngrids, mode, dt,
-                                          src);
+  return fp32 ? launch2d_t<float, true>(riemann, lim, trans, grid, st, d_grids, d_bstart, ngrids,
+                                        mode, dt, src)
+              : launch2d_t<double, false>(riemann, lim, trans, grid, st, d_grids, d_bstart, ngrids,
+                                          mode, dt, src);
 }
 
 template <typename R, bool K>

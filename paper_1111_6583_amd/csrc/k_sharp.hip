@@ -18,39 +18,46 @@
 
 namespace claw {
 
+// Pointwise inputs of the stage combination for one cell (Q^n, and the
+// compensation in FP32 stage 3), read one row ahead of their use.
+template <typename R, int M, int STAGE, bool KAHAN>
+__device__ __forceinline__ void load_point(const GridDesc& G, size_t idx, size_t plane,
+                                           R (&qn)[M], R (&cn)[M]) {
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    qn[k] = STAGE >= 2 ? ((const R*)G.q[0])[k * plane + idx] : R(0);
+    cn[k] = (STAGE == 3 && KAHAN) ? ((const R*)G.c[0])[k * plane + idx] : R(0);
+  }
+}
+
 template <typename R, class P, int STAGE, bool KAHAN>
 __device__ __forceinline__ void combine_store(const GridDesc& G, size_t idx, size_t plane,
-                                              const R (&S)[P::M], const R (&L)[P::M], R dt) {
+                                              const R (&S)[P::M], const R (&L)[P::M], R dt,
+                                              const R (&qn)[P::M], const R (&cn)[P::M]) {
   constexpr int M = P::M;
   if constexpr (STAGE == 1) {
     R* __restrict__ o = (R*)G.s1;
 #pragma unroll
     for (int k = 0; k < M; ++k) o[k * plane + idx] = S[k] + dt * L[k];
   } else if constexpr (STAGE == 2) {
-    const R* __restrict__ Q = (const R*)G.q[0];
     R* __restrict__ o = (R*)G.s2;
 #pragma unroll
-    for (int k = 0; k < M; ++k)
-      o[k * plane + idx] = R(0.75) * Q[k * plane + idx] + R(0.25) * (S[k] + dt * L[k]);
+    for (int k = 0; k < M; ++k) o[k * plane + idx] = R(0.75) * qn[k] + R(0.25) * (S[k] + dt * L[k]);
   } else {
     R* __restrict__ Q = (R*)G.q[0];
     if constexpr (KAHAN) {
       R* __restrict__ C = (R*)G.c[0];
 #pragma unroll
       for (int k = 0; k < M; ++k) {
-        const R qn = Q[k * plane + idx];
-        const R inc = R(2.0 / 3.0) * ((S[k] - qn) + dt * L[k]);
-        const R y = inc - C[k * plane + idx];
-        const R t = qn + y;
-        C[k * plane + idx] = (t - qn) - y;
+        const R inc = R(2.0 / 3.0) * ((S[k] - qn[k]) + dt * L[k]);
+        const R y = inc - cn[k];
+        const R t = qn[k] + y;
+        C[k * plane + idx] = (t - qn[k]) - y;
         Q[k * plane + idx] = t;
       }
     } else {
 #pragma unroll
-      for (int k = 0; k < M; ++k) {
-        const R qn = Q[k * plane + idx];
-        Q[k * plane + idx] = qn / R(3) + R(2.0 / 3.0) * (S[k] + dt * L[k]);
-      }
+      for (int k = 0; k < M; ++k) Q[k * plane + idx] = qn[k] / R(3) + R(2.0 / 3.0) * (S[k] + dt * L[k]);
     }
   }
 }
@@ -124,13 +131,21 @@ __global__ __launch_bounds__(kLanes) void k_sharp2d(const GridDesc* __restrict__
 #pragma unroll
     for (int s = 0; s < 5; ++s) w[s][k] = R(0);
   }
-  // row r+1 is loaded while row r is processed (software pipelining)
-  R pre[M];
+  // row r+1 is loaded while row r is processed (software pipelining); the
+  // pointwise Q^n (and compensation) of the row finalised next iteration too
+  R pre[M], pq[M], pc[M], uq[M], uc[M];
   {
     const AxisMap my = map_axis(j0 - 3, ny, G.bc[2], G.bc[3], H);
     load_state<R, P>(pre, S, plane, nx, mx, my, G);
   }
+#pragma unroll
+  for (int k = 0; k < M; ++k) pq[k] = pc[k] = uq[k] = uc[k] = R(0);
+  const int ic = i < 0 ? 0 : (i >= nx ? nx - 1 : i);   // clamped column for pointwise reads
   for (int r = j0 - 3; r <= j1 + 2; ++r) {
+#pragma unroll
+    for (int k = 0; k < M; ++k) { uq[k] = pq[k]; uc[k] = pc[k]; }
+    if (STAGE >= 2 && r - 2 >= j0 && r - 2 < j1)
+      load_point<R, M, STAGE, KAHAN>(G, (size_t)(r - 2) * nx + ic, plane, pq, pc);
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -174,7 +189,8 @@ __global__ __launch_bounds__(kLanes) void k_sharp2d(const GridDesc* __restrict__
           Lv[k] = -(Fr - F[k]) * rdx - (g_up[k] - g_lo[k]) * rdy;
           Sc[k] = w[1][k];
         }
-        if (own) combine_store<R, P, STAGE, KAHAN>(G, (size_t)(r - 3) * nx + i, plane, Sc, Lv, dt);
+        if (own)
+          combine_store<R, P, STAGE, KAHAN>(G, (size_t)(r - 3) * nx + i, plane, Sc, Lv, dt, uq, uc);
       }
 #pragma unroll
       for (int k = 0; k < M; ++k) g_lo[k] = g_up[k];
@@ -222,7 +238,9 @@ __global__ __launch_bounds__(kLanes) void k_sharp1d(const GridDesc* __restrict__
   const R sx = phys.template flux<0>(ql, xr, F);
 #pragma unroll
   for (int k = 0; k < M; ++k) Lv[k] = -(shfl_next(F[k]) - F[k]) * rdx;
-  if (own) combine_store<R, P, STAGE, KAHAN>(G, (size_t)i, (size_t)nx, c, Lv, dt);
+  R pq[M], pc[M];
+  load_point<R, M, STAGE, KAHAN>(G, (size_t)(i < 0 ? 0 : (i >= nx ? nx - 1 : i)), (size_t)nx, pq, pc);
+  if (own) combine_store<R, P, STAGE, KAHAN>(G, (size_t)i, (size_t)nx, c, Lv, dt, pq, pc);
   const double speed = own_face ? (double)sx * (1.0 / G.dx) : 0.0;
   stage_finish<STAGE>(ctrl, mode, speed, G.nblocks);
 }

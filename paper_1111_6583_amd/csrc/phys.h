@@ -32,8 +32,11 @@
 
 namespace claw {
 
-template <typename R> __device__ __forceinline__ R rmin(R a, R b) { return a < b ? a : b; }
-template <typename R> __device__ __forceinline__ R rmax(R a, R b) { return a > b ? a : b; }
+// min / max as single v_min / v_max instructions (operands are finite here)
+__device__ __forceinline__ double rmin(double a, double b) { return __builtin_fmin(a, b); }
+__device__ __forceinline__ double rmax(double a, double b) { return __builtin_fmax(a, b); }
+__device__ __forceinline__ float rmin(float a, float b) { return __builtin_fminf(a, b); }
+__device__ __forceinline__ float rmax(float a, float b) { return __builtin_fmaxf(a, b); }
 template <typename R> __device__ __forceinline__ R rabs(R a) { return a < R(0) ? -a : a; }
 
 // ---------------------------------------------------------------------------
@@ -372,10 +375,28 @@ template <> struct TinyNorm<float> { static constexpr float v = 1e-30f; };
 template <typename R>
 __device__ __forceinline__ R limiter_phi(int lim, R num, R den) {
   if (lim == 0) return R(1);
-  if (!(den > TinyNorm<R>::v)) return R(0);
-  const R th = num * frcp(den);
-  if (lim == 1) return rmax(R(0), rmin(R(1), th));
-  return rmax(R(0), rmin(rmin((R(1) + th) * R(0.5), R(2)), R(2) * th));
+  const bool ok = den > TinyNorm<R>::v;
+  const R th = num * frcp(ok ? den : R(1));
+  const R phi = lim == 1 ? rmax(R(0), rmin(R(1), th))
+                         : rmax(R(0), rmin(rmin((R(1) + th) * R(0.5), R(2)), R(2) * th));
+  return ok ? phi : R(0);
+}
+
+// The same with the limiter fixed at compile time (no branches).
+template <int LIM, typename R>
+__device__ __forceinline__ R limiter_phi_t(R num, R den) {
+  if constexpr (LIM == 0) {
+    return R(1);
+  } else {
+    const bool ok = den > TinyNorm<R>::v;
+    const R th = num * frcp(ok ? den : R(1));
+    R phi;
+    if constexpr (LIM == 1)
+      phi = rmax(R(0), rmin(R(1), th));
+    else
+      phi = rmax(R(0), rmin(rmin((R(1) + th) * R(0.5), R(2)), R(2) * th));
+    return ok ? phi : R(0);
+  }
 }
 
 // ===========================================================================
