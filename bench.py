@@ -136,9 +136,10 @@ WORKLOADS = {
 }
 
 
-def kernel_only(workload, precision, launches):
+def kernel_only(workload, precision, launches, seg_rows=0):
     """Launch only the step kernel (classic) or stages 1-2 (SharpClaw) of a
-    workload `launches` times, for hardware-counter runs."""
+    workload `launches` times, for hardware-counter runs.  seg_rows > 0 fixes
+    the tiling (no autotuning launches in the profile)."""
     from paper_1111_6583_amd import Solver
     from paper_1111_6583_amd import workloads as W
     name, make = WORKLOADS[workload]
@@ -147,7 +148,10 @@ def kernel_only(workload, precision, launches):
     s.set_state(q)
     if aux is not None:
         s.set_aux(aux)
-    s.autotune(reps=2)
+    if seg_rows > 0:
+        s.set_tuning(seg_rows)
+    else:
+        s.autotune(reps=2)
     s.advance(1e9, max_steps=10)
     ms = s.time_kernel(s.clock()["dt_next"] * 0.5, reps=launches)
     print(json.dumps(dict(mode="kernel", workload=name, precision=precision, launches=launches,
@@ -181,13 +185,14 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "fp32_kahan"], default="fp64")
     ap.add_argument("--launches", type=int, default=20)
     ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--seg-rows", type=int, default=0, help="kernel mode: fixed rows per segment")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU: this build runs the step on a single MI355X "
               "(multi-GPU decomposition is designed but not built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     if a.mode == "kernel":
-        return kernel_only(a.workload, a.precision, a.launches)
+        return kernel_only(a.workload, a.precision, a.launches, a.seg_rows)
     if a.mode == "copy":
         return copy_only(a.copy_mib, a.launches)
 

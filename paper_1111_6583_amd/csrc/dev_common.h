@@ -11,21 +11,22 @@ namespace claw {
 // Lane shifts inside one 64-lane wavefront.  x-neighbours of a cell live in
 // adjacent lanes of the marching kernels; prev = value held by lane-1,
 // next = value held by lane+1.  They are DPP wavefront shifts (wave_shr:1 /
-// wave_shl:1, one VALU move per 32 bits, no LDS); edge lanes receive 0 and
-// are halo lanes whose results are discarded.
+// wave_shl:1, one VALU move per 32 bits, no LDS).  bound_ctrl makes the edge
+// lanes (no source lane) receive 0 without a prior write of the destination;
+// they are halo lanes whose results are discarded.
 // ---------------------------------------------------------------------------
 constexpr int kDppWaveShr1 = 0x138;   // lane l reads lane l-1
 constexpr int kDppWaveShl1 = 0x130;   // lane l reads lane l+1
 
 template <int CTRL>
 __device__ __forceinline__ float dpp_f(float x) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xf, 0xf, true));
 }
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double x) {
   const unsigned long long b = (unsigned long long)__double_as_longlong(x);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, true);
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 __device__ __forceinline__ float shfl_prev(float x) { return dpp_f<kDppWaveShr1>(x); }
@@ -100,32 +101,73 @@ __device__ __forceinline__ AxisMap map_axis(int i, int n, int bc_lo, int bc_hi, 
   return m;
 }
 
-// Load one cell's state with the boundary conditions applied: the x map is
-// applied first and the y map last, so a corner ghost is the y-boundary image
-// of an x ghost.  Branch-free: the mapped index is always an interior cell,
-// Dirichlet states and wall sign flips are selected afterwards.
-template <typename R, class P>
-__device__ __forceinline__ void load_state(R (&v)[P::M], const R* __restrict__ q, size_t plane,
-                                           int nx, const AxisMap& mx, const AxisMap& my,
-                                           const GridDesc& G) {
+// Device arrays are addressed through global-address-space pointers: loads
+// and stores then become global_* instructions, which count only against the
+// vector-memory counter (flat_* ones also hold the scalar-memory counter and
+// make every scalar load wait for them).
+#define CLAW_GLOBAL __attribute__((address_space(1)))
+template <typename T> using gconst = const CLAW_GLOBAL T*;
+template <typename T> using gmut = CLAW_GLOBAL T*;
+template <typename T>
+__device__ __forceinline__ gconst<T> as_gconst(const void* p) { return (gconst<T>)p; }
+template <typename T>
+__device__ __forceinline__ gmut<T> as_gmut(void* p) { return (gmut<T>)p; }
+
+// Ghost values that do not come from memory (Dirichlet sides), held in
+// registers for the whole kernel instead of being re-read per row.
+template <typename R, int M>
+struct EdgeStates {
+  R x[M];             // this lane's x side (used if its column is a Dirichlet ghost)
+  R ylo[M], yhi[M];   // lower / upper y side
+};
+template <typename R, int M>
+__device__ __forceinline__ EdgeStates<R, M> edge_states(const GridDesc& G, const AxisMap& mx) {
+  EdgeStates<R, M> e;
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    e.x[k] = (R)(mx.side ? G.bcstate[1][k] : G.bcstate[0][k]);
+    e.ylo[k] = (R)G.bcstate[2][k];
+    e.yhi[k] = (R)G.bcstate[3][k];
+  }
+  return e;
+}
+
+// A cell's state is read in two steps so that a row can be prefetched: the
+// raw load of the mapped interior cell (always in bounds), then, once the
+// data is needed, the boundary conditions.  The x map is applied first and
+// the y map last, so a corner ghost is the y-boundary image of an x ghost.
+template <typename R, int M>
+__device__ __forceinline__ void load_raw(R (&v)[M], gconst<R> q, size_t plane, int nx,
+                                         const AxisMap& mx, const AxisMap& my) {
   const size_t off = (size_t)my.idx * nx + mx.idx;
 #pragma unroll
+  for (int k = 0; k < M; ++k) v[k] = q[k * plane + off];
+}
+template <typename R, class P>
+__device__ __forceinline__ void apply_bc(R (&v)[P::M], const AxisMap& mx, const AxisMap& my,
+                                         const EdgeStates<R, P::M>& e) {
+#pragma unroll
   for (int k = 0; k < P::M; ++k) {
-    R x = q[k * plane + off];
-    const R xd = (R)(mx.side ? G.bcstate[1][k] : G.bcstate[0][k]);
-    x = mx.kind == 2 ? xd : x;
+    R x = v[k];
+    x = mx.kind == 2 ? e.x[k] : x;
     if (P::odd(0, k)) x = mx.kind == 1 ? -x : x;
-    const R yd = (R)(my.side ? G.bcstate[3][k] : G.bcstate[2][k]);
     if (P::odd(1, k)) x = my.kind == 1 ? -x : x;
-    x = my.kind == 2 ? yd : x;
+    x = my.kind == 2 ? (my.side ? e.yhi[k] : e.ylo[k]) : x;
     v[k] = x;
   }
 }
+template <typename R, class P>
+__device__ __forceinline__ void load_state(R (&v)[P::M], gconst<R> q, size_t plane, int nx,
+                                           const AxisMap& mx, const AxisMap& my,
+                                           const EdgeStates<R, P::M>& e) {
+  load_raw<R, P::M>(v, q, plane, nx, mx, my);
+  apply_bc<R, P>(v, mx, my, e);
+}
 
 // Aux fields: ghost cells copy the mapped interior cell (no sign flips; a
-// Dirichlet side copies the edge cell).
+// Dirichlet side copies the edge cell).  No fix-up step: prefetchable as is.
 template <typename R, class P>
-__device__ __forceinline__ void load_aux(R (&a)[P::NA > 0 ? P::NA : 1], const R* __restrict__ aux,
+__device__ __forceinline__ void load_aux(R (&a)[P::NA > 0 ? P::NA : 1], gconst<R> aux,
                                          size_t plane, int nx, const AxisMap& mx,
                                          const AxisMap& my) {
   if constexpr (P::NA > 0) {

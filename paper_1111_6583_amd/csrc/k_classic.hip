@@ -31,6 +31,13 @@
 
 namespace claw {
 
+// Which pipeline stages a row of the marching loop runs.  cfl: the x-row of
+// stage C is an output row of the segment (its speeds enter the Courant
+// number).
+struct Stages {
+  bool a, b, c, d, load, cfl;
+};
+
 template <typename R, class P, bool KAHAN, int LIM, int TRANS>
 __global__ __launch_bounds__(kLanes) void k_classic2d(const GridDesc* __restrict__ grids,
                                                       const int* __restrict__ bstart, int ngrids,
@@ -64,9 +71,14 @@ __global__ __launch_bounds__(kLanes) void k_classic2d(const GridDesc* __restrict
   const int j0 = seg * G.seg_rows;
   const int j1 = min(j0 + G.seg_rows, ny);
   const AxisMap mx = map_axis(i, nx, G.bc[0], G.bc[1], H);
-  const R* __restrict__ q = (const R*)G.q[src];
-  R* __restrict__ qo = (R*)G.q[src ^ 1];
-  const R* __restrict__ aux = (const R*)G.aux;
+  const int bcy0 = G.bc[2], bcy1 = G.bc[3];
+  const int ic = i < 0 ? 0 : (i >= nx ? nx - 1 : i);   // clamped column for pointwise reads
+  const EdgeStates<R, M> es = edge_states<R, M>(G, mx);
+  const gconst<R> q = as_gconst<R>(G.q[src]);
+  const gmut<R> qo = as_gmut<R>(G.q[src ^ 1]);
+  const gconst<R> aux = as_gconst<R>(G.aux);
+  const gconst<R> cin = as_gconst<R>(G.c[src]);
+  const gmut<R> cout = as_gmut<R>(G.c[src ^ 1]);
   const R dtdx = (R)(dt / G.dx), dtdy = (R)(dt / G.dy);
   const R nux = R(0.5) * dtdx, nuy = R(0.5) * dtdy;
   constexpr int trans = TRANS;
@@ -93,30 +105,47 @@ __global__ __launch_bounds__(kLanes) void k_classic2d(const GridDesc* __restrict
     for (int k = 0; k < M; ++k) yW1[p][k] = R(0);
   }
 
-  // row r+1 is loaded while row r is processed (software pipelining)
-  R qpre[M], apre[NA];
+  // Row r+1 is loaded while row r is processed (software pipelining).  Its
+  // boundary conditions are applied just before row r's results are stored,
+  // so the wait for the load comes a row of work after it was issued and
+  // never behind this row's stores.
+  R qpre[M], apre[NA], qnext[M];
   {
-    const AxisMap my = map_axis(j0 - 2, ny, G.bc[2], G.bc[3], H);
-    load_state<R, P>(qpre, q, plane, nx, mx, my, G);
+    const AxisMap my = map_axis(j0 - 2, ny, bcy0, bcy1, H);
+    load_state<R, P>(qnext, q, plane, nx, mx, my, es);
     load_aux<R, P>(apre, aux, plane, nx, mx, my);
   }
-  for (int r = j0 - 2; r <= j1 + 1; ++r) {
+  // One row of the pipeline (the stages that row r runs are in st).
+  auto row = [&](const Stages st, const int r) {
     R qn[M], an[NA];
 #pragma unroll
-    for (int k = 0; k < M; ++k) qn[k] = qpre[k];
+    for (int k = 0; k < M; ++k) qn[k] = qnext[k];
 #pragma unroll
     for (int k = 0; k < NA; ++k) an[k] = apre[k];
-    if (r + 1 <= j1 + 1) {
-      const AxisMap my = map_axis(r + 1, ny, G.bc[2], G.bc[3], H);
-      load_state<R, P>(qpre, q, plane, nx, mx, my, G);
-      load_aux<R, P>(apre, aux, plane, nx, mx, my);
+    AxisMap mynext{0, 0, 0};
+    if (st.load) {
+      mynext = map_axis(r + 1, ny, bcy0, bcy1, H);
+      load_raw<R, M>(qpre, q, plane, nx, mx, mynext);
+      load_aux<R, P>(apre, aux, plane, nx, mx, mynext);
+    }
+    // the compensation of row r-2 (finalised below), read ahead of its use
+    R cprev[M];
+    if constexpr (KAHAN) {
+      if (st.d) {
+        const size_t off = (size_t)(r - 2) * nx + ic;
+#pragma unroll
+        for (int k = 0; k < M; ++k) cprev[k] = cin[k * plane + off];
+      } else {
+#pragma unroll
+        for (int k = 0; k < M; ++k) cprev[k] = R(0);
+      }
     }
     const Cell cn = phys.cell(qn, an);
 
     // (A) y-face r-1/2
     R yW2[MW][M], ys2[MW], yam2[M], yap2[M];
     Face yf2{};
-    if (r >= j0 - 1) {
+    if (st.a) {
       phys.template normal<1>(q1, qn, c1, cn, yW2, ys2, yam2, yap2, yf2);
     } else {
 #pragma unroll
@@ -146,7 +175,7 @@ __global__ __launch_bounds__(kLanes) void k_classic2d(const GridDesc* __restrict
     R ghi[M], glo_n[M], faL1[M], faR1[M];
 #pragma unroll
     for (int k = 0; k < M; ++k) ghi[k] = glo_n[k] = faL1[k] = faR1[k] = R(0);
-    if (r >= j0 + 1) {
+    if (st.b) {
       R cq[M];
 #pragma unroll
       for (int k = 0; k < M; ++k) cq[k] = R(0);
@@ -194,14 +223,13 @@ __global__ __launch_bounds__(kLanes) void k_classic2d(const GridDesc* __restrict
     R fxm1[M], fxp1[M], gtop1[M], gtr_cur[M];
 #pragma unroll
     for (int k = 0; k < M; ++k) fxm1[k] = fxp1[k] = gtop1[k] = gtr_cur[k] = R(0);
-    if (r >= j0) {
+    if (st.c) {
       R ql[M];
 #pragma unroll
       for (int k = 0; k < M; ++k) ql[k] = shfl_prev(q1[k]);
       R xW[MW][M], xs[MW], xam[M], xap[M];
       Face xf{};
       phys.template normal<0>(ql, q1, P::shfl_prev_cell(c1), c1, xW, xs, xam, xap, xf);
-      const bool cfl_row = (r - 1 >= j0) && (r - 1 < j1);
       R cq[M];
 #pragma unroll
       for (int k = 0; k < M; ++k) cq[k] = R(0);
@@ -217,7 +245,7 @@ __global__ __launch_bounds__(kLanes) void k_classic2d(const GridDesc* __restrict
         const R dr = shfl_next(dl);   // the right neighbour's dot product with this face
         const R phi = limiter_phi_t<LIM>(xs[p] > R(0) ? dl : dr, nrm);
         const R as = rabs(xs[p]);
-        if (cfl_row && own_face) smx = max_nan(smx, as);
+        if (st.cfl && own_face) smx = max_nan(smx, as);
         const R w = as * (R(1) - dtdx * as) * phi;
 #pragma unroll
         for (int k = 0; k < M; ++k)
@@ -255,8 +283,14 @@ __global__ __launch_bounds__(kLanes) void k_classic2d(const GridDesc* __restrict
       for (int k = 0; k < M; ++k) gtr_cur[k] = gtop2[k] + gbot1[k];
     }
 
+    if (st.load) {
+#pragma unroll
+      for (int k = 0; k < M; ++k) qnext[k] = qpre[k];
+      apply_bc<R, P>(qnext, mx, mynext, es);
+    }
+
     // (D) row r-2 is complete
-    if (r >= j0 + 2) {
+    if (st.d) {
       const int f = r - 2;
       const size_t off = (size_t)f * nx + i;
 #pragma unroll
@@ -269,11 +303,8 @@ __global__ __launch_bounds__(kLanes) void k_classic2d(const GridDesc* __restrict
         const R xs = fp + fm, ys = gp + gm;
         if (own) {
           if constexpr (KAHAN) {
-            const R* __restrict__ cin = (const R*)G.c[src];
-            R* __restrict__ cout = (R*)G.c[src ^ 1];
             const R inc = -(dtdx * xs + dtdy * ys);
-            const R cc = cin[k * plane + off];
-            const R y = inc - cc;
+            const R y = inc - cprev[k];
             const R t = q0[k] + y;
             cout[k * plane + off] = (t - q0[k]) - y;
             qo[k * plane + off] = t;
@@ -309,7 +340,12 @@ __global__ __launch_bounds__(kLanes) void k_classic2d(const GridDesc* __restrict
       for (int k = 0; k < M; ++k) yW1[p][k] = yW2[p][k];
     }
     yf1 = yf2;
-  }
+  };
+  // rows j0-2 .. j0+1 fill the pipeline; j0+2 .. j1 are steady; j1+1 drains
+  for (int r = j0 - 2; r <= j1 + 1; ++r)
+    row(Stages{r >= j0 - 1, r >= j0 + 1, r >= j0, r >= j0 + 2, r + 1 <= j1 + 1,
+               r - 1 >= j0 && r - 1 < j1},
+        r);
 
   const double speed = own ? max_nan((double)smx / G.dx, (double)smy / G.dy)
                            : (own_face ? (double)smx / G.dx : 0.0);
@@ -351,14 +387,14 @@ __global__ __launch_bounds__(kLanes) void k_classic1d(const GridDesc* __restrict
   const bool own_face = lane >= H && lane <= H + U && i <= nx;
   const AxisMap mx = map_axis(i, nx, G.bc[0], G.bc[1], H);
   const AxisMap my{0, 0, 0};
-  const R* __restrict__ q = (const R*)G.q[src];
-  R* __restrict__ qo = (R*)G.q[src ^ 1];
+  const gconst<R> q = as_gconst<R>(G.q[src]);
+  const gmut<R> qo = as_gmut<R>(G.q[src ^ 1]);
   const R dtdx = (R)(dt / G.dx);
   const P phys(G);
   using Cell = typename P::Cell;
   R qc[M], ql[M];
   R dummy[1] = {R(0)};
-  load_state<R, P>(qc, q, (size_t)nx, nx, mx, my, G);
+  load_state<R, P>(qc, q, (size_t)nx, nx, mx, my, edge_states<R, M>(G, mx));
 #pragma unroll
   for (int k = 0; k < M; ++k) ql[k] = shfl_prev(qc[k]);
   const Cell cc = phys.cell(qc, dummy);
@@ -391,8 +427,8 @@ __global__ __launch_bounds__(kLanes) void k_classic1d(const GridDesc* __restrict
     const R fm = shfl_next(am[k] + R(0.5) * cq[k]);
     if (own) {
       if constexpr (KAHAN) {
-        const R* __restrict__ cin = (const R*)G.c[src];
-        R* __restrict__ cout = (R*)G.c[src ^ 1];
+        const gconst<R> cin = as_gconst<R>(G.c[src]);
+        const gmut<R> cout = as_gmut<R>(G.c[src ^ 1]);
         const R inc = -(dtdx * (fp + fm));
         const R y = inc - cin[(size_t)k * nx + i];
         const R t = qc[k] + y;

@@ -21,43 +21,46 @@ namespace claw {
 // Pointwise inputs of the stage combination for one cell (Q^n, and the
 // compensation in FP32 stage 3), read one row ahead of their use.
 template <typename R, int M, int STAGE, bool KAHAN>
-__device__ __forceinline__ void load_point(const GridDesc& G, size_t idx, size_t plane,
+__device__ __forceinline__ void load_point(gconst<R> Qn, gconst<R> Cn, size_t idx, size_t plane,
                                            R (&qn)[M], R (&cn)[M]) {
 #pragma unroll
   for (int k = 0; k < M; ++k) {
-    qn[k] = STAGE >= 2 ? ((const R*)G.q[0])[k * plane + idx] : R(0);
-    cn[k] = (STAGE == 3 && KAHAN) ? ((const R*)G.c[0])[k * plane + idx] : R(0);
+    qn[k] = STAGE >= 2 ? Qn[k * plane + idx] : R(0);
+    cn[k] = (STAGE == 3 && KAHAN) ? Cn[k * plane + idx] : R(0);
   }
 }
 
+// Output of a stage: S1 (stage 1), S2 (stage 2) or Q in place (stage 3, with
+// its compensation C in FP32 mode).
+template <typename R, int STAGE>
+__device__ __forceinline__ gmut<R> stage_out(const GridDesc& G) {
+  return as_gmut<R>(STAGE == 1 ? G.s1 : (STAGE == 2 ? G.s2 : G.q[0]));
+}
+
 template <typename R, class P, int STAGE, bool KAHAN>
-__device__ __forceinline__ void combine_store(const GridDesc& G, size_t idx, size_t plane,
+__device__ __forceinline__ void combine_store(gmut<R> O, gmut<R> C, size_t idx, size_t plane,
                                               const R (&S)[P::M], const R (&L)[P::M], R dt,
                                               const R (&qn)[P::M], const R (&cn)[P::M]) {
   constexpr int M = P::M;
   if constexpr (STAGE == 1) {
-    R* __restrict__ o = (R*)G.s1;
 #pragma unroll
-    for (int k = 0; k < M; ++k) o[k * plane + idx] = S[k] + dt * L[k];
+    for (int k = 0; k < M; ++k) O[k * plane + idx] = S[k] + dt * L[k];
   } else if constexpr (STAGE == 2) {
-    R* __restrict__ o = (R*)G.s2;
 #pragma unroll
-    for (int k = 0; k < M; ++k) o[k * plane + idx] = R(0.75) * qn[k] + R(0.25) * (S[k] + dt * L[k]);
+    for (int k = 0; k < M; ++k) O[k * plane + idx] = R(0.75) * qn[k] + R(0.25) * (S[k] + dt * L[k]);
   } else {
-    R* __restrict__ Q = (R*)G.q[0];
     if constexpr (KAHAN) {
-      R* __restrict__ C = (R*)G.c[0];
 #pragma unroll
       for (int k = 0; k < M; ++k) {
         const R inc = R(2.0 / 3.0) * ((S[k] - qn[k]) + dt * L[k]);
         const R y = inc - cn[k];
         const R t = qn[k] + y;
         C[k * plane + idx] = (t - qn[k]) - y;
-        Q[k * plane + idx] = t;
+        O[k * plane + idx] = t;
       }
     } else {
 #pragma unroll
-      for (int k = 0; k < M; ++k) Q[k * plane + idx] = qn[k] / R(3) + R(2.0 / 3.0) * (S[k] + dt * L[k]);
+      for (int k = 0; k < M; ++k) O[k * plane + idx] = qn[k] / R(3) + R(2.0 / 3.0) * (S[k] + dt * L[k]);
     }
   }
 }
@@ -117,13 +120,15 @@ __global__ __launch_bounds__(kLanes) void k_sharp2d(const GridDesc* __restrict__
   const int j0 = seg * G.seg_rows;
   const int j1 = min(j0 + G.seg_rows, ny);
   const AxisMap mx = map_axis(i, nx, G.bc[0], G.bc[1], H);
-  const R* __restrict__ S = (const R*)(STAGE == 1 ? G.q[0] : (STAGE == 2 ? G.s1 : G.s2));
+  const int bcy0 = G.bc[2], bcy1 = G.bc[3];
+  const EdgeStates<R, M> es = edge_states<R, M>(G, mx);
+  const gconst<R> S = as_gconst<R>(STAGE == 1 ? G.q[0] : (STAGE == 2 ? G.s1 : G.s2));
   const R eps = (R)G.weno_eps;
   const R rdx = (R)(1.0 / G.dx), rdy = (R)(1.0 / G.dy);
   const P phys(G);
   R smx = R(0), smy = R(0);
 
-  R w[5][M];          // rows k-4 .. k
+  R w[5][M];          // rows r-4 .. r
   R qyl_prev[M], g_lo[M];
 #pragma unroll
   for (int k = 0; k < M; ++k) {
@@ -131,72 +136,86 @@ __global__ __launch_bounds__(kLanes) void k_sharp2d(const GridDesc* __restrict__
 #pragma unroll
     for (int s = 0; s < 5; ++s) w[s][k] = R(0);
   }
-  // row r+1 is loaded while row r is processed (software pipelining); the
-  // pointwise Q^n (and compensation) of the row finalised next iteration too
-  R pre[M], pq[M], pc[M], uq[M], uc[M];
-  {
-    const AxisMap my = map_axis(j0 - 3, ny, G.bc[2], G.bc[3], H);
-    load_state<R, P>(pre, S, plane, nx, mx, my, G);
-  }
+  const gconst<R> Qn = as_gconst<R>(G.q[0]);
+  const gconst<R> Cn = as_gconst<R>(G.c[0]);
+  const gmut<R> Out = stage_out<R, STAGE>(G);
+  const gmut<R> Cout = as_gmut<R>(G.c[0]);
+  // Row r+1 is loaded while row r is processed (software pipelining) and
+  // enters the window with its boundary conditions applied just before row
+  // r's results are stored (the wait for the load then comes a row of work
+  // after it was issued, and never behind stores).  The pointwise Q^n (and
+  // compensation) of the row finalised next iteration is read ahead too.
+  R pre[M], nxt[M], pq[M], pc[M], uq[M], uc[M];
+  load_state<R, P>(nxt, S, plane, nx, mx, map_axis(j0 - 3, ny, bcy0, bcy1, H), es);
 #pragma unroll
   for (int k = 0; k < M; ++k) pq[k] = pc[k] = uq[k] = uc[k] = R(0);
   const int ic = i < 0 ? 0 : (i >= nx ? nx - 1 : i);   // clamped column for pointwise reads
   for (int r = j0 - 3; r <= j1 + 2; ++r) {
 #pragma unroll
     for (int k = 0; k < M; ++k) { uq[k] = pq[k]; uc[k] = pc[k]; }
-    if (STAGE >= 2 && r - 2 >= j0 && r - 2 < j1)
-      load_point<R, M, STAGE, KAHAN>(G, (size_t)(r - 2) * nx + ic, plane, pq, pc);
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int k = 0; k < M; ++k) w[s][k] = w[s + 1][k];
 #pragma unroll
-    for (int k = 0; k < M; ++k) w[4][k] = pre[k];
-    if (r + 1 <= j1 + 2) {
-      const AxisMap my = map_axis(r + 1, ny, G.bc[2], G.bc[3], H);
-      load_state<R, P>(pre, S, plane, nx, mx, my, G);
+    for (int k = 0; k < M; ++k) w[4][k] = nxt[k];
+    const bool more = r + 1 <= j1 + 2;
+    AxisMap mynext{0, 0, 0};
+    if (more) {
+      mynext = map_axis(r + 1, ny, bcy0, bcy1, H);
+      load_raw<R, M>(pre, S, plane, nx, mx, mynext);
     }
-    if (r < j0 + 1) continue;
-    // y edge values of row c = r-2
-    R qyl[M], qyr[M];
+    if (STAGE >= 2 && r - 2 >= j0 && r - 2 < j1)
+      load_point<R, M, STAGE, KAHAN>(Qn, Cn, (size_t)(r - 2) * nx + ic, plane, pq, pc);
+    R Lv[M], Sc[M];
+    bool store = false;
+    if (r >= j0 + 1) {
+      // y edge values of row c = r-2
+      R qyl[M], qyr[M];
 #pragma unroll
-    for (int k = 0; k < M; ++k)
-      weno5_edges(w[0][k], w[1][k], w[2][k], w[3][k], w[4][k], eps, qyl[k], qyr[k]);
-    if (r >= j0 + 2) {
-      // y-face flux at c-1/2
-      R g_up[M];
-      const R sy = phys.template flux<1>(qyl_prev, qyr, g_up);
-      smy = max_nan(smy, sy);
-      if (r >= j0 + 3) {
-        // row f = r-3 (window row 1) is complete: x edge values, x-face fluxes
-        R xl[M], xr[M];
+      for (int k = 0; k < M; ++k)
+        weno5_edges(w[0][k], w[1][k], w[2][k], w[3][k], w[4][k], eps, qyl[k], qyr[k]);
+      if (r >= j0 + 2) {
+        // y-face flux at c-1/2
+        R g_up[M];
+        const R sy = phys.template flux<1>(qyl_prev, qyr, g_up);
+        smy = max_nan(smy, sy);
+        if (r >= j0 + 3) {
+          // row f = r-3 (window row 1) is complete: x edge values, x-face fluxes
+          R xl[M], xr[M];
 #pragma unroll
-        for (int k = 0; k < M; ++k) {
-          const R c0 = w[1][k];
-          const R m1 = shfl_prev(c0), p1 = shfl_next(c0);
-          const R m2 = shfl_prev(m1), p2 = shfl_next(p1);
-          weno5_edges(m2, m1, c0, p1, p2, eps, xl[k], xr[k]);
+          for (int k = 0; k < M; ++k) {
+            const R c0 = w[1][k];
+            const R m1 = shfl_prev(c0), p1 = shfl_next(c0);
+            const R m2 = shfl_prev(m1), p2 = shfl_next(p1);
+            weno5_edges(m2, m1, c0, p1, p2, eps, xl[k], xr[k]);
+          }
+          R ql[M], F[M];
+#pragma unroll
+          for (int k = 0; k < M; ++k) ql[k] = shfl_prev(xl[k]);
+          const R sx = phys.template flux<0>(ql, xr, F);
+          if (own_face) smx = max_nan(smx, sx);
+#pragma unroll
+          for (int k = 0; k < M; ++k) {
+            const R Fr = shfl_next(F[k]);
+            Lv[k] = -(Fr - F[k]) * rdx - (g_up[k] - g_lo[k]) * rdy;
+            Sc[k] = w[1][k];
+          }
+          store = true;
         }
-        R ql[M], F[M];
 #pragma unroll
-        for (int k = 0; k < M; ++k) ql[k] = shfl_prev(xl[k]);
-        const R sx = phys.template flux<0>(ql, xr, F);
-        if (own_face) smx = max_nan(smx, sx);
-        R Lv[M], Sc[M];
-#pragma unroll
-        for (int k = 0; k < M; ++k) {
-          const R Fr = shfl_next(F[k]);
-          Lv[k] = -(Fr - F[k]) * rdx - (g_up[k] - g_lo[k]) * rdy;
-          Sc[k] = w[1][k];
-        }
-        if (own)
-          combine_store<R, P, STAGE, KAHAN>(G, (size_t)(r - 3) * nx + i, plane, Sc, Lv, dt, uq, uc);
+        for (int k = 0; k < M; ++k) g_lo[k] = g_up[k];
       }
 #pragma unroll
-      for (int k = 0; k < M; ++k) g_lo[k] = g_up[k];
+      for (int k = 0; k < M; ++k) qyl_prev[k] = qyl[k];
     }
+    if (more) {
 #pragma unroll
-    for (int k = 0; k < M; ++k) qyl_prev[k] = qyl[k];
+      for (int k = 0; k < M; ++k) nxt[k] = pre[k];
+      apply_bc<R, P>(nxt, mx, mynext, es);
+    }
+    if (store && own)
+      combine_store<R, P, STAGE, KAHAN>(Out, Cout, (size_t)(r - 3) * nx + i, plane, Sc, Lv, dt, uq, uc);
   }
   const double speed = own ? max_nan((double)smx * (1.0 / G.dx), (double)smy * (1.0 / G.dy))
                            : (own_face ? (double)smx * (1.0 / G.dx) : 0.0);
@@ -220,12 +239,12 @@ __global__ __launch_bounds__(kLanes) void k_sharp1d(const GridDesc* __restrict__
   const bool own_face = lane >= H && lane <= H + U && i <= nx;
   const AxisMap mx = map_axis(i, nx, G.bc[0], G.bc[1], H);
   const AxisMap my{0, 0, 0};
-  const R* __restrict__ S = (const R*)(STAGE == 1 ? G.q[0] : (STAGE == 2 ? G.s1 : G.s2));
+  const gconst<R> S = as_gconst<R>(STAGE == 1 ? G.q[0] : (STAGE == 2 ? G.s1 : G.s2));
   const R eps = (R)G.weno_eps;
   const R rdx = (R)(1.0 / G.dx);
   const P phys(G);
   R c[M], xl[M], xr[M];
-  load_state<R, P>(c, S, (size_t)nx, nx, mx, my, G);
+  load_state<R, P>(c, S, (size_t)nx, nx, mx, my, edge_states<R, M>(G, mx));
 #pragma unroll
   for (int k = 0; k < M; ++k) {
     const R m1 = shfl_prev(c[k]), p1 = shfl_next(c[k]);
@@ -239,8 +258,11 @@ __global__ __launch_bounds__(kLanes) void k_sharp1d(const GridDesc* __restrict__
 #pragma unroll
   for (int k = 0; k < M; ++k) Lv[k] = -(shfl_next(F[k]) - F[k]) * rdx;
   R pq[M], pc[M];
-  load_point<R, M, STAGE, KAHAN>(G, (size_t)(i < 0 ? 0 : (i >= nx ? nx - 1 : i)), (size_t)nx, pq, pc);
-  if (own) combine_store<R, P, STAGE, KAHAN>(G, (size_t)i, (size_t)nx, c, Lv, dt, pq, pc);
+  load_point<R, M, STAGE, KAHAN>(as_gconst<R>(G.q[0]), as_gconst<R>(G.c[0]),
+                                 (size_t)(i < 0 ? 0 : (i >= nx ? nx - 1 : i)), (size_t)nx, pq, pc);
+  if (own)
+    combine_store<R, P, STAGE, KAHAN>(stage_out<R, STAGE>(G), as_gmut<R>(G.c[0]), (size_t)i,
+                                      (size_t)nx, c, Lv, dt, pq, pc);
   const double speed = own_face ? (double)sx * (1.0 / G.dx) : 0.0;
   stage_finish<STAGE>(ctrl, mode, speed, G.nblocks);
 }
