@@ -85,15 +85,53 @@ def timed_run(spec, q, aux, steps, warmup, t_end, tune=True, graph_k=16):
     return out
 
 
-def roofline(bytes_per_cell_step, cells, gpu_ms, launches, kernel_name, bytes_per_launch):
-    """Achieved algorithmic GB/s of the dominant kernel from the HIP-event
-    time of the timed region (gpu_ms over `launches` kernel launches)."""
+# Published MI355X peaks (dense, no sparsity): HBM3E bandwidth and vector
+# FP64 / FP32 rates (the FP32 figure counts packed dual FP32 issue).
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
+
+# Algorithmic work per unit, counted from the method's formulas (each add,
+# subtract, multiply, divide, square root, min, max or compare is one flop):
+#   sw       2D shallow water, classic, Roe + entropy-fix test, MC, full transverse:
+#            per cell-step 554 = 2 faces x (Roe solve 73 + limiter 46 +
+#            correction 32 + transverse split and accumulation 106) + cell
+#            primitives 4 + update 30 + Courant maxima 6
+#   euler    2D Euler SharpClaw, per cell and Runge-Kutta stage 1040 = 4
+#            components x 2 directions x WENO5 edge pair 100 + 2 faces x HLLE
+#            flux 102 + flux difference 20 + stage combination 12 + maxima 2
+# and the compulsory HBM bytes per unit (read stage inputs, write the output,
+# plus compensation and aux):
+#   sw 48 per cell-step (FP64 q; FP32 q + c); euler per stage 256/3 (FP64),
+#   160/3 (FP32+Kahan); elastic 104 (FP64), 92 (FP32+Kahan) per cell-step.
+FLOPS_PER_CELL = {"sw": 554.0, "euler_stage": 1040.0}
+
+
+def roofline(bound, cells, gpu_ms, launches, kernel_name, bytes_per_launch, flops_per_launch=None,
+             dtype="f64"):
+    """Roofline of the dominant kernel from the HIP-event time of the timed
+    region (gpu_ms over `launches` kernel launches).  bound "alu": achieved =
+    algorithmic flops per launch / launch time against the vector peak of the
+    dtype; bound "hbm": algorithmic bytes per launch / launch time against
+    8 TB/s.  The other figure is reported beside it."""
     avg_s = gpu_ms * 1e-3 / launches
-    achieved = bytes_per_launch / avg_s / 1e9
+    gbs = bytes_per_launch / avg_s / 1e9
     tr = measured_traffic(kernel_name)
-    return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=tr, kernel=kernel_name,
-                avg_launch_us=round(avg_s * 1e6, 2), algorithmic_bytes_per_cell=bytes_per_cell_step)
+    out = dict(kernel=kernel_name, avg_launch_us=round(avg_s * 1e6, 2),
+               algorithmic_bytes_per_launch=bytes_per_launch, traffic=tr)
+    if bound == "alu":
+        tf = flops_per_launch / avg_s / 1e12
+        peak = PEAK_TFLOPS[dtype]
+        out.update(bound="alu", achieved=round(tf, 3), peak=peak, unit="TFLOP/s",
+                   frac=round(tf / peak, 4), algorithmic_flops_per_launch=flops_per_launch,
+                   hbm=dict(achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                            frac=round(gbs / HBM_PEAK_GBS, 4)))
+    else:
+        out.update(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                   frac=round(gbs / HBM_PEAK_GBS, 4))
+        if flops_per_launch:
+            tf = flops_per_launch / avg_s / 1e12
+            out["alu"] = dict(achieved=round(tf, 3), peak=PEAK_TFLOPS[dtype], unit="TFLOP/s",
+                              frac=round(tf / PEAK_TFLOPS[dtype], 4))
+    return out
 
 
 def l1_error_fp32(spec_fn, n, t_end):
@@ -213,8 +251,9 @@ def main():
                                "device-controlled steps toward t=1.0",
                    "cells": h["cells"], "seg_rows": h["seg_rows"], "parallelism": "single GPU"},
     }
-    line["roofline"] = roofline(48, h["cells"], h["gpu_ms"], h["steps"] + h["rejected"],
-                                "k_classic2d<double,ShallowWater>", 48 * h["cells"])
+    line["roofline"] = roofline("alu", h["cells"], h["gpu_ms"], h["steps"] + h["rejected"],
+                                "k_classic2d<double,ShallowWater>", 48 * h["cells"],
+                                FLOPS_PER_CELL["sw"] * h["cells"], "f64")
     line["kernel_isolated_us"] = round(h["kernel_ms"] * 1e3, 2)
 
     if not a.no_extras:
@@ -223,17 +262,19 @@ def main():
         f = timed_run(dict(spec, precision="fp32_kahan"), q, None, a.steps, a.warmup, 1.0)
         f["l1_err_vs_fp64_oracle"] = l1_error_fp32(lambda n: W.radial_dam_break(n), 256, 0.25)
         f["l1_err_sample"] = "256x256 to t=0.25, oracle dt sequence"
-        f["roofline"] = roofline(48, f["cells"], f["gpu_ms"], f["steps"] + f["rejected"],
-                                 "k_classic2d<float,ShallowWater,Kahan>", 48 * f["cells"])
+        f["roofline"] = roofline("alu", f["cells"], f["gpu_ms"], f["steps"] + f["rejected"],
+                                 "k_classic2d<float,ShallowWater,Kahan>", 48 * f["cells"],
+                                 FLOPS_PER_CELL["sw"] * f["cells"], "f32")
         extras["sw_radial_1024_fp32_kahan"] = f
 
         log("shock-bubble 2048x1024 SharpClaw FP64 / FP32")
         sb_spec, sb_q = W.shock_bubble(2048, 1024)
         for prec, bpc in (("fp64", 256), ("fp32_kahan", 160)):
             r = timed_run(dict(sb_spec, precision=prec), sb_q, None, 40, 5, 1.0)
-            r["roofline"] = roofline(bpc, r["cells"], r["gpu_ms"], 3 * (r["steps"] + r["rejected"]),
+            r["roofline"] = roofline("alu", r["cells"], r["gpu_ms"], 3 * (r["steps"] + r["rejected"]),
                                      f"k_sharp2d<{'double' if prec == 'fp64' else 'float'},EulerHLLE>",
-                                     bpc * r["cells"] / 3.0)
+                                     bpc * r["cells"] / 3.0, FLOPS_PER_CELL["euler_stage"] * r["cells"],
+                                     "f64" if prec == "fp64" else "f32")
             if prec == "fp32_kahan":
                 r["l1_err_vs_fp64_oracle"] = l1_error_fp32(lambda n: W.shock_bubble(2 * n, n), 128, 0.1)
                 r["l1_err_sample"] = "256x128 to t=0.1 (shock through the bubble), oracle dt sequence"
@@ -243,7 +284,7 @@ def main():
         el_spec, el_q, el_aux = W.layered_elastic(2048)
         for prec, bpc in (("fp32_kahan", 92), ("fp64", 104)):
             r = timed_run(dict(el_spec, precision=prec), el_q, el_aux, 100, 10, 10.0)
-            r["roofline"] = roofline(bpc, r["cells"], r["gpu_ms"], r["steps"] + r["rejected"],
+            r["roofline"] = roofline("hbm", r["cells"], r["gpu_ms"], r["steps"] + r["rejected"],
                                      f"k_classic2d<{'float' if prec != 'fp64' else 'double'},Elastic>",
                                      bpc * r["cells"])
             extras[f"elastic_layered_2048_{prec}"] = r

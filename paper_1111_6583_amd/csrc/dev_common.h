@@ -225,20 +225,33 @@ __device__ inline bool ctrl_decide(Ctrl* c, double speed) {
 // slot; the last workgroup of the launch (over this grid) reads the total,
 // hands it to `decide` (the device controller, or just recording it for the
 // host controller), and clears the slot and counter for the next launch.
+//
+// Ordering without fences: both atomics are device-scope read-modify-writes
+// on one cache line, performed at the device's coherence point.  A workgroup
+// issues its counter increment only after its maximum has returned (the
+// increment's operand depends on the returned value), so whoever sees the
+// final count sees every maximum.  No release/acquire fence is used: on this
+// GPU a device-scope fence writes back and invalidates the whole L2 of the
+// XCD, which every workgroup would do at once at the end of each launch.
+// The controller fields the last workgroup writes with plain stores are read
+// by the next launch (kernel boundaries order them).
 template <class Decide>
 __device__ inline void finish_workgroup(Ctrl* c, double local_max, int nblocks, Decide decide) {
   local_max = wave_max(local_max);   // NaN-preserving: NaN bits compare above every finite speed
   if (threadIdx.x == 0) {
-    atomicMax(&c->speed_bits, dbits(local_max));
-    __threadfence();
-    const unsigned int done = atomicAdd(&c->counter, 1u);
+    CLAW_GLOBAL Ctrl* g = (CLAW_GLOBAL Ctrl*)c;
+    const unsigned long long prev = __hip_atomic_fetch_max(
+        &g->speed_bits, dbits(local_max), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned int one = 1u;
+    asm volatile("" : "+v"(one) : "v"(prev));
+    const unsigned int done =
+        __hip_atomic_fetch_add(&g->counter, one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (done == (unsigned int)(nblocks - 1)) {
-      __threadfence();
-      const double speed = bitsd(atomicAdd(&c->speed_bits, 0ull));
+      const double speed = bitsd(
+          __hip_atomic_fetch_add(&g->speed_bits, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
       decide(c, speed);
-      atomicExch(&c->speed_bits, 0ull);
-      atomicExch(&c->counter, 0u);
-      __threadfence();
+      __hip_atomic_store(&g->speed_bits, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&g->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }
