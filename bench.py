@@ -151,20 +151,76 @@ def l1_error_fp32(spec_fn, n, t_end):
     return [float(np.sum(np.abs(g[k] - qo[k])) / np.sum(np.abs(qo[k]))) for k in range(q.shape[0])]
 
 
-def cpu_baseline(spec, q, steps):
-    """The FP64 oracle on the host cores, a bounded sample of the workload."""
+def cpu_baseline(spec, q, steps, steps_1t):
+    """The FP64 oracle on the host cores, a bounded sample of the workload:
+    `steps` steps with every core of the process, then `steps_1t` with one."""
     import oracle
     dt = 0.9 / oracle.max_cell_speed(spec, q)
     oracle.step(spec, q, dt)   # warm (page in, thread pool)
-    t0 = time.perf_counter()
-    qq = q
-    for _ in range(steps):
-        qq, sp = oracle.step(spec, qq, dt)
-    wall = time.perf_counter() - t0
+
+    def run(n):
+        t0 = time.perf_counter()
+        qq = q
+        for _ in range(n):
+            qq, sp = oracle.step(spec, qq, dt)
+        return time.perf_counter() - t0
+
+    cores = oracle.num_threads()
+    wall = run(steps)
     cells = q.shape[1] * q.shape[2]
-    return dict(value=cells * steps / wall, unit="cell-updates/s", cores=oracle.num_threads(),
-                kind="oracle", sample=f"{steps} steps of the {q.shape[2]}x{q.shape[1]} grid, FP64, "
-                                      f"{oracle.cpu_model()}", wall_s=round(wall, 2))
+    out = dict(value=cells * steps / wall, unit="cell-updates/s", cores=cores, kind="oracle",
+               sample=f"{steps} steps of the {q.shape[2]}x{q.shape[1]} grid, FP64, {oracle.cpu_model()}",
+               wall_s=round(wall, 2))
+    if steps_1t > 0:
+        oracle.set_threads(1)
+        w1 = run(steps_1t)
+        oracle.set_threads(cores)
+        out["single_thread"] = dict(value=cells * steps_1t / w1, steps=steps_1t, wall_s=round(w1, 2))
+    return out
+
+
+def mall_sweep(sizes, steps):
+    """Shallow-water FP64 step at grids larger than the 256 MB Infinity Cache
+    (state ping-pong 48 B/cell), for a true HBM fraction."""
+    from paper_1111_6583_amd import workloads as W
+    out = {}
+    for n in sizes:
+        spec, q = W.radial_dam_break(n)
+        r = timed_run(spec, q, None, steps, 3, 1.0)
+        r["roofline"] = roofline("alu", r["cells"], r["gpu_ms"], r["steps"] + r["rejected"],
+                                 "k_classic2d<double,ShallowWater>", 48 * r["cells"],
+                                 FLOPS_PER_CELL["sw"] * r["cells"], "f64")
+        r["state_mb"] = round(2 * 24 * r["cells"] / 1e6, 1)
+        out[f"sw_radial_{n}_fp64"] = r
+    spec, q = W.shock_bubble(4096, 2048)
+    r = timed_run(spec, q, None, 5, 2, 1.0)
+    r["roofline"] = roofline("alu", r["cells"], r["gpu_ms"], 3 * (r["steps"] + r["rejected"]),
+                             "k_sharp2d<double,EulerHLLE>", 256 * r["cells"] / 3.0,
+                             FLOPS_PER_CELL["euler_stage"] * r["cells"], "f64")
+    r["state_mb"] = round(3 * 32 * r["cells"] / 1e6, 1)
+    out["euler_shock_bubble_4096x2048_fp64"] = r
+    return out
+
+
+def host_controller(spec, q, steps):
+    """The headline workload stepped by the host controller (claw_advance:
+    one launch per attempt, the Courant number read back every step)."""
+    import torch
+    from paper_1111_6583_amd import Solver
+    s = Solver(spec)
+    s.set_state(q)
+    seg = s.autotune(reps=3)
+    s.advance(1.0, max_steps=5, graph=False)
+    c0 = s.clock()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = s.advance(1.0, max_steps=steps, graph=False)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    acc = st["accepted"] - c0["accepted"]
+    s.close()
+    return dict(steps=acc, seg_rows=seg, wall_s=wall, ms_per_step=1e3 * wall / max(acc, 1),
+                value=q.shape[1] * q.shape[2] * acc / wall)
 
 
 WORKLOADS = {
@@ -215,7 +271,8 @@ def main():
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--cpu-steps", type=int, default=40)
+    ap.add_argument("--cpu-steps-1t", type=int, default=2)
     ap.add_argument("--serve-requests", type=int, default=400)
     ap.add_argument("--mode", choices=["bench", "kernel", "copy"], default="bench",
                     help="kernel/copy: launch only one kernel (for rocprofv3 counter runs)")
@@ -322,10 +379,14 @@ def main():
             throughput_req_s=r["throughput_req_s"], cell_updates_per_s=r["cell_updates_per_s"],
             wall_s=r["wall"], max_resident=r["max_resident"], precision="fp32_kahan",
             budget_gib=8, note="latency = completion (result on host) - scheduled arrival")
+        log("host-controller mode (headline workload)")
+        extras["sw_radial_1024_fp64_host_controller"] = host_controller(spec, q, 100)
+        log("size sweep beyond the Infinity Cache")
+        extras.update(mall_sweep((2048, 4096, 8192), 20))
         line["extras"] = extras
 
     log("cpu baseline (oracle)")
-    line["cpu_baseline"] = cpu_baseline(spec, q, a.cpu_steps)
+    line["cpu_baseline"] = cpu_baseline(spec, q, a.cpu_steps, a.cpu_steps_1t)
     print(json.dumps(line), flush=True)
 
 

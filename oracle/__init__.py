@@ -89,6 +89,8 @@ def _load():
     lib.or_totals.argtypes = [cp, dp, dp]
     lib.or_num_threads.argtypes = []
     lib.or_num_threads.restype = C.c_int
+    lib.or_set_threads.argtypes = [C.c_int]
+    lib.or_set_threads.restype = None
     for f in ("or_num_eqn", "or_num_waves", "or_num_aux"):
         getattr(lib, f).argtypes = [cp]
         getattr(lib, f).restype = C.c_int
@@ -264,6 +266,11 @@ def totals(spec, q):
     tot = np.zeros(m)
     _load().or_totals(C.byref(c), _ptr(q), _ptr(tot))
     return tot
+
+
+def set_threads(n: int) -> None:
+    """Use n OpenMP threads in later oracle calls."""
+    _load().or_set_threads(int(n))
 
 
 def num_threads() -> int:

@@ -850,6 +850,16 @@ int or_num_threads() {
 #endif
 }
 
+// Number of OpenMP threads used by later calls (n >= 1; timing of the
+// single-thread baseline).  No effect without OpenMP.
+void or_set_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 int or_num_eqn(const OCfg* c) { return num_eqn(*c); }
 int or_num_waves(const OCfg* c) { return num_waves(*c); }
 int or_num_aux(const OCfg* c) { return num_aux(*c); }
