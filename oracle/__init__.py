@@ -39,6 +39,7 @@ SOLVERS = {"advection": 1, "sw_roe": 2, "euler_hlle": 3, "elastic_vc": 4}
 LIMITERS = {"none": 0, "minmod": 1, "mc": 2}
 BCS = {"extrap": 1, "periodic": 2, "wall": 3, "dirichlet": 4}
 SIDES = ("x_lower", "x_upper", "y_lower", "y_upper")
+INTEGRATORS = {"ssp33": 1, "ssp104": 2}
 
 
 class OCfg(C.Structure):
@@ -48,6 +49,7 @@ class OCfg(C.Structure):
         ("scheme", C.c_int), ("solver", C.c_int), ("limiter", C.c_int),
         ("transverse", C.c_int), ("efix", C.c_int), ("bc", C.c_int * 4),
         ("bcstate", (C.c_double * 8) * 4), ("weno_eps", C.c_double), ("pd", C.c_double * 8),
+        ("integrator", C.c_int), ("weno_order", C.c_int),
     ]
 
 
@@ -84,6 +86,12 @@ def _load():
     lib.or_num_flux.argtypes = [cp, C.c_int, dp, dp, dp]
     lib.or_num_flux.restype = C.c_double
     lib.or_weno5.argtypes = [dp, C.c_double, dp, dp]
+    lib.or_weno_r.argtypes = [C.c_int, dp, C.c_double, dp, dp]
+    lib.or_weno_r.restype = C.c_int
+    lib.or_weno_linear_weights.argtypes = [C.c_int, dp]
+    lib.or_weno_linear_weights.restype = C.c_int
+    lib.or_ssp_riccati.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int]
+    lib.or_ssp_riccati.restype = C.c_double
     lib.or_limiter.argtypes = [C.c_int, C.c_double]
     lib.or_limiter.restype = C.c_double
     lib.or_totals.argtypes = [cp, dp, dp]
@@ -132,6 +140,8 @@ def make_cfg(spec: dict) -> OCfg:
             for k, v in enumerate(vals):
                 c.bcstate[s][k] = float(v)
     c.weno_eps = float(spec.get("weno_eps", 1e-6))
+    c.integrator = INTEGRATORS[spec.get("time_integrator", "ssp33")]
+    c.weno_order = int(spec.get("weno_order", 5))
     for k, v in enumerate(spec.get("problem_data", [])):
         c.pd[k] = float(v)
     return c
@@ -255,6 +265,29 @@ def weno5(v, eps=1e-6):
     qL, qR = C.c_double(), C.c_double()
     _load().or_weno5(_ptr(v), float(eps), C.byref(qL), C.byref(qR))
     return qL.value, qR.value
+
+
+def weno_r(r, v, eps=1e-6):
+    """WENO of order 2r-1 from 2r-1 cell averages centred on a cell: (qL, qR)
+    at its right and left edges (general construction)."""
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    assert v.size == 2 * r - 1
+    qL, qR = C.c_double(), C.c_double()
+    if _load().or_weno_r(int(r), _ptr(v), float(eps), C.byref(qL), C.byref(qR)) != 0:
+        raise ValueError("r out of range")
+    return qL.value, qR.value
+
+
+def weno_linear_weights(r):
+    d = np.zeros(r)
+    if _load().or_weno_linear_weights(int(r), _ptr(d)) != 0:
+        raise ValueError("r out of range")
+    return d
+
+
+def ssp_riccati(integrator, y0, T, n):
+    """The SharpClaw step's integrator applied to y' = 1 - y^2, n steps to T."""
+    return _load().or_ssp_riccati(INTEGRATORS[integrator], float(y0), float(T), int(n))
 
 
 def limiter(name, theta):

@@ -10,8 +10,11 @@
 //     (eq. lwflux: F = F_upwind + F_correction, first-order part written as
 //     fluctuations) and, in 2D, the unsplit transverse corrections computed by
 //     a secondary "transverse" Riemann solver;
-//   * SharpClaw method of lines: WENO5 edge values, an interface Riemann flux
-//     and flux differencing (eq. fluxdiff), inside SSP Runge-Kutta stages.
+//   * SharpClaw method of lines: WENO edge values (fifth order, or any odd
+//     order 2r-1 from the general definition), an interface Riemann flux and
+//     flux differencing (eq. fluxdiff), inside SSP Runge-Kutta stages
+//     (Shu-Osher SSPRK(3,3), or the ten-stage fourth-order SSP method with a
+//     two-register implementation that SharpClaw uses by default).
 //
 // The paper prints none of the Riemann solvers, limiters, WENO weights or RK
 // coefficients; it defers to LeVeque (1997, 2002), Jiang-Shu and Shu-Osher.
@@ -52,6 +55,8 @@ struct OCfg {
   double bcstate[4][8];// Dirichlet state per side
   double weno_eps;     // WENO epsilon
   double pd[8];        // problem data: advection (u, v); shallow water (g); Euler (gamma)
+  int integrator;      // SharpClaw: 0/1 SSPRK(3,3), 2 SSPRK(10,4)
+  int weno_order;      // SharpClaw: 0/5 WENO5, or 2r-1 for r = 3..9
 };
 
 }  // extern "C"
@@ -653,6 +658,194 @@ void weno5(const double* v, double eps, double* qL, double* qR) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// WENO of order 2r-1 (Jiang-Shu construction for any r; PyWENO generates the
+// same tables symbolically), written from its definition with cell width 1
+// and cell i = [-1/2, 1/2]:
+//   * candidate k = 0..r-1 is the polynomial of degree r-1 whose averages over
+//     cells i-r+1+k .. i+k equal the data; its values at x = +1/2 and -1/2
+//     are linear in the data (coefficient tables cR, cL);
+//   * the linear weights d_k make sum_k d_k p_k(+1/2) equal the value of the
+//     degree-(2r-2) polynomial through all 2r-1 averages (consistency);
+//     the left edge uses the mirrored weights d_{r-1-k};
+//   * beta_k = sum_{l=1}^{r-1} integral over the cell of (d^l p_k / dx^l)^2,
+//     a quadratic form in the stencil's data (matrix B_k);
+//   * omega_k = alpha_k / sum alpha, alpha_k = d_k / (eps + beta_k)^2.
+// The tables are computed once per r, in long double, by solving the small
+// interpolation systems and integrating the squared derivatives exactly.
+// ---------------------------------------------------------------------------
+struct WenoTables {
+  int r = 0;
+  double cR[9][9], cL[9][9];   // [k][j]: value at +1/2 / -1/2 from data of stencil k, j = 0..r-1
+  double d[9];                 // linear weights, right edge
+  double B[9][9][9];           // [k][a][b]: beta_k = sum_ab B v_a v_b over stencil k
+};
+
+// Coefficients a_n of p(x) = sum a_n x^n (n < r) from r cell averages at
+// cells c0 .. c0+r-1 (cell j = [j-1/2, j+1/2]): returns the matrix M with
+// a = M v.
+static void interp_matrix(int r, int c0, long double M[9][9]) {
+  long double A[9][18];
+  for (int row = 0; row < r; ++row) {
+    const long double lo = c0 + row - 0.5L, hi = c0 + row + 0.5L;
+    long double plo = lo, phi = hi;   // lo^(n+1), hi^(n+1)
+    for (int n = 0; n < r; ++n) {
+      A[row][n] = (phi - plo) / (n + 1);
+      plo *= lo;
+      phi *= hi;
+    }
+    for (int n = 0; n < r; ++n) A[row][r + n] = row == n ? 1.0L : 0.0L;
+  }
+  // Gauss-Jordan with partial pivoting: A = [V | I] -> [I | V^-1]
+  for (int col = 0; col < r; ++col) {
+    int piv = col;
+    for (int row = col + 1; row < r; ++row)
+      if (std::fabs(A[row][col]) > std::fabs(A[piv][col])) piv = row;
+    for (int n = 0; n < 2 * r; ++n) std::swap(A[col][n], A[piv][n]);
+    const long double inv = 1.0L / A[col][col];
+    for (int n = 0; n < 2 * r; ++n) A[col][n] *= inv;
+    for (int row = 0; row < r; ++row) {
+      if (row == col) continue;
+      const long double f = A[row][col];
+      for (int n = 0; n < 2 * r; ++n) A[row][n] -= f * A[col][n];
+    }
+  }
+  for (int n = 0; n < r; ++n)
+    for (int j = 0; j < r; ++j) M[n][j] = A[n][r + j];
+}
+
+static long double poly_at(int r, const long double* a, long double x) {
+  long double s = 0.0L;
+  for (int n = r - 1; n >= 0; --n) s = s * x + a[n];
+  return s;
+}
+
+static const WenoTables& weno_tables(int r) {
+  static WenoTables T[10];
+  static bool done[10] = {false};
+  WenoTables& t = T[r];
+  if (done[r]) return t;
+#pragma omp critical(weno_tables)
+  if (!done[r]) {
+    t.r = r;
+    long double cR[9][9], cL[9][9];
+    for (int k = 0; k < r; ++k) {
+      long double M[9][9];
+      interp_matrix(r, -(r - 1) + k, M);
+      for (int j = 0; j < r; ++j) {
+        long double a[9];
+        for (int n = 0; n < r; ++n) a[n] = M[n][j];
+        cR[k][j] = poly_at(r, a, 0.5L);
+        cL[k][j] = poly_at(r, a, -0.5L);
+        t.cR[k][j] = (double)cR[k][j];
+        t.cL[k][j] = (double)cL[k][j];
+      }
+      // beta_k quadratic form: derivative l of the monomial basis, squared,
+      // integrated over [-1/2, 1/2]
+      for (int a = 0; a < r; ++a)
+        for (int b = 0; b < r; ++b) {
+          long double sum = 0.0L;
+          for (int l = 1; l < r; ++l)
+            for (int n = l; n < r; ++n)
+              for (int m = l; m < r; ++m) {
+                // d^l x^n = n!/(n-l)! x^(n-l)
+                long double fn = 1.0L, fm = 1.0L;
+                for (int q = 0; q < l; ++q) { fn *= (n - q); fm *= (m - q); }
+                const int e = (n - l) + (m - l);   // integral of x^e over the cell
+                const long double ie = (std::pow(0.5L, e + 1) - std::pow(-0.5L, e + 1)) / (e + 1);
+                sum += M[n][a] * M[m][b] * fn * fm * ie;
+              }
+          t.B[k][a][b] = (double)sum;
+        }
+    }
+    // big stencil: degree 2r-2 through the averages of cells -(r-1) .. r-1
+    const int R2 = 2 * r - 1;
+    long double big[17];
+    {
+      long double A[17][34];
+      for (int row = 0; row < R2; ++row) {
+        const long double lo = -(r - 1) + row - 0.5L, hi = -(r - 1) + row + 0.5L;
+        long double plo = lo, phi = hi;
+        for (int n = 0; n < R2; ++n) {
+          A[row][n] = (phi - plo) / (n + 1);
+          plo *= lo;
+          phi *= hi;
+        }
+        for (int n = 0; n < R2; ++n) A[row][R2 + n] = row == n ? 1.0L : 0.0L;
+      }
+      for (int col = 0; col < R2; ++col) {
+        int piv = col;
+        for (int row = col + 1; row < R2; ++row)
+          if (std::fabs(A[row][col]) > std::fabs(A[piv][col])) piv = row;
+        for (int n = 0; n < 2 * R2; ++n) std::swap(A[col][n], A[piv][n]);
+        const long double inv = 1.0L / A[col][col];
+        for (int n = 0; n < 2 * R2; ++n) A[col][n] *= inv;
+        for (int row = 0; row < R2; ++row) {
+          if (row == col) continue;
+          const long double f = A[row][col];
+          for (int n = 0; n < 2 * R2; ++n) A[row][n] -= f * A[col][n];
+        }
+      }
+      // value at +1/2 as a functional of the data: sum_n (1/2)^n M[n][j]
+      for (int j = 0; j < R2; ++j) {
+        long double s = 0.0L, x = 1.0L;
+        for (int n = 0; n < R2; ++n) { s += x * A[n][R2 + j]; x *= 0.5L; }
+        big[j] = s;
+      }
+    }
+    // consistency: sum_k d_k cR[k][j - k] = big[j]; data cell j of the big
+    // stencil is cell j - k of candidate k.  Triangular in k for j < r.
+    long double dd[9];
+    for (int j = 0; j < r; ++j) {
+      long double s = big[j];
+      for (int k = 0; k < j; ++k) s -= dd[k] * cR[k][j - k];
+      dd[j] = s / cR[j][0];
+    }
+    for (int k = 0; k < r; ++k) t.d[k] = (double)dd[k];
+    done[r] = true;
+  }
+  return t;
+}
+
+// Edge values of cell i from the 2r-1 averages v[0..2r-2] centred on it
+// (v[r-1] = cell i): qL at its right edge, qR at its left edge.
+void weno_r(int r, const double* v, double eps, double* qL, double* qR) {
+  const WenoTables& t = weno_tables(r);
+  double beta[9], pR[9], pL[9];
+  for (int k = 0; k < r; ++k) {
+    const double* s = v + k;   // stencil k: v[k .. k+r-1]
+    double b = 0.0, a = 0.0, c = 0.0;
+    for (int i = 0; i < r; ++i) {
+      a += t.cR[k][i] * s[i];
+      c += t.cL[k][i] * s[i];
+      for (int j = 0; j < r; ++j) b += t.B[k][i][j] * s[i] * s[j];
+    }
+    beta[k] = b;
+    pR[k] = a;
+    pL[k] = c;
+  }
+  double sR = 0.0, sL = 0.0, nR = 0.0, nL = 0.0;
+  for (int k = 0; k < r; ++k) {
+    const double w = 1.0 / ((eps + beta[k]) * (eps + beta[k]));
+    const double aR = t.d[k] * w, aL = t.d[r - 1 - k] * w;
+    sR += aR; nR += aR * pR[k];
+    sL += aL; nL += aL * pL[k];
+  }
+  *qL = nR / sR;
+  *qR = nL / sL;
+}
+
+// Half-width of the reconstruction stencil (= ghost layers) of a config.
+int weno_r_of(const OCfg& c) { return c.weno_order >= 7 ? (c.weno_order + 1) / 2 : 3; }
+
+// Edge values of one cell from 2r-1 averages: WENO5 through its closed form,
+// other orders through the general construction.
+void weno_edges(const OCfg& c, const double* v, double* qL, double* qR) {
+  const int r = weno_r_of(c);
+  if (r == 3) weno5(v, c.weno_eps, qL, qR);
+  else weno_r(r, v, c.weno_eps, qL, qR);
+}
+
 // Physical flux in direction d.
 void euler_flux(const OCfg& c, int d, const double* q, double* f, double* un_out, double* cs_out) {
   const double gam = c.pd[0];
@@ -720,8 +913,9 @@ double num_flux(const OCfg& c, int d, const double* ql, const double* qr, double
 double sharpclaw_L(const OCfg& c, const double* qin, double* L) {
   const int m = num_eqn(c), nx = c.nx, ny = c.ny;
   const double dx = dx_of(c), dy = dy_of(c);
+  const int r = weno_r_of(c), w = 2 * r - 1;
   Field Q;
-  load_field(c, Q, qin, m, 3, false);
+  load_field(c, Q, qin, m, r, false);
   std::fill(L, L + (size_t)m * nx * ny, 0.0);
   double smax = 0.0;
   // x direction: one row at a time
@@ -731,9 +925,9 @@ double sharpclaw_L(const OCfg& c, const double* qin, double* L) {
     std::vector<double> eL((size_t)(nx + 2) * m), eR((size_t)(nx + 2) * m);
     for (int i = -1; i <= nx; ++i)
       for (int k = 0; k < m; ++k) {
-        double v[5];
-        for (int s = 0; s < 5; ++s) v[s] = Q.at(k, j, i - 2 + s);
-        weno5(v, c.weno_eps, &eL[(size_t)(i + 1) * m + k], &eR[(size_t)(i + 1) * m + k]);
+        double v[17];
+        for (int s = 0; s < w; ++s) v[s] = Q.at(k, j, i - (r - 1) + s);
+        weno_edges(c, v, &eL[(size_t)(i + 1) * m + k], &eR[(size_t)(i + 1) * m + k]);
       }
     std::vector<double> Fx((size_t)(nx + 1) * m);
     for (int f = 0; f <= nx; ++f) {
@@ -755,9 +949,9 @@ double sharpclaw_L(const OCfg& c, const double* qin, double* L) {
       std::vector<double> eL((size_t)(ny + 2) * m), eR((size_t)(ny + 2) * m);
       for (int j = -1; j <= ny; ++j)
         for (int k = 0; k < m; ++k) {
-          double v[5];
-          for (int s = 0; s < 5; ++s) v[s] = Q.at(k, j - 2 + s, i);
-          weno5(v, c.weno_eps, &eL[(size_t)(j + 1) * m + k], &eR[(size_t)(j + 1) * m + k]);
+          double v[17];
+          for (int s = 0; s < w; ++s) v[s] = Q.at(k, j - (r - 1) + s, i);
+          weno_edges(c, v, &eL[(size_t)(j + 1) * m + k], &eR[(size_t)(j + 1) * m + k]);
         }
       std::vector<double> Gy((size_t)(ny + 1) * m);
       for (int g = 0; g <= ny; ++g) {
@@ -777,18 +971,52 @@ double sharpclaw_L(const OCfg& c, const double* qin, double* L) {
   return smax;
 }
 
-// SSPRK(3,3) of Shu and Osher.  The Courant number is taken from the speeds
-// of the first stage (at Q^n).
-double sharpclaw_step(const OCfg& c, const double* qin, double* qout, double dt) {
-  const size_t N = (size_t)num_eqn(c) * c.nx * c.ny;
-  std::vector<double> L(N), Q1(N), Q2(N);
-  const double smax = sharpclaw_L(c, qin, L.data());
+// SSP Runge-Kutta integrators over a semi-discrete operator Lop(q, out)
+// (out = L(q); returns the largest speed/spacing, used from the first
+// evaluation only: the Courant number is measured at Q^n).
+//   SSPRK(3,3) (Shu-Osher):  Q1 = Q + dt L(Q);  Q2 = 3/4 Q + 1/4 (Q1 + dt L(Q1));
+//                            Q^{n+1} = 1/3 Q + 2/3 (Q2 + dt L(Q2)).
+//   SSPRK(10,4) (Ketcheson 2008, two-register form, SSP coefficient 6):
+//     q1 = q2 = Q;  five times q1 += dt/6 L(q1);  q2 = q2/25 + 9/25 q1;
+//     q1 = 15 q2 - 5 q1;  four times q1 += dt/6 L(q1);
+//     Q^{n+1} = q2 + 3/5 q1 + dt/10 L(q1).
+template <class Op>
+double ssp_step(int integrator, Op&& Lop, size_t N, const double* qin, double* qout, double dt) {
+  std::vector<double> L(N);
+  if (integrator == 2) {
+    std::vector<double> q1(qin, qin + N), q2(qin, qin + N);
+    double smax = 0.0;
+    for (int s = 0; s < 5; ++s) {
+      const double sp = Lop(q1.data(), L.data());
+      if (s == 0) smax = sp;
+      for (size_t n = 0; n < N; ++n) q1[n] = q1[n] + dt / 6.0 * L[n];
+    }
+    for (size_t n = 0; n < N; ++n) {
+      q2[n] = q2[n] / 25.0 + 9.0 / 25.0 * q1[n];
+      q1[n] = 15.0 * q2[n] - 5.0 * q1[n];
+    }
+    for (int s = 0; s < 4; ++s) {
+      Lop(q1.data(), L.data());
+      for (size_t n = 0; n < N; ++n) q1[n] = q1[n] + dt / 6.0 * L[n];
+    }
+    Lop(q1.data(), L.data());
+    for (size_t n = 0; n < N; ++n) qout[n] = q2[n] + 3.0 / 5.0 * q1[n] + dt / 10.0 * L[n];
+    return smax;
+  }
+  std::vector<double> Q1(N), Q2(N);
+  const double smax = Lop(qin, L.data());
   for (size_t n = 0; n < N; ++n) Q1[n] = qin[n] + dt * L[n];
-  sharpclaw_L(c, Q1.data(), L.data());
+  Lop(Q1.data(), L.data());
   for (size_t n = 0; n < N; ++n) Q2[n] = 0.75 * qin[n] + 0.25 * (Q1[n] + dt * L[n]);
-  sharpclaw_L(c, Q2.data(), L.data());
+  Lop(Q2.data(), L.data());
   for (size_t n = 0; n < N; ++n) qout[n] = qin[n] / 3.0 + 2.0 / 3.0 * (Q2[n] + dt * L[n]);
   return smax;
+}
+
+double sharpclaw_step(const OCfg& c, const double* qin, double* qout, double dt) {
+  const size_t N = (size_t)num_eqn(c) * c.nx * c.ny;
+  return ssp_step(c.integrator, [&](const double* q, double* L) { return sharpclaw_L(c, q, L); },
+                  N, qin, qout, dt);
 }
 
 double one_step(const OCfg& c, const double* qin, const double* aux, double* qout, double dt) {
@@ -954,6 +1182,36 @@ double or_num_flux(const OCfg* c, int d, const double* ql, const double* qr, dou
 }
 
 void or_weno5(const double* v, double eps, double* qL, double* qR) { weno5(v, eps, qL, qR); }
+
+// General WENO of order 2r-1 (3 <= r <= 9) from 2r-1 averages.
+int or_weno_r(int r, const double* v, double eps, double* qL, double* qR) {
+  if (r < 2 || r > 9) return -1;
+  weno_r(r, v, eps, qL, qR);
+  return 0;
+}
+
+// Linear weights of WENO order 2r-1 (right edge), r entries.
+int or_weno_linear_weights(int r, double* d) {
+  if (r < 2 || r > 9) return -1;
+  const WenoTables& t = weno_tables(r);
+  for (int k = 0; k < r; ++k) d[k] = t.d[k];
+  return 0;
+}
+
+// The SSP integrator of the SharpClaw step applied to the scalar Riccati
+// equation y' = 1 - y^2 (exact solution tanh(t + atanh(y0))): n steps of
+// size T/n from y0.  Pins the integrators' order on a nonlinear problem.
+double or_ssp_riccati(int integrator, double y0, double T, int n) {
+  double y = y0;
+  const double dt = T / n;
+  for (int s = 0; s < n; ++s) {
+    double out;
+    ssp_step(integrator, [](const double* q, double* L) { L[0] = 1.0 - q[0] * q[0]; return 0.0; },
+             1, &y, &out, dt);
+    y = out;
+  }
+  return y;
+}
 
 double or_limiter(int lim, double theta) { return limiter_phi(lim, theta); }
 

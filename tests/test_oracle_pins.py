@@ -184,9 +184,9 @@ def test_conservation_elastic_periodic():
 # --------------------------------------------------------------------------
 # P5 / P6: measured convergence order on smooth data
 # --------------------------------------------------------------------------
-def _adv1d_error(n, scheme, lim="none", tfinal=1.0, dt_rule=None):
+def _adv1d_error(n, scheme, lim="none", tfinal=1.0, dt_rule=None, **extra):
     s = spec1d("advection", n, 0.0, 1.0, scheme=scheme, limiter=lim, bc_lower=("periodic",),
-               bc_upper=("periodic",), problem_data=[1.0])
+               bc_upper=("periodic",), problem_data=[1.0], **extra)
     x = (np.arange(n) + 0.5) / n
     dx = 1.0 / n
     # exact cell averages of sin(2 pi x)
@@ -258,6 +258,136 @@ def test_sharpclaw_linear_2d_high_order():
             q, _ = oracle.step(s, q, dt)
         errs.append(np.sum(np.abs(q[0] - avg(0.25, 0.125))) * h * h)
     assert math.log2(errs[0] / errs[1]) > 4.5, errs
+
+
+def test_sharpclaw_ssp104_fifth_order_1d():
+    # the ten-stage fourth-order integrator with WENO5: dt ~ dx^(5/4) keeps
+    # the time error O(dx^5)
+    ns = [20, 40, 80]
+    e = [_adv1d_error(n, "sharpclaw", tfinal=0.5, dt_rule=lambda dx: 1.5 * dx ** 1.25,
+                      time_integrator="ssp104") for n in ns]
+    rates = [math.log2(e[i] / e[i + 1]) for i in range(2)]
+    assert min(rates) > 4.7, (e, rates)
+
+
+@pytest.mark.parametrize("eps,gate", [(1e3, 6.8), (1e-6, 5.8)])
+def test_sharpclaw_weno7_seventh_order_1d(eps, gate):
+    # WENO7 + SSPRK(10,4), dt ~ dx^(7/4) keeps the time error O(dx^7).  With
+    # eps >> beta the weights are the linear ones: order 7.  With eps = 1e-6
+    # the Jiang-Shu weights lose some order at the sine's critical points
+    # (about 6.2 here), still beyond what a fifth-order scheme can reach.
+    ns = [16, 32, 64]
+    e = [_adv1d_error(n, "sharpclaw", tfinal=0.25, dt_rule=lambda dx: 2.0 * dx ** 1.75,
+                      time_integrator="ssp104", weno_order=7, weno_eps=eps) for n in ns]
+    rates = [math.log2(e[i] / e[i + 1]) for i in range(2)]
+    assert min(rates) > gate, (e, rates)
+
+
+def test_sharpclaw_weno7_conservation_2d_periodic():
+    s, q = W.random_smooth_euler(24, seed=3)
+    s = dict(s, weno_order=7, time_integrator="ssp104", cfl_desired=0.7, cfl_max=0.8)
+    t0 = oracle.totals(s, q)
+    qf, info = oracle.advance(s, q, 0.05)
+    assert info["accepted"] >= 3
+    np.testing.assert_allclose(oracle.totals(s, qf), t0, rtol=0, atol=1e-12 * np.abs(t0).max())
+
+
+# --------------------------------------------------------------------------
+# SSP Runge-Kutta order on a nonlinear ODE (closed-form solution)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("integ,order", [("ssp33", 3), ("ssp104", 4)])
+def test_ssp_integrator_order_riccati(integ, order):
+    # y' = 1 - y^2 has y(t) = tanh(t + atanh(y0)); the step routine is the
+    # one the SharpClaw step uses
+    exact = math.tanh(1.0 + math.atanh(0.2))
+    errs = [abs(oracle.ssp_riccati(integ, 0.2, 1.0, n) - exact) for n in (4, 8, 16, 32)]
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(3)]
+    assert min(rates) > order - 0.1 and rates[-1] < order + 0.3, rates
+
+
+def test_ssp104_is_not_third_order_scheme():
+    # the two integrators differ at O(dt^4): a planted third-order scheme
+    # would make these agree to O(dt^5)
+    a = oracle.ssp_riccati("ssp33", 0.2, 1.0, 4)
+    b = oracle.ssp_riccati("ssp104", 0.2, 1.0, 4)
+    assert abs(a - b) > 1e-6
+
+
+# --------------------------------------------------------------------------
+# WENO of order 2r-1 from its general construction
+# --------------------------------------------------------------------------
+def _cell_averages(poly, centres):
+    """Averages over unit cells centred at `centres` of the polynomial with
+    coefficients poly[n] (power n)."""
+    prim = np.polynomial.polynomial.polyint(poly)
+    return np.array([np.polynomial.polynomial.polyval(c + 0.5, prim) -
+                     np.polynomial.polynomial.polyval(c - 0.5, prim) for c in centres])
+
+
+def test_weno_r3_equals_weno5_closed_form():
+    rng = np.random.default_rng(7)
+    for eps in (1e-6, 1e-2, 1.0):
+        for _ in range(20):
+            v = rng.normal(size=5) * rng.uniform(0.1, 10)
+            a = oracle.weno5(v, eps)
+            b = oracle.weno_r(3, v, eps)
+            assert a == pytest.approx(b, rel=1e-13, abs=1e-14)
+
+
+def test_weno_linear_weights_published():
+    # Jiang-Shu (fifth order) and Balsara-Shu (seventh order) optimal weights
+    np.testing.assert_allclose(oracle.weno_linear_weights(3), [0.1, 0.6, 0.3], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(oracle.weno_linear_weights(4), np.array([1, 12, 18, 4]) / 35.0,
+                               rtol=0, atol=1e-15)
+    for r in range(3, 10):
+        d = oracle.weno_linear_weights(r)
+        assert d.sum() == pytest.approx(1.0, abs=1e-13) and (d > 0).all()
+        if r > 2:
+            assert d[0] < d[1]   # the most upwind-far stencil gets the least weight
+
+
+@pytest.mark.parametrize("r", [3, 4, 5, 6, 7])
+def test_weno_r_candidate_exactness(r):
+    # averages of a polynomial of degree r-1: every candidate is exact, so the
+    # edge values are exact whatever the nonlinear weights are
+    rng = np.random.default_rng(r)
+    poly = rng.normal(size=r)
+    v = _cell_averages(poly, range(-(r - 1), r))
+    qL, qR = oracle.weno_r(r, v, 1e-6)
+    pv = lambda x: np.polynomial.polynomial.polyval(x, poly)
+    assert qL == pytest.approx(pv(0.5), rel=1e-9, abs=1e-9)
+    assert qR == pytest.approx(pv(-0.5), rel=1e-9, abs=1e-9)
+
+
+@pytest.mark.parametrize("r", [3, 4, 5])
+def test_weno_r_linear_limit_is_full_stencil_exact(r):
+    # with eps >> beta the weights are the linear ones, and the reconstruction
+    # is the degree-(2r-2) interpolation of the whole stencil: exact for such
+    # polynomials (pins the linear weights against the candidate tables)
+    rng = np.random.default_rng(10 + r)
+    poly = rng.normal(size=2 * r - 1)
+    v = _cell_averages(poly, range(-(r - 1), r))
+    qL, qR = oracle.weno_r(r, v, 1e20)
+    pv = lambda x: np.polynomial.polynomial.polyval(x, poly)
+    assert qL == pytest.approx(pv(0.5), rel=1e-8, abs=1e-8)
+    assert qR == pytest.approx(pv(-0.5), rel=1e-8, abs=1e-8)
+    # and not for degree 2r-1
+    poly2 = np.concatenate([poly, [1.0]])
+    v2 = _cell_averages(poly2, range(-(r - 1), r))
+    qL2, _ = oracle.weno_r(r, v2, 1e20)
+    assert abs(qL2 - np.polynomial.polynomial.polyval(0.5, poly2)) > 1e-6
+
+
+def test_weno7_smoothness_indicator_of_linear_data():
+    # linear data: every candidate has the same derivative, so all beta_k are
+    # equal and the weights are the linear ones; a step makes the stencils
+    # that cross it lose their weight
+    v = np.arange(7, dtype=float) * 0.3
+    qL, qR = oracle.weno_r(4, v, 1e-6)
+    assert qL == pytest.approx(v[3] + 0.15, abs=1e-12)
+    assert qR == pytest.approx(v[3] - 0.15, abs=1e-12)
+    qL, qR = oracle.weno_r(4, np.array([0, 0, 0, 0, 1, 1, 1.0]), 1e-6)
+    assert abs(qL) < 1e-4 and abs(qR) < 1e-10
 
 
 # --------------------------------------------------------------------------
