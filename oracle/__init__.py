@@ -88,6 +88,8 @@ def _load():
     lib.or_weno5.argtypes = [dp, C.c_double, dp, dp]
     lib.or_weno_r.argtypes = [C.c_int, dp, C.c_double, dp, dp]
     lib.or_weno_r.restype = C.c_int
+    lib.or_weno_smoothness.argtypes = [C.c_int, dp, dp]
+    lib.or_weno_smoothness.restype = C.c_int
     lib.or_weno_linear_weights.argtypes = [C.c_int, dp]
     lib.or_weno_linear_weights.restype = C.c_int
     lib.or_ssp_riccati.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int]
@@ -276,6 +278,15 @@ def weno_r(r, v, eps=1e-6):
     if _load().or_weno_r(int(r), _ptr(v), float(eps), C.byref(qL), C.byref(qR)) != 0:
         raise ValueError("r out of range")
     return qL.value, qR.value
+
+
+def weno_smoothness(r, v):
+    """Smoothness indicators of the r candidates from 2r-1 averages."""
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    b = np.zeros(r)
+    if _load().or_weno_smoothness(int(r), _ptr(v), _ptr(b)) != 0:
+        raise ValueError("r out of range")
+    return b
 
 
 def weno_linear_weights(r):

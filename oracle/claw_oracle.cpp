@@ -669,7 +669,9 @@ void weno5(const double* v, double eps, double* qL, double* qR) {
 //     degree-(2r-2) polynomial through all 2r-1 averages (consistency);
 //     the left edge uses the mirrored weights d_{r-1-k};
 //   * beta_k = sum_{l=1}^{r-1} integral over the cell of (d^l p_k / dx^l)^2,
-//     a quadratic form in the stencil's data (matrix B_k);
+//     evaluated from p_k's monomial coefficients a_1 .. a_{r-1} (the
+//     constant a_0 does not enter): beta_k = sum_{n,m>=1} H_nm a_n a_m with
+//     H_nm = sum_l (n!/(n-l)!) (m!/(m-l)!) integral of x^(n+m-2l);
 //   * omega_k = alpha_k / sum alpha, alpha_k = d_k / (eps + beta_k)^2.
 // The tables are computed once per r, in long double, by solving the small
 // interpolation systems and integrating the squared derivatives exactly.
@@ -678,7 +680,8 @@ struct WenoTables {
   int r = 0;
   double cR[9][9], cL[9][9];   // [k][j]: value at +1/2 / -1/2 from data of stencil k, j = 0..r-1
   double d[9];                 // linear weights, right edge
-  double B[9][9][9];           // [k][a][b]: beta_k = sum_ab B v_a v_b over stencil k
+  double A[9][9][9];           // [k][n][j]: monomial coefficient a_n of candidate k from its data
+  double H[9][9];              // [n][m]: beta = sum_{n,m >= 1} H a_n a_m
 };
 
 // Coefficients a_n of p(x) = sum a_n x^n (n < r) from r cell averages at
@@ -740,24 +743,22 @@ static const WenoTables& weno_tables(int r) {
         t.cR[k][j] = (double)cR[k][j];
         t.cL[k][j] = (double)cL[k][j];
       }
-      // beta_k quadratic form: derivative l of the monomial basis, squared,
-      // integrated over [-1/2, 1/2]
-      for (int a = 0; a < r; ++a)
-        for (int b = 0; b < r; ++b) {
-          long double sum = 0.0L;
-          for (int l = 1; l < r; ++l)
-            for (int n = l; n < r; ++n)
-              for (int m = l; m < r; ++m) {
-                // d^l x^n = n!/(n-l)! x^(n-l)
-                long double fn = 1.0L, fm = 1.0L;
-                for (int q = 0; q < l; ++q) { fn *= (n - q); fm *= (m - q); }
-                const int e = (n - l) + (m - l);   // integral of x^e over the cell
-                const long double ie = (std::pow(0.5L, e + 1) - std::pow(-0.5L, e + 1)) / (e + 1);
-                sum += M[n][a] * M[m][b] * fn * fm * ie;
-              }
-          t.B[k][a][b] = (double)sum;
-        }
+      for (int n = 0; n < r; ++n)
+        for (int j = 0; j < r; ++j) t.A[k][n][j] = (double)M[n][j];
     }
+    // Gram matrix of the derivatives of the monomials: integral over the cell
+    // of sum_l d^l x^n d^l x^m
+    for (int n = 1; n < r; ++n)
+      for (int m = 1; m < r; ++m) {
+        long double sum = 0.0L;
+        for (int l = 1; l <= std::min(n, m); ++l) {
+          long double fn = 1.0L, fm = 1.0L;   // n!/(n-l)!, m!/(m-l)!
+          for (int q = 0; q < l; ++q) { fn *= (n - q); fm *= (m - q); }
+          const int e = (n - l) + (m - l);
+          sum += fn * fm * (std::pow(0.5L, e + 1) - std::pow(-0.5L, e + 1)) / (e + 1);
+        }
+        t.H[n][m] = (double)sum;
+      }
     // big stencil: degree 2r-2 through the averages of cells -(r-1) .. r-1
     const int R2 = 2 * r - 1;
     long double big[17];
@@ -807,23 +808,33 @@ static const WenoTables& weno_tables(int r) {
   return t;
 }
 
+// Candidate k's edge values and smoothness indicator from its r averages s[].
+static void weno_candidate(const WenoTables& t, int k, const double* s, double* pR, double* pL,
+                           double* beta) {
+  const int r = t.r;
+  double a = 0.0, c = 0.0, an[9];
+  for (int i = 0; i < r; ++i) {
+    a += t.cR[k][i] * s[i];
+    c += t.cL[k][i] * s[i];
+  }
+  for (int n = 1; n < r; ++n) {
+    an[n] = 0.0;
+    for (int i = 0; i < r; ++i) an[n] += t.A[k][n][i] * s[i];
+  }
+  double b = 0.0;
+  for (int n = 1; n < r; ++n)
+    for (int m = 1; m < r; ++m) b += t.H[n][m] * an[n] * an[m];
+  *pR = a;
+  *pL = c;
+  *beta = b;
+}
+
 // Edge values of cell i from the 2r-1 averages v[0..2r-2] centred on it
 // (v[r-1] = cell i): qL at its right edge, qR at its left edge.
 void weno_r(int r, const double* v, double eps, double* qL, double* qR) {
   const WenoTables& t = weno_tables(r);
   double beta[9], pR[9], pL[9];
-  for (int k = 0; k < r; ++k) {
-    const double* s = v + k;   // stencil k: v[k .. k+r-1]
-    double b = 0.0, a = 0.0, c = 0.0;
-    for (int i = 0; i < r; ++i) {
-      a += t.cR[k][i] * s[i];
-      c += t.cL[k][i] * s[i];
-      for (int j = 0; j < r; ++j) b += t.B[k][i][j] * s[i] * s[j];
-    }
-    beta[k] = b;
-    pR[k] = a;
-    pL[k] = c;
-  }
+  for (int k = 0; k < r; ++k) weno_candidate(t, k, v + k, &pR[k], &pL[k], &beta[k]);
   double sR = 0.0, sL = 0.0, nR = 0.0, nL = 0.0;
   for (int k = 0; k < r; ++k) {
     const double w = 1.0 / ((eps + beta[k]) * (eps + beta[k]));
@@ -1187,6 +1198,18 @@ void or_weno5(const double* v, double eps, double* qL, double* qR) { weno5(v, ep
 int or_weno_r(int r, const double* v, double eps, double* qL, double* qR) {
   if (r < 2 || r > 9) return -1;
   weno_r(r, v, eps, qL, qR);
+  return 0;
+}
+
+// Smoothness indicators beta_0 .. beta_{r-1} of the candidates of WENO
+// order 2r-1 from 2r-1 averages.
+int or_weno_smoothness(int r, const double* v, double* beta) {
+  if (r < 2 || r > 9) return -1;
+  const WenoTables& t = weno_tables(r);
+  for (int k = 0; k < r; ++k) {
+    double a, c;
+    weno_candidate(t, k, v + k, &a, &c, &beta[k]);
+  }
   return 0;
 }
 

@@ -378,6 +378,34 @@ def test_weno_r_linear_limit_is_full_stencil_exact(r):
     assert abs(qL2 - np.polynomial.polynomial.polyval(0.5, poly2)) > 1e-6
 
 
+@pytest.mark.parametrize("r", [3, 4, 5, 6])
+def test_weno_r_smoothness_indicator_closed_form(r):
+    # data = averages of a polynomial p of degree r-1: every candidate is p,
+    # so every beta_k is sum_{l=1}^{r-1} of the integral over the cell of
+    # (p^(l))^2 (Jiang-Shu), computed here with numpy's polynomial calculus
+    P = np.polynomial.polynomial
+    rng = np.random.default_rng(20 + r)
+    poly = rng.normal(size=r)
+    v = _cell_averages(poly, range(-(r - 1), r)) + 7.0   # an offset does not change beta
+    ref = 0.0
+    for l in range(1, r):
+        d = P.polyder(poly, l)
+        sq = P.polyint(P.polymul(d, d))
+        ref += P.polyval(0.5, sq) - P.polyval(-0.5, sq)
+    beta = oracle.weno_smoothness(r, v)
+    np.testing.assert_allclose(beta, ref, rtol=1e-9)
+
+
+def test_weno5_smoothness_indicators_jiang_shu_closed_form():
+    # the general construction at r = 3 gives the Jiang-Shu formulas
+    v = np.random.default_rng(3).normal(size=5)
+    a, b, c, d, e = v
+    js = [13 / 12 * (a - 2 * b + c) ** 2 + 0.25 * (a - 4 * b + 3 * c) ** 2,
+          13 / 12 * (b - 2 * c + d) ** 2 + 0.25 * (b - d) ** 2,
+          13 / 12 * (c - 2 * d + e) ** 2 + 0.25 * (3 * c - 4 * d + e) ** 2]
+    np.testing.assert_allclose(oracle.weno_smoothness(3, v), js, rtol=1e-12)
+
+
 def test_weno7_smoothness_indicator_of_linear_data():
     # linear data: every candidate has the same derivative, so all beta_k are
     # equal and the weights are the linear ones; a step makes the stencils
