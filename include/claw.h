@@ -14,12 +14,15 @@
  *                     first-order part as fluctuations), and in 2D the
  *                     unsplit transverse corrections from a secondary
  *                     Riemann solver (Section 2.1);
- *   CLAW_SHARPCLAW -- the SharpClaw method of lines: WENO5 edge values, an
- *                     interface Riemann flux, flux differencing
- *                     (Section 2, eq. fluxdiff), inside the three stages of
- *                     the SSP Runge-Kutta method SSPRK(3,3) (Section 2.1:
- *                     SharpClaw uses WENO in space and SSP RK in time, with
- *                     normal Riemann problems only in 2D).
+ *   CLAW_SHARPCLAW -- the SharpClaw method of lines: WENO edge values (fifth
+ *                     or seventh order), an interface Riemann flux, flux
+ *                     differencing (Section 2, eq. fluxdiff), inside the
+ *                     stages of an SSP Runge-Kutta method: SSPRK(3,3), or
+ *                     the ten-stage fourth-order SSP method (Ketcheson 2008,
+ *                     two-register form) that SharpClaw uses by default
+ *                     (Section 2.1: WENO in space and SSP RK in time, with
+ *                     normal Riemann problems only in 2D; higher WENO
+ *                     orders from generated coefficients).
  *
  * Ghost cells carry the boundary conditions (Section 5, "Parallelization");
  * after each step the Courant number is checked and the next step size is
@@ -82,6 +85,10 @@ enum claw_riemann {
 };
 enum claw_limiter { CLAW_LIM_NONE = 0, CLAW_LIM_MINMOD = 1, CLAW_LIM_MC = 2 };
 enum claw_bc { CLAW_BC_EXTRAP = 1, CLAW_BC_PERIODIC = 2, CLAW_BC_WALL = 3, CLAW_BC_DIRICHLET = 4 };
+enum claw_integrator {
+  CLAW_SSP33 = 1,   /* Shu-Osher SSPRK(3,3): 3 stages (launches), two stage arrays */
+  CLAW_SSP104 = 2   /* SSPRK(10,4): 10 stages, SSP coefficient 6, three stage arrays */
+};
 enum claw_precision {
   CLAW_FP64 = 1,       /* all arithmetic in float64 */
   CLAW_FP32_KAHAN = 2  /* reconstruction, Riemann and limiter arithmetic in float32; the state is
@@ -107,9 +114,12 @@ typedef struct claw_config {
   double cfl_max;        /* steps with a larger Courant number are rejected */
   double dt_initial;     /* first dt; <= 0: cfl_desired / max cell characteristic speed */
   double dt_max;         /* <= 0: unbounded */
-  double weno_eps;       /* SharpClaw WENO5 epsilon (1e-6 if <= 0) */
+  double weno_eps;       /* SharpClaw WENO epsilon (1e-6 if <= 0) */
   int precision;         /* claw_precision */
   double problem_data[8];
+  int time_integrator;   /* SharpClaw: claw_integrator (0 = CLAW_SSP33); ignored by classic */
+  int weno_order;        /* SharpClaw: 5 or 7 (0 = 5); ignored by classic.  Any other value:
+                            CLAW_E_INVAL */
 } claw_config;
 
 /* Clock and counters of a handle; also the checkpoint record of the

@@ -18,6 +18,7 @@ SOLVERS = {"advection": 1, "sw_roe": 2, "euler_hlle": 3, "elastic_vc": 4}
 LIMITERS = {"none": 0, "minmod": 1, "mc": 2}
 BCS = {"extrap": 1, "periodic": 2, "wall": 3, "dirichlet": 4}
 PRECISIONS = {"fp64": 1, "fp32_kahan": 2}
+INTEGRATORS = {"ssp33": 1, "ssp104": 2}
 SIDES = ("x_lower", "x_upper", "y_lower", "y_upper")
 
 
@@ -29,7 +30,7 @@ class ClawConfig(C.Structure):
         ("bc_lower", C.c_int * 2), ("bc_upper", C.c_int * 2), ("bc_state", (C.c_double * 8) * 4),
         ("cfl_desired", C.c_double), ("cfl_max", C.c_double), ("dt_initial", C.c_double),
         ("dt_max", C.c_double), ("weno_eps", C.c_double), ("precision", C.c_int),
-        ("problem_data", C.c_double * 8),
+        ("problem_data", C.c_double * 8), ("time_integrator", C.c_int), ("weno_order", C.c_int),
     ]
 
 
@@ -165,6 +166,8 @@ def make_config(spec: dict) -> ClawConfig:
     c.dt_max = float(spec.get("dt_max", 0.0) or 0.0)
     c.weno_eps = float(spec.get("weno_eps", 1e-6))
     c.precision = PRECISIONS[spec.get("precision", "fp64")]
+    c.time_integrator = INTEGRATORS[spec.get("time_integrator", "ssp33")]
+    c.weno_order = int(spec.get("weno_order", 5))
     for k, v in enumerate(spec.get("problem_data", [])):
         c.problem_data[k] = float(v)
     return c

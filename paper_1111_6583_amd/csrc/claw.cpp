@@ -27,8 +27,9 @@ hipError_t launch_classic1d(int riemann, int fp32, int nblocks, hipStream_t st,
 hipError_t launch_classic1d_run(int riemann, int fp32, int m, int nx, hipStream_t st,
                                 const GridDesc* d_grids);
 size_t classic1d_run_smem(int m, int nx, int fp32);
-hipError_t launch_sharp_stage(int ndim, int riemann, int fp32, int stage, int nblocks,
-                              hipStream_t st, const GridDesc* d_grids, int mode, double dt);
+hipError_t launch_sharp_stage(int ndim, int riemann, int fp32, int weno_r, int kind, int nblocks,
+                              hipStream_t st, const GridDesc* d_grids, int mode, double dt,
+                              const StageArgs& sa);
 hipError_t launch_load_state(int fp32, void* q, void* c, const double* in, size_t n,
                              hipStream_t st);
 hipError_t launch_store_state(int fp32, double* out, const void* q, const void* c, size_t n,
@@ -53,7 +54,8 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kMarchLanesClassic = kLanes - 4;   // useful columns per classic strip
-constexpr int kMarchLanesSharp = kLanes - 6;     // useful columns per SharpClaw strip
+// useful columns per SharpClaw strip: r halo lanes a side for WENO order 2r-1
+int march_lanes_sharp(int weno_r) { return kLanes - 2 * weno_r; }
 constexpr size_t kRun1dSmemMax = 64 * 1024;      // LDS budget of the 1D whole-run kernel
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -91,6 +93,10 @@ int validate(const claw_config* c) {
     if (c->transverse < 0 || c->transverse > 2) return CLAW_E_INVAL;
   } else if (c->scheme == CLAW_SHARPCLAW) {
     if (c->riemann != CLAW_RP_ADVECTION && c->riemann != CLAW_RP_EULER_HLLE) return CLAW_E_INVAL;
+    if (c->time_integrator != 0 && c->time_integrator != CLAW_SSP33 &&
+        c->time_integrator != CLAW_SSP104)
+      return CLAW_E_INVAL;
+    if (c->weno_order != 0 && c->weno_order != 5 && c->weno_order != 7) return CLAW_E_INVAL;
   } else {
     return CLAW_E_INVAL;
   }
@@ -98,9 +104,12 @@ int validate(const claw_config* c) {
   return CLAW_OK;
 }
 
-// Process-wide tiling cache: (scheme, riemann, precision, nx, ny) -> seg_rows.
+// Process-wide tiling cache: (scheme, riemann, precision, WENO order, nx, ny) -> seg_rows.
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int, int>, int> g_tune;
+std::map<std::tuple<int, int, int, int, int, int>, int> g_tune;
+
+int weno_r_of(const claw_config& c) { return c.weno_order == 7 ? 4 : 3; }
+bool ssp104(const claw_config& c) { return c.time_integrator == CLAW_SSP104; }
 
 int default_seg_rows(int ny) { return std::min(ny, 16); }
 
@@ -175,6 +184,7 @@ size_t layout(const claw_config& c, size_t off[16]) {
   if (!classic) {
     take(9, m * N * rb);                                   // s1
     take(10, m * N * rb);                                  // s2
+    if (ssp104(c)) take(12, m * N * rb);                   // s3
   }
   if (na) take(11, na * N * rb);                           // aux
   return p;
@@ -182,15 +192,16 @@ size_t layout(const claw_config& c, size_t off[16]) {
 
 int seg_rows_for(claw_t h) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  auto key = std::make_tuple(h->cfg.scheme, h->cfg.riemann, h->cfg.precision, h->cfg.num_cells[0],
-                             h->cfg.ndim == 2 ? h->cfg.num_cells[1] : 1);
+  auto key = std::make_tuple(h->cfg.scheme, h->cfg.riemann, h->cfg.precision, h->cfg.weno_order,
+                             h->cfg.num_cells[0], h->cfg.ndim == 2 ? h->cfg.num_cells[1] : 1);
   auto it = g_tune.find(key);
   return it != g_tune.end() ? it->second : default_seg_rows(h->cfg.ndim == 2 ? h->cfg.num_cells[1] : 1);
 }
 
 void set_tiling(claw_t h, int seg_rows) {
   GridDesc& g = h->hg;
-  const int lanes = h->cfg.scheme == CLAW_CLASSIC ? kMarchLanesClassic : kMarchLanesSharp;
+  const int lanes =
+      h->cfg.scheme == CLAW_CLASSIC ? kMarchLanesClassic : march_lanes_sharp(weno_r_of(h->cfg));
   g.strips = (g.nx + lanes - 1) / lanes;
   if (h->cfg.ndim == 2) {
     g.seg_rows = std::max(1, std::min(seg_rows, g.ny));
@@ -218,6 +229,88 @@ int read_ctrl(claw_t h) {
   return CLAW_OK;
 }
 
+// The stage sequence of one SharpClaw attempt (see k_sharp.hip):
+//   SSPRK(3,3): Q -> S1 = y;  S1 -> S2 = 3/4 Q + 1/4 y;  S2 -> Q = 1/3 Q + 2/3 y.
+//   SSPRK(10,4): stages 1-4, 6-9 y = S + dt/6 L(S) alternating S1/S2;
+//                stage 5 S3 = Q/25 + 9/25 y, S1 = 3/5 Q + 2/5 y (= 15 S3 - 5 y);
+//                stage 10 Q = S3 + 3/5 y.
+int sharp_plan(claw_t h, StageArgs* st, int* kind) {
+  const GridDesc& g = h->hg;
+  void* Q = g.q[0];
+  for (int s = 0; s < 10; ++s) std::memset(&st[s], 0, sizeof(StageArgs));
+  auto plain = [&](int s, void* in, void* out, double gamma) {
+    st[s].in = in;
+    st[s].out1 = out;
+    st[s].gamma = gamma;
+    st[s].b1 = 1.0;
+    kind[s] = kStagePlain;
+  };
+  if (ssp104(h->cfg)) {
+    void* S1 = g.s1;
+    void* S2 = g.s2;
+    void* S3 = g.s3;
+    const double g6 = 1.0 / 6.0;
+    plain(0, Q, S1, g6);
+    plain(1, S1, S2, g6);
+    plain(2, S2, S1, g6);
+    plain(3, S1, S2, g6);
+    st[4].in = S2;
+    st[4].out1 = S3;
+    st[4].out2 = S1;
+    st[4].p1 = Q;
+    st[4].gamma = g6;
+    st[4].a1 = 1.0 / 25.0;
+    st[4].b1 = 9.0 / 25.0;
+    st[4].a2 = 3.0 / 5.0;
+    st[4].b2 = 2.0 / 5.0;
+    kind[4] = kStageCombine;
+    plain(5, S1, S2, g6);
+    plain(6, S2, S1, g6);
+    plain(7, S1, S2, g6);
+    plain(8, S2, S1, g6);
+    st[9].in = S1;
+    st[9].out1 = Q;
+    st[9].p1 = S3;
+    st[9].gamma = g6;
+    st[9].a1 = 1.0;
+    st[9].b1 = 3.0 / 5.0;
+    st[9].w = (1.0 - 3.0 / 5.0) / 1.0;
+    kind[9] = kStageFinal;
+    st[0].first = 1;
+    return 10;
+  }
+  plain(0, Q, g.s1, 1.0);
+  st[0].first = 1;
+  st[1].in = g.s1;
+  st[1].out1 = g.s2;
+  st[1].p1 = Q;
+  st[1].gamma = 1.0;
+  st[1].a1 = 0.75;
+  st[1].b1 = 0.25;
+  kind[1] = kStageCombine;
+  st[2].in = g.s2;
+  st[2].out1 = Q;
+  st[2].p1 = Q;
+  st[2].p1_is_q = 1;
+  st[2].gamma = 1.0;
+  st[2].a1 = 1.0 / 3.0;
+  st[2].b1 = 2.0 / 3.0;
+  st[2].w = 1.0;
+  kind[2] = kStageFinal;
+  return 3;
+}
+
+// Launch SharpClaw stages [from, to) of one attempt.
+int launch_sharp_stages(claw_t h, int from, int to, int mode, double dt) {
+  StageArgs st[10];
+  int kind[10];
+  const int n = sharp_plan(h, st, kind);
+  for (int s = from; s < std::min(to, n); ++s)
+    HIPCHK(launch_sharp_stage(h->cfg.ndim, h->cfg.riemann, h->fp32, h->hg.weno_r, kind[s],
+                              h->hg.nblocks, h->stream, h->d_grid, mode, dt, st[s]));
+  return CLAW_OK;
+}
+
 // One attempt's kernels in host-dt mode (classic: one kernel; SharpClaw: the
 // first stage only when `stage1_only`).
 int launch_attempt_host(claw_t h, double dt, bool stage1_only) {
@@ -230,25 +323,12 @@ int launch_attempt_host(claw_t h, double dt, bool stage1_only) {
       HIPCHK(launch_classic1d(h->cfg.riemann, h->fp32, g.nblocks, h->stream, h->d_grid, kHostDt, dt,
                               h->src));
   } else {
-    HIPCHK(launch_sharp_stage(h->cfg.ndim, h->cfg.riemann, h->fp32, 1, g.nblocks, h->stream,
-                              h->d_grid, kHostDt, dt));
-    if (!stage1_only) {
-      HIPCHK(launch_sharp_stage(h->cfg.ndim, h->cfg.riemann, h->fp32, 2, g.nblocks, h->stream,
-                                h->d_grid, kHostDt, dt));
-      HIPCHK(launch_sharp_stage(h->cfg.ndim, h->cfg.riemann, h->fp32, 3, g.nblocks, h->stream,
-                                h->d_grid, kHostDt, dt));
-    }
+    return launch_sharp_stages(h, 0, stage1_only ? 1 : 10, kHostDt, dt);
   }
   return CLAW_OK;
 }
 
-int sharp_finish_host(claw_t h, double dt) {
-  HIPCHK(launch_sharp_stage(h->cfg.ndim, h->cfg.riemann, h->fp32, 2, h->hg.nblocks, h->stream,
-                            h->d_grid, kHostDt, dt));
-  HIPCHK(launch_sharp_stage(h->cfg.ndim, h->cfg.riemann, h->fp32, 3, h->hg.nblocks, h->stream,
-                            h->d_grid, kHostDt, dt));
-  return CLAW_OK;
-}
+int sharp_finish_host(claw_t h, double dt) { return launch_sharp_stages(h, 1, 10, kHostDt, dt); }
 
 // One attempt in device-controller mode (what a graph node sequence holds).
 int launch_attempt_device(claw_t h) {
@@ -261,9 +341,7 @@ int launch_attempt_device(claw_t h) {
       HIPCHK(launch_classic1d(h->cfg.riemann, h->fp32, g.nblocks, h->stream, h->d_grid, kDeviceCtrl,
                               0.0, 0));
   } else {
-    for (int s = 1; s <= 3; ++s)
-      HIPCHK(launch_sharp_stage(h->cfg.ndim, h->cfg.riemann, h->fp32, s, g.nblocks, h->stream,
-                                h->d_grid, kDeviceCtrl, 0.0));
+    return launch_sharp_stages(h, 0, 10, kDeviceCtrl, 0.0);
   }
   return CLAW_OK;
 }
@@ -372,6 +450,8 @@ int claw_create(const claw_config* cfg, void* d_ws, size_t ws_bytes, void* hip_s
   if (!h) return CLAW_E_NOMEM;
   h->cfg = *cfg;
   if (h->cfg.weno_eps <= 0.0) h->cfg.weno_eps = 1e-6;
+  if (h->cfg.time_integrator == 0) h->cfg.time_integrator = CLAW_SSP33;
+  if (h->cfg.weno_order == 0) h->cfg.weno_order = 5;
   if (hipGetDevice(&h->device) != hipSuccess) { delete h; return CLAW_E_DEVICE; }
   h->m = num_eqn_of(*cfg);
   h->na = num_aux_of(*cfg);
@@ -417,6 +497,8 @@ int claw_create(const claw_config* cfg, void* d_ws, size_t ws_bytes, void* hip_s
   g.c[1] = buf(h, off, 8, base);
   g.s1 = buf(h, off, 9, base);
   g.s2 = buf(h, off, 10, base);
+  g.s3 = buf(h, off, 12, base);
+  g.weno_r = weno_r_of(h->cfg);
   g.aux = buf(h, off, 11, base);
   g.ctrl = h->d_ctrl;
   set_tiling(h, seg_rows_for(h));
@@ -723,11 +805,7 @@ int claw_autotune(claw_t h, int reps, claw_tuning* out) {
     // the state untouched
     auto run = [&]() -> int {
       if (h->cfg.scheme == CLAW_CLASSIC) return launch_attempt_host(h, dt, true);
-      HIPCHK(launch_sharp_stage(h->cfg.ndim, h->cfg.riemann, h->fp32, 1, h->hg.nblocks, h->stream,
-                                h->d_grid, kHostDt, dt));
-      HIPCHK(launch_sharp_stage(h->cfg.ndim, h->cfg.riemann, h->fp32, 2, h->hg.nblocks, h->stream,
-                                h->d_grid, kHostDt, dt));
-      return CLAW_OK;
+      return launch_sharp_stages(h, 0, 2, kHostDt, dt);
     };
     if ((rc = run())) break;
     HIPCHK(hipEventRecord(e0, h->stream));
@@ -745,7 +823,8 @@ int claw_autotune(claw_t h, int reps, claw_tuning* out) {
   if (rc) return rc;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[std::make_tuple(h->cfg.scheme, h->cfg.riemann, h->cfg.precision, h->hg.nx, ny)] = best;
+    g_tune[std::make_tuple(h->cfg.scheme, h->cfg.riemann, h->cfg.precision, h->cfg.weno_order,
+                           h->hg.nx, ny)] = best;
   }
   set_tiling(h, best);
   if ((rc = upload_grid(h))) return rc;
@@ -763,11 +842,7 @@ int claw_time_kernel(claw_t h, double dt, int reps, double* avg_ms) {
   HIPCHK(hipSetDevice(h->device));
   auto one = [&]() -> int {
     if (h->cfg.scheme == CLAW_CLASSIC) return launch_attempt_host(h, dt, true);
-    HIPCHK(launch_sharp_stage(h->cfg.ndim, h->cfg.riemann, h->fp32, 1, h->hg.nblocks, h->stream,
-                              h->d_grid, kHostDt, dt));
-    HIPCHK(launch_sharp_stage(h->cfg.ndim, h->cfg.riemann, h->fp32, 2, h->hg.nblocks, h->stream,
-                              h->d_grid, kHostDt, dt));
-    return CLAW_OK;
+    return launch_sharp_stages(h, 0, 2, kHostDt, dt);
   };
   int rc = one();
   if (rc) return rc;

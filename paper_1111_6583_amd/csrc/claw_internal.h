@@ -45,8 +45,25 @@ struct GridDesc {
   void* c[2];                     // compensation ping-pong (Real, FP32 mode)
   void* s1;                       // SharpClaw stage buffers (Real)
   void* s2;
+  void* s3;                       // SharpClaw SSPRK(10,4): the second register
+  int weno_r;                     // SharpClaw: WENO order 2r-1 (r = 3 or 4)
   const void* aux;                // aux fields (Real)
   Ctrl* ctrl;
+};
+
+// One SharpClaw Runge-Kutta stage (see k_sharp.hip): y = S + gamma dt L(S),
+// then PLAIN out1 = y; COMBINE out1 = a1 P1 + b1 y (and out2 = a2 P1 + b2 y
+// if out2 is set); FINAL Q = a1 P1 + b1 y in place.
+enum StageKind { kStagePlain = 0, kStageCombine = 1, kStageFinal = 2 };
+struct StageArgs {
+  const void* in;    // S
+  void* out1;
+  void* out2;        // or null
+  const void* p1;    // pointwise input of COMBINE / FINAL
+  double gamma, a1, b1, a2, b2;
+  double w;          // FINAL, FP32 increment form: a1 (P1 - w Q) + b1 ((S - Q) + gamma dt L)
+  int first;         // first stage of an attempt: Courant number + controller
+  int p1_is_q;       // FINAL: P1 is Q itself
 };
 
 // How a kernel obtains dt and the source buffer.

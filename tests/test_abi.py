@@ -80,3 +80,18 @@ def test_invalid_configs_rejected(bad):
 def test_elastic_only_classic_2d():
     spec, _, _ = W.layered_elastic(64)
     assert _bytes(dict(spec, scheme="sharpclaw"))[0] == 0
+
+
+def test_sharpclaw_integrator_and_weno_order_options():
+    spec, _ = W.shock_bubble(256, 128)
+    n33, m = _bytes(spec)
+    n104, _ = _bytes(dict(spec, time_integrator="ssp104"))
+    arr = m * 256 * 128 * 8
+    # SSPRK(10,4) keeps one more state-sized register than SSPRK(3,3)
+    assert arr <= n104 - n33 < arr + 4096
+    assert _bytes(dict(spec, weno_order=7))[0] == n33
+    for bad in (3, 6, 9):
+        assert _bytes(dict(spec, weno_order=bad))[0] == 0
+    # classic ignores both
+    sw, _ = W.radial_dam_break(64)
+    assert _bytes(dict(sw, time_integrator="ssp104", weno_order=7))[0] == _bytes(sw)[0]

@@ -64,6 +64,19 @@ def l1_rel(g, o):
             for k in range(o.shape[0])]
 
 
+def l1_rel_groups(g, o, spec):
+    """L1 error per component relative to the largest L1 norm among the
+    components sharing its units (the FP32 counterpart of the FP64 floor: a
+    transverse momentum that is small against the streamwise one is measured
+    on the momentum scale)."""
+    norms = [float(np.sum(np.abs(o[k]))) for k in range(o.shape[0])]
+    floor = list(norms)
+    for grp in unit_groups(spec):
+        for k in grp:
+            floor[k] = max(norms[m] for m in grp)
+    return [float(np.sum(np.abs(g[k] - o[k]))) / max(floor[k], 1e-300) for k in range(o.shape[0])]
+
+
 def replay(spec, q, dts, aux=None, seg_rows=None):
     s = solver(spec, q, aux, seg_rows)
     for dt in dts:
@@ -284,6 +297,122 @@ def test_full_size_shock_bubble_one_step():
     s.step(dt)
     o, _ = oracle.step(spec, q1, dt)
     assert fp64_err(s.get_state(), o, spec) <= 1e-12
+
+
+# --------------------------------------------------------------------------
+# SharpClaw variants: SSPRK(10,4) (the SharpClaw default) and WENO7
+# --------------------------------------------------------------------------
+VARIANTS = [("ssp104", 5), ("ssp33", 7), ("ssp104", 7)]
+
+
+@pytest.mark.parametrize("integ,order", VARIANTS)
+def test_sharpclaw_variant_shock_bubble_replay(integ, order):
+    say("case: shock-bubble 128x64", integ, "WENO", order, "20 steps")
+    spec, q = W.shock_bubble(128, 64)
+    spec = dict(spec, time_integrator=integ, weno_order=order)
+    qo, info = oracle.advance(spec, q, 1.0, max_steps=20)
+    g = replay(spec, q, info["dts"][info["acc"] == 1])
+    assert fp64_err(g, qo, spec) <= 1e-12
+
+
+@pytest.mark.parametrize("integ,order", VARIANTS)
+def test_sharpclaw_variant_ragged_periodic(integ, order):
+    say("case: smooth periodic Euler 77x61", integ, "WENO", order, "12 steps")
+    spec, q = W.random_smooth_euler(77, seed=5)
+    q = q[:, :61, :].copy()
+    spec = dict(spec, num_cells=(77, 61), upper=(1.0, 61 / 77), time_integrator=integ,
+                weno_order=order)
+    qo, info = oracle.advance(spec, q, 1.0, max_steps=12)
+    g = replay(spec, q, info["dts"][info["acc"] == 1], seg_rows=7)
+    assert fp64_err(g, qo, spec) <= 1e-12
+
+
+def test_sharpclaw_weno7_advection_walls_replay():
+    say("case: SharpClaw WENO7 advection 70x50, wall/extrap BCs, 15 steps")
+    rng = np.random.default_rng(11)
+    spec = dict(ndim=2, num_cells=(70, 50), lower=(0.0, 0.0), upper=(1.4, 1.0),
+                scheme="sharpclaw", riemann="advection", problem_data=[0.7, -0.4],
+                bc_lower=("wall", "extrap"), bc_upper=("extrap", "wall"), weno_order=7,
+                time_integrator="ssp104", cfl_desired=0.7, cfl_max=0.8)
+    q = rng.uniform(0.5, 1.5, (1, 50, 70))
+    qo, info = oracle.advance(spec, q, 1.0, max_steps=15)
+    g = replay(spec, q, info["dts"][info["acc"] == 1], seg_rows=9)
+    assert fp64_err(g, qo, spec) <= 1e-12
+
+
+@pytest.mark.parametrize("integ,order", VARIANTS)
+def test_sharpclaw_variant_1d_planar_shock_device_controller(integ, order):
+    say("case: SharpClaw 1D planar shock, 300 cells,", integ, "WENO", order)
+    rho1, u1, p1, S = W.rankine_hugoniot(2.0)
+    n = 300
+    post = [rho1, rho1 * u1, p1 / 0.4 + 0.5 * rho1 * u1 * u1]
+    spec = dict(ndim=1, num_cells=(n,), lower=(0.0,), upper=(2.0,), scheme="sharpclaw",
+                riemann="euler_hlle", problem_data=[1.4], bc_lower=("dirichlet",),
+                bc_upper=("extrap",), bc_state={"x_lower": post}, cfl_desired=0.5, cfl_max=0.6,
+                time_integrator=integ, weno_order=order)
+    x = (np.arange(n) + 0.5) * 2.0 / n
+    q = np.zeros((3, 1, n))
+    for k in range(3):
+        q[k, 0] = np.where(x < 0.3, post[k], [1.0, 0.0, 2.5][k])
+    qo, dts, info = oracle_run(spec, q, 0.3)
+    s = solver(spec, q)
+    st = s.advance(0.3, steps_per_graph=4)
+    assert st["accepted"] == info["accepted"]
+    assert fp64_err(s.get_state(), qo, spec) <= 1e-12
+
+
+def test_sharpclaw_ssp104_device_vs_host_controller():
+    say("case: shock-bubble 96x48 SSPRK(10,4) WENO7, host vs device controller")
+    spec, q = W.shock_bubble(96, 48)
+    spec = dict(spec, time_integrator="ssp104", weno_order=7, cfl_desired=0.7, cfl_max=0.8)
+    qo, dts, info = oracle_run(spec, q, 0.03)
+    a = solver(spec, q)
+    sa = a.advance(0.03, graph=False)
+    b = solver(spec, q)
+    sb = b.advance(0.03, graph=True, steps_per_graph=3)
+    assert sa["accepted"] == sb["accepted"] == info["accepted"]
+    np.testing.assert_array_equal(a.get_state(), b.get_state())
+    assert fp64_err(b.get_state(), qo, spec) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_kahan"])
+def test_sharpclaw_weno7_tiling_does_not_change_results(prec):
+    say("case: WENO7 SSPRK(10,4) seg_rows 3/16/100 bitwise equal", prec)
+    spec, q = W.shock_bubble(150, 100)
+    spec = dict(spec, precision=prec, time_integrator="ssp104", weno_order=7)
+    outs = [replay(spec, q, [1e-3] * 4, seg_rows=sr) for sr in (3, 16, 100)]
+    np.testing.assert_array_equal(outs[0], outs[1])
+    np.testing.assert_array_equal(outs[0], outs[2])
+
+
+def test_full_size_shock_bubble_weno7_ssp104_one_step():
+    say("case: shock-bubble 2048x1024 WENO7 SSPRK(10,4), one-step parity after 5 GPU steps")
+    spec, q = W.shock_bubble(2048, 1024)
+    spec = dict(spec, time_integrator="ssp104", weno_order=7, cfl_desired=0.7, cfl_max=0.8)
+    s = solver(spec, q)
+    s.autotune(reps=1)
+    s.advance(1.0, max_steps=5)
+    q1 = s.get_state()
+    dt = s.clock()["dt_next"]
+    s.step(dt)
+    o, _ = oracle.step(spec, q1, dt)
+    assert fp64_err(s.get_state(), o, spec) <= 1e-12
+
+
+@pytest.mark.parametrize("integ,order", VARIANTS)
+def test_fp32_kahan_sharpclaw_variant_l1(integ, order):
+    # 60 steps: the shock has entered the bubble, so rho*v is no longer zero
+    # up to rounding (its L1 norm would otherwise be pure noise)
+    say("case: FP32+Kahan shock-bubble 256x128,", integ, "WENO", order, "60 steps (replayed dt)")
+    spec, q = W.shock_bubble(256, 128)
+    spec = dict(spec, time_integrator=integ, weno_order=order)
+    qo, info = oracle.advance(spec, q, 1.0, max_steps=60)
+    g = replay(dict(spec, precision="fp32_kahan"), q, info["dts"][info["acc"] == 1])
+    err = l1_rel(g, qo)
+    errg = l1_rel_groups(g, qo, spec)
+    say("L1 relative errors", err, "on the unit-group scale", errg)
+    assert max(errg) <= 1e-4
+    assert max(err[0], err[1], err[3]) <= 1e-5
 
 
 # --------------------------------------------------------------------------
