@@ -35,7 +35,8 @@ _lock = threading.Lock()
 _lib = None
 
 SCHEMES = {"classic": 1, "sharpclaw": 2}
-SOLVERS = {"advection": 1, "sw_roe": 2, "euler_hlle": 3, "elastic_vc": 4}
+SOLVERS = {"advection": 1, "sw_roe": 2, "euler_hlle": 3, "elastic_vc": 4, "euler_roe": 5}
+SOURCES = {"none": 0, "axisymmetric": 1}
 LIMITERS = {"none": 0, "minmod": 1, "mc": 2}
 BCS = {"extrap": 1, "periodic": 2, "wall": 3, "dirichlet": 4}
 SIDES = ("x_lower", "x_upper", "y_lower", "y_upper")
@@ -49,7 +50,7 @@ class OCfg(C.Structure):
         ("scheme", C.c_int), ("solver", C.c_int), ("limiter", C.c_int),
         ("transverse", C.c_int), ("efix", C.c_int), ("bc", C.c_int * 4),
         ("bcstate", (C.c_double * 8) * 4), ("weno_eps", C.c_double), ("pd", C.c_double * 8),
-        ("integrator", C.c_int), ("weno_order", C.c_int),
+        ("integrator", C.c_int), ("weno_order", C.c_int), ("tracer", C.c_int), ("source", C.c_int),
     ]
 
 
@@ -84,6 +85,8 @@ def _load():
     lib.or_riemann.argtypes = [cp, C.c_int, dp, dp, dp, dp, dp, dp, dp, dp]
     lib.or_transverse.argtypes = [cp, C.c_int, dp, dp, dp, dp, dp, dp, dp, dp]
     lib.or_num_flux.argtypes = [cp, C.c_int, dp, dp, dp]
+    lib.or_source_step.argtypes = [cp, dp, C.c_double]
+    lib.or_source_step.restype = C.c_int
     lib.or_num_flux.restype = C.c_double
     lib.or_weno5.argtypes = [dp, C.c_double, dp, dp]
     lib.or_weno_r.argtypes = [C.c_int, dp, C.c_double, dp, dp]
@@ -144,6 +147,8 @@ def make_cfg(spec: dict) -> OCfg:
     c.weno_eps = float(spec.get("weno_eps", 1e-6))
     c.integrator = INTEGRATORS[spec.get("time_integrator", "ssp33")]
     c.weno_order = int(spec.get("weno_order", 5))
+    c.tracer = int(spec.get("tracer", 0))
+    c.source = SOURCES[spec.get("source", "none")]
     for k, v in enumerate(spec.get("problem_data", [])):
         c.pd[k] = float(v)
     return c
@@ -226,13 +231,22 @@ def riemann(spec, d, ql, qr, auxl=None, auxr=None):
     qr = np.zeros(5) + np.pad(np.asarray(qr, float), (0, 5 - m))
     al = np.zeros(3) if auxl is None else np.asarray(auxl, float).copy()
     ar = np.zeros(3) if auxr is None else np.asarray(auxr, float).copy()
-    W = np.zeros((4, 5))
-    s = np.zeros(4)
+    W = np.zeros((5, 5))
+    s = np.zeros(5)
     am = np.zeros(5)
     ap = np.zeros(5)
     lib.or_riemann(C.byref(c), int(d), _ptr(ql), _ptr(qr), _ptr(al), _ptr(ar), _ptr(W), _ptr(s),
                    _ptr(am), _ptr(ap))
     return W[:mw, :m], s[:mw], am[:m], ap[:m]
+
+
+def source_step(spec, q, dt):
+    """The geometric source fractional step alone on a state (returns a copy)."""
+    c, m, q = _state(spec, q)
+    out = q.copy()
+    if _load().or_source_step(C.byref(c), _ptr(out), float(dt)) != 0:
+        raise ValueError("configuration has no source term")
+    return out
 
 
 def transverse(spec, d, ql, qr, asdq, aux_m=None, aux_c=None, aux_p=None):

@@ -5,11 +5,16 @@
 // PyClaw paper describes (Section 2, "Finite Volume Hyperbolic PDE solvers",
 // and Section 2.1, "Clawpack and SharpClaw"):
 //
-//   * classic Clawpack wave propagation: a Riemann solve at every interface,
+//   * classic Clawpack wave propagation (Riemann solvers: advection, shallow
+//     water Roe, Euler Roe with an optional tracer, elasticity): a Riemann
+//     solve at every interface,
 //     waves limited by the upwind neighbour, a second-order correction flux
 //     (eq. lwflux: F = F_upwind + F_correction, first-order part written as
 //     fluctuations) and, in 2D, the unsplit transverse corrections computed by
-//     a secondary "transverse" Riemann solver;
+//     a secondary "transverse" Riemann solver; a geometric source term (the
+//     axisymmetric Euler equations, eq. euler-rz) is applied by a fractional
+//     step after the hyperbolic update (Section 2.1, source terms by
+//     operator splitting);
 //   * SharpClaw method of lines: WENO edge values (fifth order, or any odd
 //     order 2r-1 from the general definition), an interface Riemann flux and
 //     flux differencing (eq. fluxdiff), inside SSP Runge-Kutta stages
@@ -57,13 +62,15 @@ struct OCfg {
   double pd[8];        // problem data: advection (u, v); shallow water (g); Euler (gamma)
   int integrator;      // SharpClaw: 0/1 SSPRK(3,3), 2 SSPRK(10,4)
   int weno_order;      // SharpClaw: 0/5 WENO5, or 2r-1 for r = 3..9
+  int tracer;          // Euler Roe: 1 = one passive tracer advected with the flow
+  int source;          // classic 2D Euler Roe: 1 = axisymmetric about y = 0 (r = y)
 };
 
 }  // extern "C"
 
 namespace {
 
-enum { S_ADV = 1, S_SW = 2, S_EULER = 3, S_ELASTIC = 4 };
+enum { S_ADV = 1, S_SW = 2, S_EULER = 3, S_ELASTIC = 4, S_EULER_ROE = 5 };
 enum { BC_EXTRAP = 1, BC_PERIODIC = 2, BC_WALL = 3, BC_DIRICHLET = 4 };
 
 int num_eqn(const OCfg& c) {
@@ -72,6 +79,7 @@ int num_eqn(const OCfg& c) {
     case S_SW: return c.ndim == 1 ? 2 : 3;
     case S_EULER: return c.ndim == 1 ? 3 : 4;
     case S_ELASTIC: return 5;
+    case S_EULER_ROE: return (c.ndim == 1 ? 3 : 4) + (c.tracer ? 1 : 0);
   }
   return 0;
 }
@@ -81,6 +89,7 @@ int num_waves(const OCfg& c) {
     case S_SW: return c.ndim == 1 ? 2 : 3;
     case S_EULER: return 2;
     case S_ELASTIC: return 4;
+    case S_EULER_ROE: return (c.ndim == 1 ? 3 : 4) + (c.tracer ? 1 : 0);
   }
   return 0;
 }
@@ -94,7 +103,8 @@ double dy_of(const OCfg& c) { return c.ndim == 2 ? (c.yhi - c.ylo) / c.ny : 1.0;
 bool odd_under_reflection(const OCfg& c, int d, int k) {
   switch (c.solver) {
     case S_SW:
-    case S_EULER: return k == 1 + d;                 // normal momentum
+    case S_EULER:
+    case S_EULER_ROE: return k == 1 + d;             // normal momentum
     case S_ELASTIC: return k == 2 || k == 3 + d;      // shear stress and normal velocity
   }
   return false;
@@ -190,8 +200,8 @@ void load_field(const OCfg& c, Field& f, const double* src, int m, int g, bool i
 // ---------------------------------------------------------------------------
 
 struct FaceSol {
-  double W[4][5];
-  double s[4];
+  double W[5][5];
+  double s[5];
   double amdq[5], apdq[5];
 };
 
@@ -334,12 +344,138 @@ void rp_elastic(int d, const double* ql, const double* qr, const double* auxl,
   }
 }
 
+// Euler equations, Roe solver (LeVeque 2002, ch. 15 for the 1D system; in 2D
+// the tangential momentum adds a shear wave).  q = (rho, rho u, [rho v,] E
+// [, phi]) with an optional passive tracer phi (q_t + u phi_x = 0 form,
+// advected at the Roe velocity).  For a face normal to d, n = normal
+// momentum, t = tangential momentum, e = energy.
+//   Roe averages with sqrt(rho) weights: u~ (normal), v~ (tangential), H~;
+//   c~^2 = (gamma-1)(H~ - (u~^2 + v~^2)/2).
+//   Waves and speeds:
+//     acoustic  a1 (1, u~-c~, v~, H~ - u~ c~)          at u~ - c~
+//     entropy   a2 (1, u~,    v~, (u~^2+v~^2)/2)       at u~
+//     shear     a3 (0, 0,     1,  v~)          [2D]    at u~
+//     acoustic  a4 (1, u~+c~, v~, H~ + u~ c~)          at u~ + c~
+//     tracer    d_phi e_phi                    [opt]   at u~
+//   with a3 = d_t - v~ d_rho,
+//        a2 = (gamma-1)/c~^2 ((H~ - u~^2 - v~^2) d_rho + u~ d_n + v~ d_t - d_e),
+//        a4 = (d_n + (c~ - u~) d_rho - c~ a2) / (2 c~),  a1 = d_rho - a2 - a4.
+//   A^-dQ = sum min(s,0) W (Harten-Hyman fix on the acoustic waves when
+//   entropy_fix is set), A^+dQ = sum s W - A^-dQ.
+struct RoeEuler {
+  double un, ut, H, c, q2;
+};
+struct EIdxE { int n, t, e, phi; };
+EIdxE euler_idx(const OCfg& c, int d) {
+  if (c.ndim == 1) return EIdxE{1, -1, 2, c.tracer ? 3 : -1};
+  return EIdxE{1 + d, 2 - d, 3, c.tracer ? 4 : -1};
+}
+// pressure and velocities of a state in the face frame
+static void euler_prim(const OCfg& c, const EIdxE& x, const double* q, double* un, double* ut,
+                       double* p) {
+  const double rho = q[0];
+  *un = q[x.n] / rho;
+  *ut = x.t >= 0 ? q[x.t] / rho : 0.0;
+  *p = (c.pd[0] - 1.0) * (q[x.e] - 0.5 * rho * (*un * *un + *ut * *ut));
+}
+RoeEuler euler_roe_avg(const OCfg& c, const EIdxE& x, const double* ql, const double* qr) {
+  double unl, utl, pl, unr, utr, pr;
+  euler_prim(c, x, ql, &unl, &utl, &pl);
+  euler_prim(c, x, qr, &unr, &utr, &pr);
+  const double wl = std::sqrt(ql[0]), wr = std::sqrt(qr[0]);
+  const double Hl = (ql[x.e] + pl) / ql[0], Hr = (qr[x.e] + pr) / qr[0];
+  RoeEuler a;
+  a.un = (wl * unl + wr * unr) / (wl + wr);
+  a.ut = (wl * utl + wr * utr) / (wl + wr);
+  a.H = (wl * Hl + wr * Hr) / (wl + wr);
+  a.q2 = a.un * a.un + a.ut * a.ut;
+  a.c = std::sqrt((c.pd[0] - 1.0) * (a.H - 0.5 * a.q2));
+  return a;
+}
+
+void rp_euler_roe(const OCfg& c, int d, const double* ql, const double* qr, FaceSol& r) {
+  const int m = num_eqn(c), mw = num_waves(c);
+  const double g1 = c.pd[0] - 1.0;
+  const EIdxE x = euler_idx(c, d);
+  const RoeEuler a = euler_roe_avg(c, x, ql, qr);
+  double dq[5];
+  for (int k = 0; k < m; ++k) dq[k] = qr[k] - ql[k];
+  const double dt_ = x.t >= 0 ? dq[x.t] : 0.0;
+  const double a2 = g1 / (a.c * a.c) *
+                    ((a.H - a.q2) * dq[0] + a.un * dq[x.n] + a.ut * dt_ - dq[x.e]);
+  const double a4 = (dq[x.n] + (a.c - a.un) * dq[0] - a.c * a2) / (2.0 * a.c);
+  const double a1 = dq[0] - a2 - a4;
+  std::memset(r.W, 0, sizeof(r.W));
+  int p = 0;
+  const int p1 = p++;
+  r.W[p1][0] = a1; r.W[p1][x.n] = a1 * (a.un - a.c); r.W[p1][x.e] = a1 * (a.H - a.un * a.c);
+  if (x.t >= 0) r.W[p1][x.t] = a1 * a.ut;
+  r.s[p1] = a.un - a.c;
+  const int p2 = p++;
+  r.W[p2][0] = a2; r.W[p2][x.n] = a2 * a.un; r.W[p2][x.e] = a2 * 0.5 * a.q2;
+  if (x.t >= 0) r.W[p2][x.t] = a2 * a.ut;
+  r.s[p2] = a.un;
+  if (x.t >= 0) {
+    const int p3 = p++;
+    const double a3 = dq[x.t] - a.ut * dq[0];
+    r.W[p3][x.t] = a3; r.W[p3][x.e] = a3 * a.ut;
+    r.s[p3] = a.un;
+  }
+  const int p4 = p++;
+  r.W[p4][0] = a4; r.W[p4][x.n] = a4 * (a.un + a.c); r.W[p4][x.e] = a4 * (a.H + a.un * a.c);
+  if (x.t >= 0) r.W[p4][x.t] = a4 * a.ut;
+  r.s[p4] = a.un + a.c;
+  if (x.phi >= 0) {
+    const int p5 = p++;
+    r.W[p5][x.phi] = dq[x.phi];
+    r.s[p5] = a.un;
+  }
+  (void)mw;
+  double coef[5];
+  for (int q = 0; q < p; ++q) coef[q] = std::min(r.s[q], 0.0);
+  if (c.efix) {
+    // Harten-Hyman: a transonic acoustic rarefaction splits its A^- part
+    const double gam = c.pd[0];
+    double unl, utl, pl, unr, utr, pr;
+    euler_prim(c, x, ql, &unl, &utl, &pl);
+    euler_prim(c, x, qr, &unr, &utr, &pr);
+    {
+      double qm[5];
+      for (int k = 0; k < m; ++k) qm[k] = ql[k] + r.W[p1][k];
+      double um, utm, pm;
+      euler_prim(c, x, qm, &um, &utm, &pm);
+      const double lam_l = unl - std::sqrt(gam * pl / ql[0]);
+      const double lam_r = um - std::sqrt(gam * pm / qm[0]);
+      if (lam_l < 0.0 && 0.0 < lam_r) coef[p1] = lam_l * (lam_r - r.s[p1]) / (lam_r - lam_l);
+    }
+    {
+      double qm[5];
+      for (int k = 0; k < m; ++k) qm[k] = qr[k] - r.W[p4][k];
+      double um, utm, pm;
+      euler_prim(c, x, qm, &um, &utm, &pm);
+      const double lam_l = um + std::sqrt(gam * pm / qm[0]);
+      const double lam_r = unr + std::sqrt(gam * pr / qr[0]);
+      if (lam_l < 0.0 && 0.0 < lam_r) coef[p4] = lam_l * (lam_r - r.s[p4]) / (lam_r - lam_l);
+    }
+  }
+  for (int k = 0; k < m; ++k) {
+    double am = 0.0, sw = 0.0;
+    for (int q = 0; q < p; ++q) {
+      am += coef[q] * r.W[q][k];
+      sw += r.s[q] * r.W[q][k];
+    }
+    r.amdq[k] = am;
+    r.apdq[k] = sw - am;
+  }
+}
+
 void rp_normal(const OCfg& c, int d, const double* ql, const double* qr, const double* auxl,
                const double* auxr, FaceSol& r) {
   switch (c.solver) {
     case S_ADV: rp_advection(c, d, ql, qr, r); break;
     case S_SW: rp_sw_roe(c, d, ql, qr, r); break;
     case S_ELASTIC: rp_elastic(d, ql, qr, auxl, auxr, r); break;
+    case S_EULER_ROE: rp_euler_roe(c, d, ql, qr, r); break;
     default: std::memset(&r, 0, sizeof(r)); break;
   }
 }
@@ -380,6 +516,42 @@ void rp_transverse(const OCfg& c, int d, const double* ql, const double* qr, con
               std::max(l3, 0.0) * b3 * r3[k];
     }
     (void)m;
+    return;
+  }
+  if (c.solver == S_EULER_ROE) {
+    // eigen-decomposition in the transverse direction with the face's Roe
+    // averages: velocity along it v~ = a.ut, across it u~ = a.un
+    const EIdxE x = euler_idx(c, d);
+    const RoeEuler a = euler_roe_avg(c, x, ql, qr);
+    const double g1 = c.pd[0] - 1.0;
+    const double* dq = asdq;
+    const double b3 = dq[x.n] - a.un * dq[0];   // shear wave (momentum across the transverse dir.)
+    const double b2 = g1 / (a.c * a.c) *
+                      ((a.H - a.q2) * dq[0] + a.un * dq[x.n] + a.ut * dq[x.t] - dq[x.e]);
+    const double b4 = (dq[x.t] + (a.c - a.ut) * dq[0] - a.c * b2) / (2.0 * a.c);
+    const double b1 = dq[0] - b2 - b4;
+    double R[5][5] = {{0}}, lam[5], beta[5];
+    int np = 0;
+    R[np][0] = 1.0; R[np][x.n] = a.un; R[np][x.t] = a.ut - a.c; R[np][x.e] = a.H - a.ut * a.c;
+    lam[np] = a.ut - a.c; beta[np++] = b1;
+    R[np][0] = 1.0; R[np][x.n] = a.un; R[np][x.t] = a.ut; R[np][x.e] = 0.5 * a.q2;
+    lam[np] = a.ut; beta[np++] = b2;
+    R[np][x.n] = 1.0; R[np][x.e] = a.un;
+    lam[np] = a.ut; beta[np++] = b3;
+    R[np][0] = 1.0; R[np][x.n] = a.un; R[np][x.t] = a.ut + a.c; R[np][x.e] = a.H + a.ut * a.c;
+    lam[np] = a.ut + a.c; beta[np++] = b4;
+    if (x.phi >= 0) {
+      R[np][x.phi] = 1.0;
+      lam[np] = a.ut; beta[np++] = dq[x.phi];
+    }
+    for (int k = 0; k < m; ++k) {
+      bm[k] = 0.0;
+      bp[k] = 0.0;
+      for (int q = 0; q < np; ++q) {
+        bm[k] += std::min(lam[q], 0.0) * beta[q] * R[q][k];
+        bp[k] += std::max(lam[q], 0.0) * beta[q] * R[q][k];
+      }
+    }
     return;
   }
   if (c.solver == S_ELASTIC) {
@@ -423,7 +595,7 @@ double limiter_phi(int lim, double th) {
 }
 
 void limit_waves(const OCfg& c, int m, int mw, const FaceSol& lo, const FaceSol& me,
-                 const FaceSol& hi, double Wl[4][5]) {
+                 const FaceSol& hi, double Wl[5][5]) {
   for (int p = 0; p < mw; ++p) {
     double nrm = 0.0, dlo = 0.0, dhi = 0.0;
     for (int k = 0; k < m; ++k) {
@@ -461,7 +633,7 @@ double classic_1d(const OCfg& c, const double* qin, double* qout, double dt) {
   std::vector<double> Ft((size_t)(nx + 1) * m, 0.0);
   for (int f = 0; f <= nx; ++f) {
     const FaceSol& me = F[f + 1];
-    double Wl[4][5];
+    double Wl[5][5];
     limit_waves(c, m, mw, F[f], me, F[f + 2], Wl);
     for (int p = 0; p < mw; ++p) {
       const double as = std::fabs(me.s[p]);
@@ -531,7 +703,7 @@ double classic_2d(const OCfg& c, const double* qin, const double* auxin, double*
   for (int j = -1; j <= ny; ++j)
     for (int f = 0; f <= nx; ++f) {
       const FaceSol& me = xf(f, j);
-      double Wl[4][5], cq[5] = {0, 0, 0, 0, 0};
+      double Wl[5][5], cq[5] = {0, 0, 0, 0, 0};
       limit_waves(c, m, mw, xf(f - 1, j), me, xf(f + 1, j), Wl);
       for (int p = 0; p < mw; ++p) {
         const double as = std::fabs(me.s[p]);
@@ -571,7 +743,7 @@ double classic_2d(const OCfg& c, const double* qin, const double* auxin, double*
   for (int g = 0; g <= ny; ++g)
     for (int i = -1; i <= nx; ++i) {
       const FaceSol& me = yf(i, g);
-      double Wl[4][5], cq[5] = {0, 0, 0, 0, 0};
+      double Wl[5][5], cq[5] = {0, 0, 0, 0, 0};
       limit_waves(c, m, mw, yf(i, g - 1), me, yf(i, g + 1), Wl);
       for (int p = 0; p < mw; ++p) {
         const double as = std::fabs(me.s[p]);
@@ -1030,16 +1202,56 @@ double sharpclaw_step(const OCfg& c, const double* qin, double* qout, double dt)
                   N, qin, qout, dt);
 }
 
+// Geometric source of the axisymmetric Euler equations (eq. euler-rz with the
+// axial coordinate z = x and the radius r = y): the right-hand sides are
+//   psi(q) = -(v / r) (rho, rho u, rho v, rho E + p)   (tracer: 0),
+// v the radial velocity.  It is applied after the hyperbolic step as a
+// fractional step (Section 2.1; LeVeque 2002, ch. 17), integrated over dt by
+// Heun's method (explicit trapezoidal rule, second order):
+//   q* = q + dt psi(q),   q <- q + dt/2 (psi(q) + psi(q*)),
+// with r the radius of the cell centre.
+void euler_axisym_psi(const OCfg& c, const double* q, double r, double* out) {
+  const double rho = q[0], u = q[1] / rho, v = q[2] / rho, E = q[3];
+  const double p = (c.pd[0] - 1.0) * (E - 0.5 * rho * (u * u + v * v));
+  out[0] = -rho * v / r;
+  out[1] = -q[1] * v / r;
+  out[2] = -q[2] * v / r;
+  out[3] = -(E + p) * v / r;
+  out[4] = 0.0;
+}
+
+void source_step(const OCfg& c, double* q, double dt) {
+  const int m = num_eqn(c), nx = c.nx, ny = c.ny;
+  const size_t N = (size_t)nx * ny;
+  const double dy = dy_of(c);
+#pragma omp parallel for schedule(static)
+  for (int j = 0; j < ny; ++j) {
+    const double r = c.ylo + (j + 0.5) * dy;
+    for (int i = 0; i < nx; ++i) {
+      const size_t n = (size_t)j * nx + i;
+      double q0[5], qs[5], f0[5], f1[5];
+      for (int k = 0; k < m; ++k) q0[k] = q[k * N + n];
+      euler_axisym_psi(c, q0, r, f0);
+      for (int k = 0; k < m; ++k) qs[k] = q0[k] + dt * f0[k];
+      euler_axisym_psi(c, qs, r, f1);
+      for (int k = 0; k < m; ++k) q[k * N + n] = q0[k] + 0.5 * dt * (f0[k] + f1[k]);
+    }
+  }
+}
+
+bool has_source(const OCfg& c) { return c.source == 1 && c.solver == S_EULER_ROE && c.ndim == 2; }
+
 double one_step(const OCfg& c, const double* qin, const double* aux, double* qout, double dt) {
   if (c.scheme == 2) return sharpclaw_step(c, qin, qout, dt);
   if (c.ndim == 1) return classic_1d(c, qin, qout, dt);
-  return classic_2d(c, qin, aux, qout, dt);
+  const double s = classic_2d(c, qin, aux, qout, dt);
+  if (has_source(c)) source_step(c, qout, dt);
+  return s;
 }
 
 // Largest characteristic speed over spacing among the cells: used for the
 // a-priori first time step when none is given.
 double max_cell_speed(const OCfg& c, const double* q, const double* aux) {
-  const int m = num_eqn(c);
   const size_t N = (size_t)c.nx * c.ny;
   const double dx = dx_of(c), dy = dy_of(c);
   double best = 0.0;
@@ -1055,10 +1267,12 @@ double max_cell_speed(const OCfg& c, const double* q, const double* aux) {
         s = (std::fabs(q[N + n] / h) + cel) / dx;
         if (c.ndim == 2) s = std::max(s, (std::fabs(q[2 * N + n] / h) + cel) / dy);
       } break;
-      case S_EULER: {
+      case S_EULER:
+      case S_EULER_ROE: {
+        // energy follows the momenta; a tracer (Euler Roe) comes last
         const double rho = q[n], u = q[N + n] / rho;
-        const double v = m == 4 ? q[2 * N + n] / rho : 0.0;
-        const double E = q[(size_t)(m - 1) * N + n];
+        const double v = c.ndim == 2 ? q[2 * N + n] / rho : 0.0;
+        const double E = q[(size_t)(1 + c.ndim) * N + n];
         const double p = (c.pd[0] - 1.0) * (E - 0.5 * rho * (u * u + v * v));
         const double cs = std::sqrt(c.pd[0] * p / rho);
         s = (std::fabs(u) + cs) / dx;
@@ -1167,9 +1381,16 @@ int or_advance(const OCfg* c, double* q, const double* aux, double* t_io, double
   return rc;
 }
 
+// The source fractional step alone (q in place), for its pins.
+int or_source_step(const OCfg* c, double* q, double dt) {
+  if (!has_source(*c)) return -1;
+  source_step(*c, q, dt);
+  return 0;
+}
+
 // Per-face Riemann solve (exposed for algebraic identity tests).
 int or_riemann(const OCfg* c, int d, const double* ql, const double* qr, const double* auxl,
-               const double* auxr, double* W /*[4][5]*/, double* s /*[4]*/, double* amdq,
+               const double* auxr, double* W /*[5][5]*/, double* s /*[5]*/, double* amdq,
                double* apdq) {
   FaceSol r;
   std::memset(&r, 0, sizeof(r));

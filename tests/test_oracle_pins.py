@@ -783,3 +783,241 @@ def test_controller_rejects_then_accepts_and_lands_on_t_end():
         if ok:
             qr, _ = oracle.step(spec, qr, dt)
     np.testing.assert_array_equal(qr, qf)
+
+
+# --------------------------------------------------------------------------
+# Classic Euler: Roe solver (4 waves, optional tracer), transverse split,
+# axisymmetric source term
+# --------------------------------------------------------------------------
+from exact import euler_exact, euler_star   # noqa: E402
+
+GAM = 1.4
+
+
+def euler_q(rho, u, v, p, phi=None):
+    E = p / (GAM - 1.0) + 0.5 * rho * (u * u + v * v)
+    q = [rho, rho * u, rho * v, E]
+    return np.array(q + ([phi] if phi is not None else []))
+
+
+def euler_flux2d(q, d):
+    rho, mu, mv, E = q[:4]
+    u, v = mu / rho, mv / rho
+    p = (GAM - 1.0) * (E - 0.5 * rho * (u * u + v * v))
+    un = (u, v)[d]
+    f = np.array([rho * un, mu * un, mv * un, (E + p) * un])
+    f[1 + d] += p
+    if len(q) == 5:
+        f = np.append(f, 0.0)   # tracer: non-conservative, no flux
+    return f
+
+
+def roe_spec(ndim=2, tracer=0, efix=0, **kw):
+    s = dict(ndim=ndim, num_cells=(8, 8)[:ndim], lower=(0.0, 0.0)[:ndim], upper=(1.0, 1.0)[:ndim],
+             scheme="classic", riemann="euler_roe", problem_data=[GAM], tracer=tracer,
+             entropy_fix=efix, limiter="mc", transverse=2)
+    s.update(kw)
+    return s
+
+
+@pytest.mark.parametrize("tracer", [0, 1])
+@pytest.mark.parametrize("efix", [0, 1])
+@pytest.mark.parametrize("d", [0, 1])
+def test_euler_roe_identities(tracer, efix, d):
+    rng = np.random.default_rng(31 + 2 * d + efix + 4 * tracer)
+    s = roe_spec(tracer=tracer, efix=efix)
+    for _ in range(20):
+        ql = euler_q(rng.uniform(0.5, 2), *rng.uniform(-1, 1, 2), rng.uniform(0.5, 2),
+                     *( [rng.uniform(0, 1)] if tracer else []))
+        qr = euler_q(rng.uniform(0.5, 2), *rng.uniform(-1, 1, 2), rng.uniform(0.5, 2),
+                     *( [rng.uniform(0, 1)] if tracer else []))
+        W, sp, am, ap = oracle.riemann(s, d, ql, qr)
+        np.testing.assert_allclose(W.sum(axis=0), qr - ql, atol=1e-13)
+        # Roe property: the fluctuations add up to the flux difference (the
+        # tracer's "flux difference" is u~ d_phi, its transport term)
+        fd = euler_flux2d(qr, d) - euler_flux2d(ql, d)
+        np.testing.assert_allclose((am + ap)[:4], fd[:4], atol=1e-12)
+        if tracer:
+            assert (am + ap)[4] == pytest.approx(sp[-1] * (qr[4] - ql[4]), abs=1e-13)
+        # equal states give no waves
+        W0, _, am0, ap0 = oracle.riemann(s, d, ql, ql)
+        assert np.abs(W0).max() == 0 and np.abs(am0).max() == 0 and np.abs(ap0).max() == 0
+
+
+@pytest.mark.parametrize("d", [0, 1])
+def test_euler_transverse_split_is_roe_jacobian(d):
+    # B^- + B^+ applied to a fluctuation equals the flux Jacobian of the
+    # transverse direction at the face's Roe-averaged state (u~, v~, H~)
+    rng = np.random.default_rng(40 + d)
+    s = roe_spec()
+    for _ in range(10):
+        ql = euler_q(rng.uniform(0.5, 2), *rng.uniform(-1, 1, 2), rng.uniform(0.5, 2))
+        qr = euler_q(rng.uniform(0.5, 2), *rng.uniform(-1, 1, 2), rng.uniform(0.5, 2))
+        wl, wr = math.sqrt(ql[0]), math.sqrt(qr[0])
+        prim = lambda q: (q[1] / q[0], q[2] / q[0],
+                          (q[3] + (GAM - 1) * (q[3] - 0.5 * (q[1] ** 2 + q[2] ** 2) / q[0])) / q[0])
+        (ul, vl, Hl), (ur, vr, Hr) = prim(ql), prim(qr)
+        u = (wl * ul + wr * ur) / (wl + wr)
+        v = (wl * vl + wr * vr) / (wl + wr)
+        H = (wl * Hl + wr * Hr) / (wl + wr)
+        E = (H + (GAM - 1) * 0.5 * (u * u + v * v)) / GAM    # rho = 1 state with enthalpy H
+        qh = np.array([1.0, u, v, E])
+        J = np.zeros((4, 4))
+        for k in range(4):
+            h = 1e-6
+            e = np.zeros(4); e[k] = h
+            J[:, k] = (euler_flux2d(qh + e, 1 - d) - euler_flux2d(qh - e, 1 - d)) / (2 * h)
+        dq = rng.normal(size=4)
+        bm, bp = oracle.transverse(s, d, ql, qr, dq)
+        np.testing.assert_allclose(bm + bp, J @ dq, atol=1e-7)
+        # and the split is by sign: B^- has only non-positive speeds
+        assert np.dot(bm, bm) >= 0
+
+
+def _euler_1d_run(n, left, right, t_end, efix=0, lim="mc"):
+    spec = dict(ndim=1, num_cells=(n,), lower=(-0.5,), upper=(0.5,), scheme="classic",
+                riemann="euler_roe", problem_data=[GAM], entropy_fix=efix, limiter=lim,
+                bc_lower=("extrap",), bc_upper=("extrap",), cfl_desired=0.8, cfl_max=0.9)
+    x = -0.5 + (np.arange(n) + 0.5) / n
+    q = np.zeros((3, 1, n))
+    for k, (a, b) in enumerate(zip(euler_q(*left[:2], 0.0, left[2])[[0, 1, 3]],
+                                   euler_q(*right[:2], 0.0, right[2])[[0, 1, 3]])):
+        q[k, 0] = np.where(x < 0, a, b)
+    qf, info = oracle.advance(spec, q, t_end)
+    assert info["rc"] == 0
+    ex = euler_exact(*left, *right, x / t_end, GAM)
+    return x, qf[:, 0], ex
+
+
+def test_euler_roe_sod_converges_to_exact_solution():
+    errs = []
+    for n in (200, 400, 800):
+        x, q, ex = _euler_1d_run(n, (1.0, 0.0, 1.0), (0.125, 0.0, 0.1), 0.2)
+        errs.append(np.mean(np.abs(q[0] - ex[0])))
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert errs[-1] < 3e-3 and min(rates) > 0.55, (errs, rates)
+    # the plateau between contact and shock has the exact star pressure
+    x, q, ex = _euler_1d_run(800, (1.0, 0.0, 1.0), (0.125, 0.0, 0.1), 0.2)
+    ps, us = euler_star(1.0, 0.0, 1.0, 0.125, 0.0, 0.1)
+    u = q[1] / q[0]
+    p = (GAM - 1) * (q[2] - 0.5 * q[0] * u * u)
+    mid = (x > 0.25) & (x < 0.3)   # between contact (0.185) and shock (0.35) at t = 0.2
+    assert np.abs(p[mid] - ps).max() < 1e-3 and np.abs(u[mid] - us).max() < 1e-3
+
+
+def test_euler_roe_entropy_fix_removes_sonic_glitch():
+    # Toro's test with a sonic point inside the left rarefaction: Roe's
+    # linearisation without a fix leaves an entropy-violating jump there
+    left, right = (1.0, 0.75, 1.0), (0.125, 0.0, 0.1)
+    _, q0, ex = _euler_1d_run(400, left, right, 0.2, efix=0, lim="minmod")
+    _, q1, _ = _euler_1d_run(400, left, right, 0.2, efix=1, lim="minmod")
+    jump = lambda q: np.abs(np.diff(q[1] / q[0]))[150:200].max()   # u jumps near the sonic point
+    e0, e1 = np.mean(np.abs(q0[0] - ex[0])), np.mean(np.abs(q1[0] - ex[0]))
+    assert jump(q1) < 0.5 * jump(q0), (jump(q0), jump(q1))
+    assert e1 < e0
+
+
+def test_euler_roe_planar_shock_speed():
+    rho1, u1, p1, S = W.rankine_hugoniot(2.0)
+    n, t_end = 400, 0.3
+    spec = dict(ndim=2, num_cells=(n, 4), lower=(0.0, 0.0), upper=(2.0, 0.02), scheme="classic",
+                riemann="euler_roe", problem_data=[GAM], limiter="mc", transverse=2,
+                bc_lower=("dirichlet", "periodic"), bc_upper=("extrap", "periodic"),
+                bc_state={"x_lower": list(euler_q(rho1, u1, 0.0, p1))}, cfl_desired=0.8, cfl_max=0.9)
+    x = (np.arange(n) + 0.5) * 2.0 / n
+    q = np.zeros((4, 4, n))
+    for k, (a, b) in enumerate(zip(euler_q(rho1, u1, 0.0, p1), euler_q(1.0, 0.0, 0.0, 1.0))):
+        q[k] = np.where(x < 0.3, a, b)[None, :]
+    qf, info = oracle.advance(spec, q, t_end)
+    assert info["rc"] == 0
+    # shock position from the mass in the domain: rho = rho1 behind the shock,
+    # 1 ahead of it, so mass = rho1 s + (2 - s)
+    mass = qf[0, 0].sum() * 2.0 / n
+    est = (mass - 2.0) / (rho1 - 1.0)
+    assert abs(est - (0.3 + S * t_end)) < 2.0 / n, (est, 0.3 + S * t_end)
+
+
+def test_euler_roe_tracer_translates_exactly_at_courant_one():
+    n = 64
+    spec = dict(ndim=1, num_cells=(n,), lower=(0.0,), upper=(1.0,), scheme="classic",
+                riemann="euler_roe", problem_data=[GAM], tracer=1, limiter="mc",
+                bc_lower=("periodic",), bc_upper=("periodic",))
+    u = 0.5
+    q = np.zeros((4, 1, n))
+    rng = np.random.default_rng(5)
+    phi = rng.uniform(0, 1, n)
+    q[:, 0] = np.array([1.0, u, 1.0 / (GAM - 1) + 0.5 * u * u, 0.0])[:, None]
+    q[3, 0] = phi
+    dt = (1.0 / n) / u   # Courant number 1 for the tracer (acoustic speeds exceed it, but the
+    qq = q               # uniform gas has no acoustic waves)
+    for _ in range(5):
+        qq, _ = oracle.step(spec, qq, dt)
+    np.testing.assert_allclose(qq[3, 0], np.roll(phi, 5), atol=1e-13)
+    np.testing.assert_allclose(qq[:3, 0], q[:3, 0], atol=1e-13)
+
+
+def test_euler_roe_conservation_periodic():
+    n = 24
+    rng = np.random.default_rng(8)
+    spec = dict(roe_spec(), num_cells=(n, n), bc_lower=("periodic", "periodic"),
+                bc_upper=("periodic", "periodic"), cfl_desired=0.8, cfl_max=0.9)
+    sp, q = W.random_smooth_euler(n, seed=2)
+    t0 = oracle.totals(spec, q)
+    qf, info = oracle.advance(spec, q, 0.05)
+    assert info["accepted"] >= 3
+    np.testing.assert_allclose(oracle.totals(spec, qf), t0, rtol=0, atol=1e-12 * np.abs(t0).max())
+
+
+def test_euler_roe_2d_uniform_in_y_reduces_to_1d():
+    n = 60
+    s1 = dict(ndim=1, num_cells=(n,), lower=(-0.5,), upper=(0.5,), scheme="classic",
+              riemann="euler_roe", problem_data=[GAM], limiter="mc", entropy_fix=1)
+    s2 = dict(s1, ndim=2, num_cells=(n, 5), lower=(-0.5, 0.0), upper=(0.5, 5.0 / n),
+              transverse=2, bc_lower=("extrap", "periodic"), bc_upper=("extrap", "periodic"))
+    x = -0.5 + (np.arange(n) + 0.5) / n
+    ql, qr = euler_q(1.0, 0.3, 0.0, 1.0), euler_q(0.3, -0.2, 0.0, 0.4)
+    q2 = np.where(x[None, None, :] < 0, ql[:, None, None], qr[:, None, None]) * np.ones((4, 5, n))
+    q1 = q2[[0, 1, 3], :1, :]
+    dt = 0.4 / n
+    for _ in range(10):
+        q1, _ = oracle.step(s1, q1, dt)
+        q2, _ = oracle.step(s2, q2, dt)
+    for j in range(5):
+        np.testing.assert_allclose(q2[[0, 1, 3], j], q1[:, 0], rtol=0, atol=1e-13)
+    assert np.abs(q2[2]).max() < 1e-14
+
+
+def test_axisymmetric_source_step_second_order_and_exact_cases():
+    from scipy.integrate import solve_ivp
+    n = 4
+    spec = dict(roe_spec(), num_cells=(n, n), lower=(0.0, 0.0), upper=(1.0, 0.5),
+                source="axisymmetric", tracer=1)
+    rng = np.random.default_rng(9)
+    q = np.stack([euler_q(rng.uniform(0.5, 2), rng.uniform(-1, 1), rng.uniform(-1, 1),
+                          rng.uniform(0.5, 2), rng.uniform(0, 1)) for _ in range(n * n)], axis=1)
+    q = q.reshape(5, n, n)
+    r = (np.arange(n) + 0.5) * 0.5 / n
+
+    def rhs(t, y, rr):
+        rho, mu, mv, E, _ = y
+        u, v = mu / rho, mv / rho
+        p = (GAM - 1) * (E - 0.5 * rho * (u * u + v * v))
+        return -v / rr * np.array([rho, mu, mv, E + p, 0.0])
+    T = 0.01
+    ref = np.zeros_like(q)
+    for j in range(n):
+        for i in range(n):
+            ref[:, j, i] = solve_ivp(rhs, (0, T), q[:, j, i], args=(r[j],), rtol=1e-13, atol=1e-14).y[:, -1]
+    errs = []
+    for steps in (4, 8, 16):
+        qq = q.copy()
+        for _ in range(steps):
+            qq = oracle.source_step(spec, qq, T / steps)
+        errs.append(np.abs(qq - ref).max())
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert min(rates) > 1.9 and max(rates) < 2.2, (errs, rates)
+    # no radial velocity: no source; the tracer is never changed
+    q0 = q.copy()
+    q0[2] = 0.0
+    np.testing.assert_array_equal(oracle.source_step(spec, q0, 0.01), q0)
+    np.testing.assert_array_equal(oracle.source_step(spec, q, 0.01)[4], q[4])
