@@ -102,7 +102,13 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 # plus compensation and aux):
 #   sw 48 per cell-step (FP64 q; FP32 q + c); euler per stage 256/3 (FP64),
 #   160/3 (FP32+Kahan); elastic 104 (FP64), 92 (FP32+Kahan) per cell-step.
-FLOPS_PER_CELL = {"sw": 554.0, "euler_stage": 1040.0}
+#   euler_stage_weno7  the same with WENO7: edge pair per component and
+#            direction 200 (candidates 56, smoothness indicators 96, weights
+#            and normalisation 48) -> 8 x 200 + 204 + 20 + 12 + 2 = 1840
+#   SSPRK(10,4) stage bytes, FP64, averaged over the ten stages: eight plain
+#   stages 64 B (S in, y out), stage 5 128 B (S, Q in; two registers out),
+#   stage 10 96 B (S, S3 in; Q out) -> 73.6 B per cell-stage.
+FLOPS_PER_CELL = {"sw": 554.0, "euler_stage": 1040.0, "euler_stage_weno7": 1840.0}
 
 
 def roofline(bound, cells, gpu_ms, launches, kernel_name, bytes_per_launch, flops_per_launch=None,
@@ -336,6 +342,19 @@ def main():
                 r["l1_err_vs_fp64_oracle"] = l1_error_fp32(lambda n: W.shock_bubble(2 * n, n), 128, 0.1)
                 r["l1_err_sample"] = "256x128 to t=0.1 (shock through the bubble), oracle dt sequence"
             extras[f"euler_shock_bubble_2048x1024_{prec}"] = r
+
+        log("shock-bubble 2048x1024 SharpClaw SSPRK(10,4) (the SharpClaw default), WENO5 / WENO7")
+        for order in (5, 7):
+            spec104 = dict(sb_spec, time_integrator="ssp104", weno_order=order, cfl_desired=2.45,
+                           cfl_max=2.5)
+            r = timed_run(spec104, sb_q, None, 10, 2, 1.0)
+            r["roofline"] = roofline("alu", r["cells"], r["gpu_ms"], 10 * (r["steps"] + r["rejected"]),
+                                     "k_sharp2d<double,EulerHLLE,SSPRK104>",
+                                     73.6 * r["cells"],
+                                     (FLOPS_PER_CELL["euler_stage"] if order == 5 else
+                                      FLOPS_PER_CELL["euler_stage_weno7"]) * r["cells"], "f64")
+            r["cfl"] = [2.45, 2.5]
+            extras[f"euler_shock_bubble_2048x1024_fp64_ssp104_weno{order}"] = r
 
         log("layered elasticity 2048^2")
         el_spec, el_q, el_aux = W.layered_elastic(2048)

@@ -80,8 +80,19 @@ enum claw_riemann {
                              problem_data = (g); m = 2 (1D) or 3 (2D); classic only */
   CLAW_RP_EULER_HLLE = 3, /* Euler, HLLE flux, problem_data = (gamma); m = 3 (1D) or 4 (2D);
                              SharpClaw only */
-  CLAW_RP_ELASTIC_VC = 4  /* 2D linear elasticity, variable coefficients, m = 5,
+  CLAW_RP_ELASTIC_VC = 4, /* 2D linear elasticity, variable coefficients, m = 5,
                              q = (s11, s22, s12, u, v), aux = (rho, lambda, mu); classic, 2D only */
+  CLAW_RP_EULER_ROE = 5   /* Euler, Roe solver (two acoustic, entropy and - in 2D - shear waves)
+                             with its transverse solver, problem_data = (gamma); m = 3 (1D) or
+                             4 (2D), plus one with a tracer; optional Harten-Hyman entropy fix;
+                             classic only */
+};
+enum claw_source {
+  CLAW_SOURCE_NONE = 0,
+  CLAW_SOURCE_AXISYMMETRIC = 1  /* CLAW_RP_EULER_ROE in 2D: cylindrical symmetry about y = 0
+                                   (x = axial coordinate z, y = radius r > 0), geometric source
+                                   -(v/r)(rho, rho u, rho v, E + p) applied after each hyperbolic
+                                   step by one step of Heun's method (fractional step) */
 };
 enum claw_limiter { CLAW_LIM_NONE = 0, CLAW_LIM_MINMOD = 1, CLAW_LIM_MC = 2 };
 enum claw_bc { CLAW_BC_EXTRAP = 1, CLAW_BC_PERIODIC = 2, CLAW_BC_WALL = 3, CLAW_BC_DIRICHLET = 4 };
@@ -120,6 +131,9 @@ typedef struct claw_config {
   int time_integrator;   /* SharpClaw: claw_integrator (0 = CLAW_SSP33); ignored by classic */
   int weno_order;        /* SharpClaw: 5 or 7 (0 = 5); ignored by classic.  Any other value:
                             CLAW_E_INVAL */
+  int tracer;            /* CLAW_RP_EULER_ROE: 1 adds a passive tracer as the last component,
+                            advected by the flow (q_t + u phi_x + v phi_y = 0); else 0 */
+  int source;            /* claw_source (0 = none) */
 } claw_config;
 
 /* Clock and counters of a handle; also the checkpoint record of the

@@ -66,8 +66,13 @@ int num_eqn_of(const claw_config& c) {
     case CLAW_RP_SW_ROE: return c.ndim == 1 ? 2 : 3;
     case CLAW_RP_EULER_HLLE: return c.ndim == 1 ? 3 : 4;
     case CLAW_RP_ELASTIC_VC: return 5;
+    case CLAW_RP_EULER_ROE: return (c.ndim == 1 ? 3 : 4) + (c.tracer ? 1 : 0);
   }
   return 0;
+}
+// Kernel variant of the Riemann solver (the tracer is a separate instance).
+int kernel_riemann(const claw_config& c) {
+  return c.riemann == CLAW_RP_EULER_ROE && c.tracer ? 6 : c.riemann;
 }
 int num_aux_of(const claw_config& c) { return c.riemann == CLAW_RP_ELASTIC_VC ? 3 : 0; }
 
@@ -85,10 +90,15 @@ int validate(const claw_config* c) {
       return CLAW_E_INVAL;
   }
   if (c->precision != CLAW_FP64 && c->precision != CLAW_FP32_KAHAN) return CLAW_E_INVAL;
+  if (c->tracer != 0 && (c->tracer != 1 || c->riemann != CLAW_RP_EULER_ROE)) return CLAW_E_INVAL;
+  if (c->source != CLAW_SOURCE_NONE &&
+      (c->source != CLAW_SOURCE_AXISYMMETRIC || c->riemann != CLAW_RP_EULER_ROE || c->ndim != 2 ||
+       !(c->lower[1] >= 0.0)))
+    return CLAW_E_INVAL;
   if (c->scheme == CLAW_CLASSIC) {
     if (c->riemann == CLAW_RP_EULER_HLLE) return CLAW_E_INVAL;
     if (c->riemann == CLAW_RP_ELASTIC_VC && c->ndim != 2) return CLAW_E_INVAL;
-    if (c->riemann < 1 || c->riemann > 4) return CLAW_E_INVAL;
+    if (c->riemann < 1 || c->riemann > 5) return CLAW_E_INVAL;
     if (c->limiter < CLAW_LIM_NONE || c->limiter > CLAW_LIM_MC) return CLAW_E_INVAL;
     if (c->transverse < 0 || c->transverse > 2) return CLAW_E_INVAL;
   } else if (c->scheme == CLAW_SHARPCLAW) {
@@ -119,6 +129,7 @@ struct claw_solver {
   claw_config cfg;
   int device = 0;
   int m = 0, na = 0, fp32 = 0;
+  int kr = 0;                    // kernel variant of the Riemann solver
   size_t ncell = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -192,7 +203,7 @@ size_t layout(const claw_config& c, size_t off[16]) {
 
 int seg_rows_for(claw_t h) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  auto key = std::make_tuple(h->cfg.scheme, h->cfg.riemann, h->cfg.precision, h->cfg.weno_order,
+  auto key = std::make_tuple(h->cfg.scheme, h->kr, h->cfg.precision, h->cfg.weno_order,
                              h->cfg.num_cells[0], h->cfg.ndim == 2 ? h->cfg.num_cells[1] : 1);
   auto it = g_tune.find(key);
   return it != g_tune.end() ? it->second : default_seg_rows(h->cfg.ndim == 2 ? h->cfg.num_cells[1] : 1);
@@ -317,10 +328,10 @@ int launch_attempt_host(claw_t h, double dt, bool stage1_only) {
   const GridDesc& g = h->hg;
   if (h->cfg.scheme == CLAW_CLASSIC) {
     if (h->cfg.ndim == 2)
-      HIPCHK(launch_classic2d(h->cfg.riemann, h->fp32, g.limiter, g.transverse, g.nblocks, h->stream, h->d_grid, nullptr, 1,
+      HIPCHK(launch_classic2d(h->kr, h->fp32, g.limiter, g.transverse, g.nblocks, h->stream, h->d_grid, nullptr, 1,
                               kHostDt, dt, h->src));
     else
-      HIPCHK(launch_classic1d(h->cfg.riemann, h->fp32, g.nblocks, h->stream, h->d_grid, kHostDt, dt,
+      HIPCHK(launch_classic1d(h->kr, h->fp32, g.nblocks, h->stream, h->d_grid, kHostDt, dt,
                               h->src));
   } else {
     return launch_sharp_stages(h, 0, stage1_only ? 1 : 10, kHostDt, dt);
@@ -335,10 +346,10 @@ int launch_attempt_device(claw_t h) {
   const GridDesc& g = h->hg;
   if (h->cfg.scheme == CLAW_CLASSIC) {
     if (h->cfg.ndim == 2)
-      HIPCHK(launch_classic2d(h->cfg.riemann, h->fp32, g.limiter, g.transverse, g.nblocks, h->stream, h->d_grid, nullptr, 1,
+      HIPCHK(launch_classic2d(h->kr, h->fp32, g.limiter, g.transverse, g.nblocks, h->stream, h->d_grid, nullptr, 1,
                               kDeviceCtrl, 0.0, 0));
     else
-      HIPCHK(launch_classic1d(h->cfg.riemann, h->fp32, g.nblocks, h->stream, h->d_grid, kDeviceCtrl,
+      HIPCHK(launch_classic1d(h->kr, h->fp32, g.nblocks, h->stream, h->d_grid, kDeviceCtrl,
                               0.0, 0));
   } else {
     return launch_sharp_stages(h, 0, 10, kDeviceCtrl, 0.0);
@@ -349,7 +360,7 @@ int launch_attempt_device(claw_t h) {
 // A-priori first dt: cfl_desired / max cell speed.
 int apriori_dt(claw_t h, double* dt) {
   HIPCHK(hipMemsetAsync(h->d_speed, 0, sizeof(unsigned long long), h->stream));
-  HIPCHK(launch_cell_speed(h->cfg.ndim, h->cfg.riemann, h->fp32, h->d_grid, h->src, h->ncell,
+  HIPCHK(launch_cell_speed(h->cfg.ndim, h->kr, h->fp32, h->d_grid, h->src, h->ncell,
                            h->d_speed, h->stream));
   unsigned long long bits = 0;
   HIPCHK(hipMemcpyAsync(&bits, h->d_speed, sizeof(bits), hipMemcpyDeviceToHost, h->stream));
@@ -455,6 +466,7 @@ int claw_create(const claw_config* cfg, void* d_ws, size_t ws_bytes, void* hip_s
   if (hipGetDevice(&h->device) != hipSuccess) { delete h; return CLAW_E_DEVICE; }
   h->m = num_eqn_of(*cfg);
   h->na = num_aux_of(*cfg);
+  h->kr = kernel_riemann(*cfg);
   h->fp32 = cfg->precision == CLAW_FP32_KAHAN;
   h->ncell = (size_t)cfg->num_cells[0] * (cfg->ndim == 2 ? cfg->num_cells[1] : 1);
   if (hip_stream) {
@@ -488,6 +500,8 @@ int claw_create(const claw_config* cfg, void* d_ws, size_t ws_bytes, void* hip_s
   g.scheme = cfg->scheme;
   g.dx = (cfg->upper[0] - cfg->lower[0]) / g.nx;
   g.dy = cfg->ndim == 2 ? (cfg->upper[1] - cfg->lower[1]) / g.ny : 1.0;
+  g.ylo = cfg->ndim == 2 ? cfg->lower[1] : 0.0;
+  g.source = cfg->source;
   g.weno_eps = h->cfg.weno_eps;
   std::memcpy(g.bcstate, cfg->bc_state, sizeof(g.bcstate));
   std::memcpy(g.pd, cfg->problem_data, sizeof(g.pd));
@@ -685,7 +699,7 @@ int claw_advance_graph(claw_t h, double t_end, int k, long long max_steps, claw_
   const bool run1d = h->cfg.ndim == 1 && h->cfg.scheme == CLAW_CLASSIC &&
                      classic1d_run_smem(h->m, h->hg.nx, h->fp32) <= kRun1dSmemMax;
   if (run1d) {
-    HIPCHK(launch_classic1d_run(h->cfg.riemann, h->fp32, h->m, h->hg.nx, h->stream, h->d_grid));
+    HIPCHK(launch_classic1d_run(h->kr, h->fp32, h->m, h->hg.nx, h->stream, h->d_grid));
     if ((rc = read_ctrl(h))) return rc;
   } else {
     if (!h->graph || h->graph_k != k) {
@@ -823,7 +837,7 @@ int claw_autotune(claw_t h, int reps, claw_tuning* out) {
   if (rc) return rc;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[std::make_tuple(h->cfg.scheme, h->cfg.riemann, h->cfg.precision, h->cfg.weno_order,
+    g_tune[std::make_tuple(h->cfg.scheme, h->kr, h->cfg.precision, h->cfg.weno_order,
                            h->hg.nx, ny)] = best;
   }
   set_tiling(h, best);
@@ -960,7 +974,7 @@ int claw_batch_add(claw_batch_t b, claw_t h, double t_end) {
   for (claw_t o : b->members)
     if (o == h) return CLAW_E_INVAL;
   if (!b->members.empty() &&
-      (b->riemann != h->cfg.riemann || b->fp32 != h->fp32 || b->limiter != h->hg.limiter ||
+      (b->riemann != h->kr || b->fp32 != h->fp32 || b->limiter != h->hg.limiter ||
        b->transverse != h->hg.transverse))
     return CLAW_E_INVAL;
   HIPCHK(hipSetDevice(b->device));
@@ -972,7 +986,7 @@ int claw_batch_add(claw_batch_t b, claw_t h, double t_end) {
   *h->h_ctrl = c;
   HIPCHK(hipMemcpyAsync(h->d_ctrl, h->h_ctrl, sizeof(Ctrl), hipMemcpyHostToDevice, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
-  b->riemann = h->cfg.riemann;
+  b->riemann = h->kr;
   b->fp32 = h->fp32;
   b->limiter = h->hg.limiter;
   b->transverse = h->hg.transverse;

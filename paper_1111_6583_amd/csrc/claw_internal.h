@@ -37,7 +37,9 @@ struct GridDesc {
   int nblocks;                    // workgroups of one launch over this grid
   int bc[4];                      // x-lower, x-upper, y-lower, y-upper
   int limiter, transverse, efix, scheme;
+  int source;                     // 1: axisymmetric Euler source (r = y), fractional step
   double dx, dy;
+  double ylo;                     // lower y of the domain (radius of the source term)
   double weno_eps;
   double bcstate[4][8];
   double pd[8];

@@ -293,6 +293,7 @@ __global__ __launch_bounds__(kLanes) void k_classic2d(const GridDesc* __restrict
     if (st.d) {
       const int f = r - 2;
       const size_t off = (size_t)f * nx + i;
+      R xs[M], ys[M];
 #pragma unroll
       for (int k = 0; k < M; ++k) {
         const R ftr = shfl_prev(faR2[k]) + faL2[k];   // transverse part of F~ at x-face i-1/2
@@ -300,16 +301,49 @@ __global__ __launch_bounds__(kLanes) void k_classic2d(const GridDesc* __restrict
         const R fm = shfl_next(fxm2[k] + ftr);         // A^-dQ + F~ at i+1/2
         const R gp = glo[k] - gtr_lo[k];               // B^+dQ - G~ at r-5/2
         const R gm = ghi[k] + gtr_cur[k];              // B^-dQ + G~ at r-3/2
-        const R xs = fp + fm, ys = gp + gm;
+        xs[k] = fp + fm;
+        ys[k] = gp + gm;
+      }
+      if constexpr (P::kSource) {
+        // geometric source as a fractional step after the hyperbolic update,
+        // fused here: pointwise on the updated cell, so the same arithmetic
+        // as a separate pass over the new state
+        R inc[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) inc[k] = -(dtdx * xs[k] + dtdy * ys[k]);
+        if (G.source) {
+          const R ir = (R)(1.0 / (G.ylo + (f + 0.5) * G.dy));
+          R qs[4], ds[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) qs[k] = q0[k] + inc[k];
+          phys.source_increment(qs, ir, (R)dt, ds);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) inc[k] += ds[k];
+        }
         if (own) {
+#pragma unroll
+          for (int k = 0; k < M; ++k) {
+            if constexpr (KAHAN) {
+              const R y = inc[k] - cprev[k];
+              const R t = q0[k] + y;
+              cout[k * plane + off] = (t - q0[k]) - y;
+              qo[k * plane + off] = t;
+            } else {
+              qo[k * plane + off] = q0[k] + inc[k];
+            }
+          }
+        }
+      } else if (own) {
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
           if constexpr (KAHAN) {
-            const R inc = -(dtdx * xs + dtdy * ys);
+            const R inc = -(dtdx * xs[k] + dtdy * ys[k]);
             const R y = inc - cprev[k];
             const R t = q0[k] + y;
             cout[k * plane + off] = (t - q0[k]) - y;
             qo[k * plane + off] = t;
           } else {
-            qo[k * plane + off] = q0[k] - dtdx * xs - dtdy * ys;
+            qo[k * plane + off] = q0[k] - dtdx * xs[k] - dtdy * ys[k];
           }
         }
       }
@@ -598,6 +632,14 @@ static hipError_t launch2d_lt(int riemann, dim3 grid, hipStream_t st, const Grid
       hipLaunchKernelGGL((k_classic2d<R, Elastic<R>, K, LIM, TRANS>), grid, dim3(kLanes), 0, st, g,
                          bs, ng, mode, dt, src);
       break;
+    case 5:
+      hipLaunchKernelGGL((k_classic2d<R, EulerRoe<R, 2, false>, K, LIM, TRANS>), grid, dim3(kLanes),
+                         0, st, g, bs, ng, mode, dt, src);
+      break;
+    case 6:
+      hipLaunchKernelGGL((k_classic2d<R, EulerRoe<R, 2, true>, K, LIM, TRANS>), grid, dim3(kLanes),
+                         0, st, g, bs, ng, mode, dt, src);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -650,6 +692,14 @@ static hipError_t launch1d_t(int riemann, dim3 grid, hipStream_t st, const GridD
       hipLaunchKernelGGL((k_classic1d<R, ShallowWater<R, 1>, K>), grid, dim3(kLanes), 0, st, g,
                          nullptr, 1, mode, dt, src);
       break;
+    case 5:
+      hipLaunchKernelGGL((k_classic1d<R, EulerRoe<R, 1, false>, K>), grid, dim3(kLanes), 0, st, g,
+                         nullptr, 1, mode, dt, src);
+      break;
+    case 6:
+      hipLaunchKernelGGL((k_classic1d<R, EulerRoe<R, 1, true>, K>), grid, dim3(kLanes), 0, st, g,
+                         nullptr, 1, mode, dt, src);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -676,6 +726,14 @@ static hipError_t launch1d_run_t(int riemann, size_t smem, hipStream_t st, const
       break;
     case 2:
       hipLaunchKernelGGL((k_classic1d_run<R, ShallowWater<R, 1>, K>), dim3(1),
+                         dim3(kPersistThreads), smem, st, g);
+      break;
+    case 5:
+      hipLaunchKernelGGL((k_classic1d_run<R, EulerRoe<R, 1, false>, K>), dim3(1),
+                         dim3(kPersistThreads), smem, st, g);
+      break;
+    case 6:
+      hipLaunchKernelGGL((k_classic1d_run<R, EulerRoe<R, 1, true>, K>), dim3(1),
                          dim3(kPersistThreads), smem, st, g);
       break;
     default: return hipErrorInvalidValue;

@@ -147,6 +147,8 @@ static hipError_t cell_speed_t(int ndim, int riemann, const GridDesc* g, int src
       case 2: hipLaunchKernelGGL((k_cell_speed<R, ShallowWater<R, 2>>), grid, blk, 0, st, g, src, out); break;
       case 3: hipLaunchKernelGGL((k_cell_speed<R, EulerHLLE<R, 2>>), grid, blk, 0, st, g, src, out); break;
       case 4: hipLaunchKernelGGL((k_cell_speed<R, Elastic<R>>), grid, blk, 0, st, g, src, out); break;
+      case 5: hipLaunchKernelGGL((k_cell_speed<R, EulerRoe<R, 2, false>>), grid, blk, 0, st, g, src, out); break;
+      case 6: hipLaunchKernelGGL((k_cell_speed<R, EulerRoe<R, 2, true>>), grid, blk, 0, st, g, src, out); break;
       default: return hipErrorInvalidValue;
     }
   } else {
@@ -154,6 +156,8 @@ static hipError_t cell_speed_t(int ndim, int riemann, const GridDesc* g, int src
       case 1: hipLaunchKernelGGL((k_cell_speed<R, Advection<R, 1>>), grid, blk, 0, st, g, src, out); break;
       case 2: hipLaunchKernelGGL((k_cell_speed<R, ShallowWater<R, 1>>), grid, blk, 0, st, g, src, out); break;
       case 3: hipLaunchKernelGGL((k_cell_speed<R, EulerHLLE<R, 1>>), grid, blk, 0, st, g, src, out); break;
+      case 5: hipLaunchKernelGGL((k_cell_speed<R, EulerRoe<R, 1, false>>), grid, blk, 0, st, g, src, out); break;
+      case 6: hipLaunchKernelGGL((k_cell_speed<R, EulerRoe<R, 1, true>>), grid, blk, 0, st, g, src, out); break;
       default: return hipErrorInvalidValue;
     }
   }

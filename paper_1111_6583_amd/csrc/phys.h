@@ -46,6 +46,7 @@ template <typename R> __device__ __forceinline__ R rabs(R a) { return a < R(0) ?
 template <typename R, int NDIM>
 struct Advection {
   static constexpr int M = 1, MW = 1, NA = 0;
+  static constexpr bool kSource = false;
   struct Cell {};
   struct Face {};
   R u, v;
@@ -95,6 +96,7 @@ struct ShallowWater {
   static constexpr int MW = M;
   static constexpr int NA = 0;
   static constexpr int LAST = MW - 1;
+  static constexpr bool kSource = false;
   struct Cell {
     R u, v, sh, c;   // velocities, sqrt(h), celerity sqrt(g h)
   };
@@ -266,6 +268,7 @@ struct ShallowWater {
 template <typename R>
 struct Elastic {
   static constexpr int M = 5, MW = 4, NA = 3;
+  static constexpr bool kSource = false;
   struct Cell {
     R lam, mu, a, cp, cs;   // Lame parameters, lambda + 2 mu, P and S speeds
   };
@@ -398,6 +401,258 @@ __device__ __forceinline__ R limiter_phi_t(R num, R den) {
     return ok ? phi : R(0);
   }
 }
+
+// ---------------------------------------------------------------------------
+// Euler equations, Roe solver (LeVeque 2002, ch. 15; the 2D system adds a
+// shear wave), optional passive tracer phi advected at the Roe velocity, and
+// an optional Harten-Hyman entropy fix on the acoustic waves.
+// q = (rho, rho u, [rho v,] E [, phi]).  For a face normal to D the waves are
+//   0 acoustic  a1 (1, u-c, v, H - u c)      speed u - c
+//   1 entropy   a2 (1, u,   v, (u^2+v^2)/2)  speed u
+//   2 shear     a3 (0, 0,   1, v)    [2D]    speed u
+//   . acoustic  a4 (1, u+c, v, H + u c)      speed u + c
+//   . tracer    d_phi e_phi          [opt]   speed u
+// in (rho, normal, tangential, E) order with Roe averages u (normal), v
+// (tangential), H, c; a3 = d_t - v d_rho, a2 = (gamma-1)/c^2 ((H - u^2 - v^2)
+// d_rho + u d_n + v d_t - d_E), a4 = (d_n + (c - u) d_rho - c a2) / (2c),
+// a1 = d_rho - a2 - a4.  2D axisymmetric flows (z = x, r = y) add the
+// geometric source of eq. euler-rz as a fractional step (Heun's method).
+// ---------------------------------------------------------------------------
+template <typename R, int NDIM, bool TRACER>
+struct EulerRoe {
+  static constexpr int M = 2 + NDIM + (TRACER ? 1 : 0);
+  static constexpr int MW = M;
+  static constexpr int NA = 0;
+  static constexpr int EI = 1 + NDIM;                  // energy
+  static constexpr int PHI = TRACER ? 2 + NDIM : -1;   // tracer
+  static constexpr int ACR = NDIM == 2 ? 3 : 2;        // right acoustic wave
+  static constexpr bool kSource = NDIM == 2;
+  struct Cell {
+    R u, v, sr, H, c;   // velocities, sqrt(rho), enthalpy, sound speed
+  };
+  struct Face {
+    R un, ut, H, c, q2, i2c, g1c2;   // Roe averages; 1/(2c); (gamma-1)/c^2
+  };
+  R gamma, g1;
+  int efix;
+  __device__ explicit EulerRoe(const GridDesc& G)
+      : gamma((R)G.pd[0]), g1((R)G.pd[0] - R(1)), efix(G.efix) {}
+
+  template <int D>
+  static constexpr bool nz(int p, int k) {
+    if (TRACER && (p == M - 1 || k == M - 1)) return p == M - 1 && k == M - 1;
+    if (NDIM == 2 && p == 2) return k == 2 - D || k == EI;   // shear: tangential momentum, E
+    return true;
+  }
+  static constexpr bool odd(int d, int k) { return k == 1 + d; }
+
+  __device__ __forceinline__ Cell cell(const R* q, const R*) const {
+    const R is = frsq(q[0]);           // 1/sqrt(rho)
+    const R ir = is * is;
+    Cell c;
+    c.sr = q[0] * is;
+    c.u = q[1] * ir;
+    c.v = NDIM == 2 ? q[2] * ir : R(0);
+    const R p = g1 * (q[EI] - R(0.5) * (q[1] * c.u + (NDIM == 2 ? q[2] * c.v : R(0))));
+    c.H = (q[EI] + p) * ir;
+    c.c = fsqrt(gamma * p * ir);
+    return c;
+  }
+  __device__ __forceinline__ static Cell shfl_prev_cell(const Cell& c) {
+    return Cell{shfl_prev(c.u), NDIM == 2 ? shfl_prev(c.v) : R(0), shfl_prev(c.sr), shfl_prev(c.H),
+                shfl_prev(c.c)};
+  }
+  __device__ __forceinline__ static Cell shfl_next_cell(const Cell& c) {
+    return Cell{shfl_next(c.u), NDIM == 2 ? shfl_next(c.v) : R(0), shfl_next(c.sr), shfl_next(c.H),
+                shfl_next(c.c)};
+  }
+  __device__ __forceinline__ static Face shfl_next_face(const Face& f) {
+    return Face{shfl_next(f.un), shfl_next(f.ut), shfl_next(f.H), shfl_next(f.c), shfl_next(f.q2),
+                shfl_next(f.i2c), shfl_next(f.g1c2)};
+  }
+
+  // normal velocity, pressure of a state in the frame of a face normal to D
+  template <int D>
+  __device__ __forceinline__ void prim(const R* q, R& un, R& p) const {
+    constexpr int n = 1 + D, t = 2 - D;
+    const R ir = frcp(q[0]);
+    un = q[n] * ir;
+    const R kin = q[n] * q[n] + (NDIM == 2 ? q[t] * q[t] : R(0));
+    p = g1 * (q[EI] - R(0.5) * kin * ir);
+  }
+
+  template <int D>
+  __device__ __forceinline__ void normal(const R* ql, const R* qr, const Cell& cl, const Cell& cr,
+                                         R (&W)[MW][M], R (&s)[MW], R (&am)[M], R (&ap)[M],
+                                         Face& f) const {
+    constexpr int n = 1 + D, t = 2 - D;
+    const R unl = D == 0 ? cl.u : cl.v, unr = D == 0 ? cr.u : cr.v;
+    const R rden = frcp(cl.sr + cr.sr);
+    f.un = (cl.sr * unl + cr.sr * unr) * rden;
+    if constexpr (NDIM == 2) {
+      const R utl = D == 0 ? cl.v : cl.u, utr = D == 0 ? cr.v : cr.u;
+      f.ut = (cl.sr * utl + cr.sr * utr) * rden;
+    } else {
+      f.ut = R(0);
+    }
+    f.H = (cl.sr * cl.H + cr.sr * cr.H) * rden;
+    f.q2 = f.un * f.un + f.ut * f.ut;
+    const R c2 = g1 * (f.H - R(0.5) * f.q2);
+    const R rs = frsq(c2);
+    f.c = c2 * rs;
+    f.i2c = R(0.5) * rs;
+    f.g1c2 = g1 * rs * rs;
+    R dq[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) dq[k] = qr[k] - ql[k];
+    const R dtn = NDIM == 2 ? dq[t] : R(0);
+    const R a2 = f.g1c2 * ((f.H - f.q2) * dq[0] + f.un * dq[n] + f.ut * dtn - dq[EI]);
+    const R a4 = (dq[n] + (f.c - f.un) * dq[0] - f.c * a2) * f.i2c;
+    const R a1 = dq[0] - a2 - a4;
+#pragma unroll
+    for (int p = 0; p < MW; ++p)
+#pragma unroll
+      for (int k = 0; k < M; ++k) W[p][k] = R(0);
+    W[0][0] = a1; W[0][n] = a1 * (f.un - f.c); W[0][EI] = a1 * (f.H - f.un * f.c);
+    W[1][0] = a2; W[1][n] = a2 * f.un; W[1][EI] = a2 * R(0.5) * f.q2;
+    W[ACR][0] = a4; W[ACR][n] = a4 * (f.un + f.c); W[ACR][EI] = a4 * (f.H + f.un * f.c);
+    s[0] = f.un - f.c;
+    s[1] = f.un;
+    s[ACR] = f.un + f.c;
+    if constexpr (NDIM == 2) {
+      const R a3 = dq[t] - f.ut * dq[0];
+      W[0][t] = a1 * f.ut;
+      W[1][t] = a2 * f.ut;
+      W[ACR][t] = a4 * f.ut;
+      W[2][t] = a3;
+      W[2][EI] = a3 * f.ut;
+      s[2] = f.un;
+    }
+    if constexpr (TRACER) {
+      W[M - 1][PHI] = dq[PHI];
+      s[M - 1] = f.un;
+    }
+    R coef[MW];
+#pragma unroll
+    for (int p = 0; p < MW; ++p) coef[p] = rmin(s[p], R(0));
+    if (efix) {
+      // Harten-Hyman: a transonic acoustic rarefaction (characteristic speed
+      // negative on its left, positive on its right) contributes
+      // lam_l (lam_r - s) / (lam_r - lam_l) W to A^-dQ.  The middle state's
+      // speed is formed only when a cheap exact test (u_m > c_m, i.e.
+      // m_n > 0 and m_n^2 > gamma p_m rho_m) says the wave is transonic.
+      {
+        const R lam_l = unl - cl.c;
+        R qm[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) qm[k] = ql[k] + W[0][k];
+        const R kin = qm[n] * qm[n] + (NDIM == 2 ? qm[t] * qm[t] : R(0));
+        const R prho = g1 * (qm[EI] * qm[0] - R(0.5) * kin);   // p_m rho_m
+        if (lam_l < R(0) && qm[0] > R(0) && prho > R(0) && qm[n] > R(0) &&
+            qm[n] * qm[n] > gamma * prho) {
+          R um, pm;
+          prim<D>(qm, um, pm);
+          const R lam_r = um - fsqrt(gamma * pm * frcp(qm[0]));
+          if (R(0) < lam_r) coef[0] = lam_l * (lam_r - s[0]) * frcp(lam_r - lam_l);
+        }
+      }
+      {
+        const R lam_r = unr + cr.c;
+        R qm[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) qm[k] = qr[k] - W[ACR][k];
+        const R kin = qm[n] * qm[n] + (NDIM == 2 ? qm[t] * qm[t] : R(0));
+        const R prho = g1 * (qm[EI] * qm[0] - R(0.5) * kin);
+        if (lam_r > R(0) && qm[0] > R(0) && prho > R(0) && qm[n] < R(0) &&
+            qm[n] * qm[n] > gamma * prho) {
+          R um, pm;
+          prim<D>(qm, um, pm);
+          const R lam_l = um + fsqrt(gamma * pm * frcp(qm[0]));
+          if (lam_l < R(0)) coef[ACR] = lam_l * (lam_r - s[ACR]) * frcp(lam_r - lam_l);
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      R a = R(0), sw = R(0);
+#pragma unroll
+      for (int p = 0; p < MW; ++p) {
+        if (!nz<D>(p, k)) continue;
+        a += coef[p] * W[p][k];
+        sw += s[p] * W[p][k];
+      }
+      am[k] = a;
+      ap[k] = sw - a;
+    }
+  }
+
+  // Split a fluctuation from a face normal to D in the transverse direction
+  // with the face's Roe averages: speeds v-c, v, v, v+c (and v for the
+  // tracer), v being the velocity along the transverse direction.
+  template <int D>
+  __device__ __forceinline__ void transverse(const Face& f, const Cell&, const Cell&, const Cell&,
+                                             const R* d, R* bm, R* bp) const {
+    if constexpr (NDIM == 2) {
+      constexpr int n = 1 + D, t = 2 - D;
+      const R b3 = d[n] - f.un * d[0];
+      const R b2 = f.g1c2 * ((f.H - f.q2) * d[0] + f.un * d[n] + f.ut * d[t] - d[EI]);
+      const R b4 = (d[t] + (f.c - f.ut) * d[0] - f.c * b2) * f.i2c;
+      const R b1 = d[0] - b2 - b4;
+      const R l1 = f.ut - f.c, l2 = f.ut, l4 = f.ut + f.c;
+      const R m1 = rmin(l1, R(0)) * b1, m2 = rmin(l2, R(0)) * b2, m3 = rmin(l2, R(0)) * b3,
+              m4 = rmin(l4, R(0)) * b4;
+      const R p1 = rmax(l1, R(0)) * b1, p2 = rmax(l2, R(0)) * b2, p3 = rmax(l2, R(0)) * b3,
+              p4 = rmax(l4, R(0)) * b4;
+      // eigenvectors (rho, across, along, E): (1, u, v-c, H - v c), (1, u, v, q2/2),
+      // (0, 1, 0, u), (1, u, v+c, H + v c)
+      const R hq = R(0.5) * f.q2;
+      bm[0] = m1 + m2 + m4;
+      bm[n] = (m1 + m2 + m4) * f.un + m3;
+      bm[t] = m1 * l1 + m2 * l2 + m4 * l4;
+      bm[EI] = m1 * (f.H - f.ut * f.c) + m2 * hq + m3 * f.un + m4 * (f.H + f.ut * f.c);
+      bp[0] = p1 + p2 + p4;
+      bp[n] = (p1 + p2 + p4) * f.un + p3;
+      bp[t] = p1 * l1 + p2 * l2 + p4 * l4;
+      bp[EI] = p1 * (f.H - f.ut * f.c) + p2 * hq + p3 * f.un + p4 * (f.H + f.ut * f.c);
+      if constexpr (TRACER) {
+        bm[PHI] = rmin(l2, R(0)) * d[PHI];
+        bp[PHI] = rmax(l2, R(0)) * d[PHI];
+      }
+    }
+  }
+
+  // Axisymmetric geometric source -(v/r)(rho, rho u, rho v, E + p) (tracer 0)
+  // over dt by Heun's method: the increment dt/2 (psi(q) + psi(q + dt psi(q))).
+  __device__ __forceinline__ void psi(const R* q, R ir, R* out) const {
+    const R irho = frcp(q[0]);
+    const R v = q[2] * irho;
+    const R p = g1 * (q[3] - R(0.5) * (q[1] * q[1] + q[2] * q[2]) * irho);
+    const R w = -v * ir;
+    out[0] = w * q[0];
+    out[1] = w * q[1];
+    out[2] = w * q[2];
+    out[3] = w * (q[3] + p);
+  }
+  __device__ __forceinline__ void source_increment(const R* q, R ir, R dt, R* inc) const {
+    R f0[4], f1[4], qs[4];
+    psi(q, ir, f0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) qs[k] = q[k] + dt * f0[k];
+    psi(qs, ir, f1);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) inc[k] = R(0.5) * dt * (f0[k] + f1[k]);
+  }
+
+  __device__ __forceinline__ double cell_speed(const R* q, const R*, double rdx, double rdy) const {
+    const double rho = q[0], u = (double)q[1] / rho;
+    const double v = NDIM == 2 ? (double)q[2] / rho : 0.0;
+    const double p = ((double)gamma - 1.0) * ((double)q[EI] - 0.5 * rho * (u * u + v * v));
+    const double c = sqrt((double)gamma * p / rho);
+    double s = (fabs(u) + c) * rdx;
+    if (NDIM == 2) s = fmax(s, (fabs(v) + c) * rdy);
+    return s;
+  }
+};
 
 // ===========================================================================
 // SharpClaw: numerical fluxes at an interface from reconstructed edge values.

@@ -139,6 +139,82 @@ def shock_bubble(nx=2048, ny=1024, mach=2.0, gamma=GAMMA, bubble_rho=0.1, center
     return spec, q
 
 
+def _bubble_fraction(x, y, dx, dy, center, radius, sub):
+    """Per-cell fraction inside a circle by sub x sub sub-cell midpoints."""
+    off = (np.arange(sub) + 0.5) / sub - 0.5
+    frac = np.zeros((len(y), len(x)))
+    X, Y = np.meshgrid(x, y)
+    near = (np.abs(X - center[0]) < radius + dx) & (np.abs(Y - center[1]) < radius + dy)
+    jj, ii = np.nonzero(near)
+    r2 = radius * radius
+    for a in off:
+        for b in off:
+            xs = x[ii] + a * dx
+            ys = y[jj] + b * dy
+            frac[jj, ii] += ((xs - center[0]) ** 2 + (ys - center[1]) ** 2 < r2)
+    return frac / (sub * sub)
+
+
+# ---------------------------------------------------------------------------
+# The paper's classic shock-bubble run (Section 7, eq. euler-rz): axisymmetric
+# Euler on [0,2] x [0,0.5] (x = axial z, y = radius r), a planar shock moving
+# in +z into still gas (rho = p = 1) holding a spherical bubble (rho = 0.1,
+# p = 1) centred on the axis; a tracer is 1 in the bubble.  The post-shock
+# state printed in the paper (p = 5, rho ~ 2.82, axial velocity ~ 1.61) is the
+# Mach-2.1044 shock, imposed at the left edge.  Reflecting axis (bottom),
+# outflow top and right.  Classic Clawpack: Roe solver, MC limiter, full
+# transverse corrections, maximum CFL 0.8.  Bubble centre (0.5, 0), radius
+# 0.2, shock at z = 0.2 (not given in the paper).
+# ---------------------------------------------------------------------------
+PAPER_MACH = 2.104417123237
+
+
+def shock_bubble_axisym(nx=1280, ny=320, mach=PAPER_MACH, gamma=GAMMA, bubble_rho=0.1,
+                        center=(0.5, 0.0), radius=0.2, shock_x=0.2, sub=16, tracer=1, **kw):
+    rho1, u1, p1, _ = rankine_hugoniot(mach, gamma)
+    post = list(euler_conserved(rho1, u1, 0.0, p1, gamma)) + ([0.0] if tracer else [])
+    spec = _base(2, (nx, ny), (0.0, 0.0), (2.0, 0.5), "euler_roe", problem_data=[gamma],
+                 tracer=tracer, source="axisymmetric", entropy_fix=1, limiter="mc", transverse=2,
+                 bc_lower=("dirichlet", "wall"), bc_upper=("extrap", "extrap"),
+                 bc_state={"x_lower": post}, cfl_desired=0.75, cfl_max=0.8, **kw)
+    x, y = centers(spec)
+    dx = 2.0 / nx
+    dy = 0.5 / ny
+    frac = _bubble_fraction(x, y, dx, dy, center, radius, sub)
+    X, _ = np.meshgrid(x, y)
+    m = 4 + (1 if tracer else 0)
+    q = np.zeros((m, ny, nx))
+    q[0] = 1.0 * (1.0 - frac) + bubble_rho * frac
+    q[3] = 1.0 / (gamma - 1.0)
+    if tracer:
+        q[4] = frac
+    behind = X < shock_x
+    for k in range(m):
+        q[k] = np.where(behind, post[k], q[k])
+    return spec, q
+
+
+# ---------------------------------------------------------------------------
+# The paper's Listing 1: a 2D Euler Riemann problem on [0,1]^2 with four
+# quadrant states, extrapolation boundaries, gamma = 1.4, to t = 0.3, classic
+# Clawpack with the 4-wave Roe solver.  The initial data follow the listing's
+# formulas as printed (its q[1], q[2] enter the energy as given).
+# ---------------------------------------------------------------------------
+def listing1_riemann(n=100, gamma=GAMMA, **kw):
+    spec = _base(2, (n, n), (0.0, 0.0), (1.0, 1.0), "euler_roe", problem_data=[gamma],
+                 limiter="mc", transverse=2, **kw)
+    x, y = centers(spec)
+    X, Y = np.meshgrid(x, y)
+    l, r = X < 0.5, X >= 0.5
+    b, t = Y < 0.5, Y >= 0.5
+    q = np.zeros((4, n, n))
+    q[0] = 2.0 * (l & t) + 1.0 * (l & b) + 1.0 * (r & t) + 3.0 * (r & b)
+    q[1] = 0.75 * t - 0.75 * b
+    q[2] = 0.5 * l - 0.5 * r
+    q[3] = 0.5 * q[0] * (q[1] ** 2 + q[2] ** 2) + 1.0 / (gamma - 1.0)
+    return spec, q
+
+
 # ---------------------------------------------------------------------------
 # 2D linear elasticity in a layered medium: 16 layers along x with interfaces
 # at seeded sorted uniform positions snapped to cell faces; per layer

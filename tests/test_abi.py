@@ -95,3 +95,16 @@ def test_sharpclaw_integrator_and_weno_order_options():
     # classic ignores both
     sw, _ = W.radial_dam_break(64)
     assert _bytes(dict(sw, time_integrator="ssp104", weno_order=7))[0] == _bytes(sw)[0]
+
+
+def test_euler_roe_tracer_and_source_options():
+    spec, q = W.shock_bubble_axisym(160, 40)
+    n, m = _bytes(spec)
+    assert m == 5 and n >= 2 * 5 * 160 * 40 * 8
+    assert _bytes(dict(spec, tracer=0))[1] == 4
+    # a tracer only exists for the Euler Roe solver; the source only in 2D classic Euler Roe
+    sw, _ = W.radial_dam_break(64)
+    assert _bytes(dict(sw, tracer=1))[0] == 0
+    assert _bytes(dict(sw, source="axisymmetric"))[0] == 0
+    assert _bytes(dict(spec, scheme="sharpclaw"))[0] == 0
+    assert _bytes(dict(spec, lower=(0.0, -0.5)))[0] == 0   # the radius must be >= 0

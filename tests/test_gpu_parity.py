@@ -43,6 +43,9 @@ def unit_groups(spec):
         return [[0], [1]] if nd == 1 else [[0], [1, 2]]
     if r == "euler_hlle":
         return [[0], [1], [2]] if nd == 1 else [[0], [1, 2], [3]]
+    if r == "euler_roe":
+        g = [[0], [1], [2]] if nd == 1 else [[0], [1, 2], [3]]
+        return g + ([[len(g) + (0 if nd == 1 else 1)]] if spec.get("tracer") else [])
     if r == "elastic_vc":
         return [[0, 1, 2], [3, 4]]
     return [[0]]
@@ -413,6 +416,100 @@ def test_fp32_kahan_sharpclaw_variant_l1(integ, order):
     say("L1 relative errors", err, "on the unit-group scale", errg)
     assert max(errg) <= 1e-4
     assert max(err[0], err[1], err[3]) <= 1e-5
+
+
+# --------------------------------------------------------------------------
+# Classic Euler: Roe solver + transverse split (+ tracer, + axisymmetric
+# source as a fractional step)
+# --------------------------------------------------------------------------
+def test_listing1_riemann_problem_classic_euler():
+    say("case: Listing 1 2D Euler Riemann problem 100x100, classic Roe, to t=0.3 on the device")
+    spec, q = W.listing1_riemann(100)
+    qo, dts, info = oracle_run(spec, q, 0.3)
+    s = solver(spec, q)
+    st = s.advance(0.3, steps_per_graph=8)
+    assert st["accepted"] == info["accepted"] and st["rejected"] == info["rejected"]
+    assert fp64_err(s.get_state(), qo, spec) <= 1e-12
+
+
+@pytest.mark.parametrize("tracer,efix", [(0, 0), (1, 1)])
+def test_euler_roe_ragged_periodic_replay(tracer, efix):
+    say("case: smooth periodic Euler Roe 77x61, tracer", tracer, "efix", efix, "15 steps")
+    spec, q = W.random_smooth_euler(77, seed=7)
+    q = q[:, :61, :].copy()
+    if tracer:
+        q = np.concatenate([q, np.random.default_rng(3).uniform(0, 1, (1, 61, 77))])
+    spec = dict(spec, scheme="classic", riemann="euler_roe", num_cells=(77, 61),
+                upper=(1.0, 61 / 77), limiter="mc", transverse=2, tracer=tracer, entropy_fix=efix,
+                cfl_desired=0.8, cfl_max=0.9)
+    qo, info = oracle.advance(spec, q, 1.0, max_steps=15)
+    g = replay(spec, q, info["dts"][info["acc"] == 1], seg_rows=9)
+    assert fp64_err(g, qo, spec) <= 1e-12
+
+
+@pytest.mark.parametrize("trans,lim", [(0, "none"), (1, "minmod"), (2, "mc")])
+def test_axisym_shock_bubble_replay(trans, lim):
+    say("case: axisymmetric shock-bubble 160x40 (tracer, source), transverse", trans, lim)
+    spec, q = W.shock_bubble_axisym(160, 40)
+    spec = dict(spec, transverse=trans, limiter=lim)
+    qo, info = oracle.advance(spec, q, 1.0, max_steps=25)
+    g = replay(spec, q, info["dts"][info["acc"] == 1])
+    assert fp64_err(g, qo, spec) <= 1e-12
+
+
+def test_euler_roe_1d_sod_device_controller():
+    say("case: 1D Euler Roe Sod 500 cells (one-workgroup run kernel), entropy fix")
+    n = 500
+    spec = dict(ndim=1, num_cells=(n,), lower=(-0.5,), upper=(0.5,), scheme="classic",
+                riemann="euler_roe", problem_data=[1.4], entropy_fix=1, limiter="mc",
+                bc_lower=("extrap",), bc_upper=("extrap",), cfl_desired=0.8, cfl_max=0.9)
+    x = -0.5 + (np.arange(n) + 0.5) / n
+    q = np.zeros((3, 1, n))
+    q[0, 0] = np.where(x < 0, 1.0, 0.125)
+    q[1, 0] = np.where(x < 0, 0.75, 0.0)
+    q[2, 0] = np.where(x < 0, 1.0 / 0.4 + 0.5 * 0.75 ** 2, 0.1 / 0.4)
+    qo, dts, info = oracle_run(spec, q, 0.2)
+    s = solver(spec, q)
+    st = s.advance(0.2)
+    assert st["accepted"] == info["accepted"]
+    assert fp64_err(s.get_state(), qo, spec) <= 1e-12
+    # and the strip kernel (replayed dt)
+    g = replay(spec, q, dts)
+    assert fp64_err(g, qo, spec) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_kahan"])
+def test_euler_roe_tiling_does_not_change_results(prec):
+    say("case: axisymmetric shock-bubble seg_rows 4/16/100 bitwise equal", prec)
+    spec, q = W.shock_bubble_axisym(150, 100)
+    spec = dict(spec, precision=prec)
+    outs = [replay(spec, q, [4e-4] * 6, seg_rows=sr) for sr in (4, 16, 100)]
+    np.testing.assert_array_equal(outs[0], outs[1])
+    np.testing.assert_array_equal(outs[0], outs[2])
+
+
+def test_full_size_axisym_shock_bubble_one_step():
+    say("case: axisymmetric shock-bubble 1280x320, one-step parity after 40 GPU steps")
+    spec, q = W.shock_bubble_axisym(1280, 320)
+    s = solver(spec, q)
+    s.autotune(reps=1)
+    s.advance(1.0, max_steps=40)
+    q1 = s.get_state()
+    dt = s.clock()["dt_next"]
+    s.step(dt)
+    o, _ = oracle.step(spec, q1, dt)
+    assert fp64_err(s.get_state(), o, spec) <= 1e-12
+
+
+def test_fp32_kahan_axisym_shock_bubble_l1():
+    say("case: FP32+Kahan axisymmetric shock-bubble 320x80, 80 steps (replayed dt)")
+    spec, q = W.shock_bubble_axisym(320, 80)
+    qo, info = oracle.advance(spec, q, 1.0, max_steps=80)
+    g = replay(dict(spec, precision="fp32_kahan"), q, info["dts"][info["acc"] == 1])
+    err = l1_rel(g, qo)
+    errg = l1_rel_groups(g, qo, spec)
+    say("L1 relative errors", err, "on the unit-group scale", errg)
+    assert max(errg) <= 1e-5 and max(err[0], err[1], err[3], err[4]) <= 1e-5
 
 
 # --------------------------------------------------------------------------
