@@ -108,7 +108,13 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 #   SSPRK(10,4) stage bytes, FP64, averaged over the ten stages: eight plain
 #   stages 64 B (S in, y out), stage 5 128 B (S, Q in; two registers out),
 #   stage 10 96 B (S, S3 in; Q out) -> 73.6 B per cell-stage.
-FLOPS_PER_CELL = {"sw": 554.0, "euler_stage": 1040.0, "euler_stage_weno7": 1840.0}
+#   euler_roe  2D Euler, classic, Roe + entropy-fix test, MC, full transverse,
+#            tracer, axisymmetric source: per cell-step 1160 = 2 faces x (Roe
+#            solve 156 + limiter for 5 waves 90 + correction 60 + transverse
+#            split and accumulation 214) + cell primitives 16 + update 50 +
+#            source (Heun) 48 + Courant maxima 10; HBM 80 B (5 FP64 in + out)
+FLOPS_PER_CELL = {"sw": 554.0, "euler_stage": 1040.0, "euler_stage_weno7": 1840.0,
+                  "euler_roe": 1160.0}
 
 
 def roofline(bound, cells, gpu_ms, launches, kernel_name, bytes_per_launch, flops_per_launch=None,
@@ -355,6 +361,14 @@ def main():
                                       FLOPS_PER_CELL["euler_stage_weno7"]) * r["cells"], "f64")
             r["cfl"] = [2.45, 2.5]
             extras[f"euler_shock_bubble_2048x1024_fp64_ssp104_weno{order}"] = r
+
+        log("classic axisymmetric shock-bubble 1280x320 (the paper's run), Roe + tracer, FP64")
+        ax_spec, ax_q = W.shock_bubble_axisym(1280, 320)
+        r = timed_run(ax_spec, ax_q, None, 100, 10, 1.0)
+        r["roofline"] = roofline("alu", r["cells"], r["gpu_ms"], r["steps"] + r["rejected"],
+                                 "k_classic2d<double,EulerRoe+tracer>", 80 * r["cells"],
+                                 FLOPS_PER_CELL["euler_roe"] * r["cells"], "f64")
+        extras["euler_shock_bubble_axisym_1280x320_classic_fp64"] = r
 
         log("layered elasticity 2048^2")
         el_spec, el_q, el_aux = W.layered_elastic(2048)
