@@ -37,6 +37,7 @@ _lib = None
 SCHEMES = {"classic": 1, "sharpclaw": 2}
 SOLVERS = {"advection": 1, "sw_roe": 2, "euler_hlle": 3, "elastic_vc": 4, "euler_roe": 5}
 SOURCES = {"none": 0, "axisymmetric": 1}
+SPLITS = {"none": 0, "godunov": 1, "strang": 2}
 LIMITERS = {"none": 0, "minmod": 1, "mc": 2}
 BCS = {"extrap": 1, "periodic": 2, "wall": 3, "dirichlet": 4}
 SIDES = ("x_lower", "x_upper", "y_lower", "y_upper")
@@ -51,6 +52,7 @@ class OCfg(C.Structure):
         ("transverse", C.c_int), ("efix", C.c_int), ("bc", C.c_int * 4),
         ("bcstate", (C.c_double * 8) * 4), ("weno_eps", C.c_double), ("pd", C.c_double * 8),
         ("integrator", C.c_int), ("weno_order", C.c_int), ("tracer", C.c_int), ("source", C.c_int),
+        ("split", C.c_int),
     ]
 
 
@@ -149,6 +151,7 @@ def make_cfg(spec: dict) -> OCfg:
     c.weno_order = int(spec.get("weno_order", 5))
     c.tracer = int(spec.get("tracer", 0))
     c.source = SOURCES[spec.get("source", "none")]
+    c.split = SPLITS[spec.get("dimensional_split", "none")]
     for k, v in enumerate(spec.get("problem_data", [])):
         c.pd[k] = float(v)
     return c

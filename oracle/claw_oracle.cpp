@@ -64,6 +64,7 @@ struct OCfg {
   int weno_order;      // SharpClaw: 0/5 WENO5, or 2r-1 for r = 3..9
   int tracer;          // Euler Roe: 1 = one passive tracer advected with the flow
   int source;          // classic 2D Euler Roe: 1 = axisymmetric about y = 0 (r = y)
+  int split;           // classic 2D: 0 unsplit, 1 Godunov (x then y), 2 Strang (x/2, y, x/2)
 };
 
 }  // extern "C"
@@ -793,6 +794,74 @@ double classic_2d(const OCfg& c, const double* qin, const double* auxin, double*
 }
 
 // ---------------------------------------------------------------------------
+// Dimensionally split classic step (the paper names both dimensionally-split
+// and fully multidimensional algorithms, Section 2.1): each sweep applies the
+// 1D wave-propagation update (normal solves, limited correction fluxes, no
+// transverse terms) along x to every row, or along y to every column, of the
+// 2D state.  Godunov splitting: x sweep over dt, then y sweep over dt.
+// Strang splitting: x over dt/2, y over dt, x over dt/2.  The Courant number
+// is the step's dt times the largest speed / spacing met in any sweep.
+// ---------------------------------------------------------------------------
+double classic_sweep(const OCfg& c, int d, const double* qin, const double* auxin, double* qout,
+                     double dt) {
+  const int m = num_eqn(c), mw = num_waves(c), na = num_aux(c);
+  const int nx = c.nx, ny = c.ny;
+  const double h = d == 0 ? dx_of(c) : dy_of(c), dth = dt / h;
+  Field Q, A;
+  load_field(c, Q, qin, m, 2, false);
+  load_field(c, A, auxin, na, 2, true);
+  const int n = d == 0 ? nx : ny, lines = d == 0 ? ny : nx;
+  double smax = 0.0;
+#pragma omp parallel for schedule(static) reduction(max : smax)
+  for (int L = 0; L < lines; ++L) {
+    auto at = [&](int k, int s) { return d == 0 ? Q.at(k, L, s) : Q.at(k, s, L); };
+    auto aux_at = [&](int k, int s) { return d == 0 ? A.at(k, L, s) : A.at(k, s, L); };
+    // faces f = -1 .. n+1 along the line; face f lies between cells f-1 and f
+    std::vector<FaceSol> F(n + 3);
+    for (int f = -1; f <= n + 1; ++f) {
+      double ql[5], qr[5], al[3] = {0, 0, 0}, ar[3] = {0, 0, 0};
+      for (int k = 0; k < m; ++k) { ql[k] = at(k, f - 1); qr[k] = at(k, f); }
+      for (int k = 0; k < na; ++k) { al[k] = aux_at(k, f - 1); ar[k] = aux_at(k, f); }
+      rp_normal(c, d, ql, qr, al, ar, F[f + 1]);
+    }
+    std::vector<double> Ft((size_t)(n + 1) * m, 0.0);
+    for (int f = 0; f <= n; ++f) {
+      const FaceSol& me = F[f + 1];
+      double Wl[5][5];
+      limit_waves(c, m, mw, F[f], me, F[f + 2], Wl);
+      for (int p = 0; p < mw; ++p) {
+        const double as = std::fabs(me.s[p]);
+        smax = std::max(smax, as / h);
+        for (int k = 0; k < m; ++k) Ft[(size_t)f * m + k] += 0.5 * as * (1.0 - dth * as) * Wl[p][k];
+      }
+    }
+    for (int s = 0; s < n; ++s)
+      for (int k = 0; k < m; ++k) {
+        const size_t idx = d == 0 ? ((size_t)k * ny + L) * nx + s : ((size_t)k * ny + s) * nx + L;
+        qout[idx] = at(k, s) - dth * (F[s + 1].apdq[k] + F[s + 2].amdq[k]) -
+                    dth * (Ft[(size_t)(s + 1) * m + k] - Ft[(size_t)s * m + k]);
+      }
+  }
+  return smax;
+}
+
+double classic_2d_split(const OCfg& c, const double* qin, const double* auxin, double* qout,
+                        double dt) {
+  const size_t N = (size_t)num_eqn(c) * c.nx * c.ny;
+  std::vector<double> a(N), b(N);
+  double s = 0.0;
+  if (c.split == 2) {
+    s = std::max(s, classic_sweep(c, 0, qin, auxin, a.data(), 0.5 * dt));
+    s = std::max(s, classic_sweep(c, 1, a.data(), auxin, b.data(), dt));
+    s = std::max(s, classic_sweep(c, 0, b.data(), auxin, qout, 0.5 * dt));
+  } else {
+    s = std::max(s, classic_sweep(c, 0, qin, auxin, a.data(), dt));
+    s = std::max(s, classic_sweep(c, 1, a.data(), auxin, qout, dt));
+  }
+  return s;
+}
+
+// ---------------------------------------------------------------------------
 // SharpClaw (Section 2, method of lines; Section 2.1: WENO5 in space, SSP
 // Runge-Kutta in time, normal Riemann problems only in multi-D).
 // ---------------------------------------------------------------------------
@@ -1244,7 +1313,7 @@ bool has_source(const OCfg& c) { return c.source == 1 && c.solver == S_EULER_ROE
 double one_step(const OCfg& c, const double* qin, const double* aux, double* qout, double dt) {
   if (c.scheme == 2) return sharpclaw_step(c, qin, qout, dt);
   if (c.ndim == 1) return classic_1d(c, qin, qout, dt);
-  const double s = classic_2d(c, qin, aux, qout, dt);
+  const double s = c.split ? classic_2d_split(c, qin, aux, qout, dt) : classic_2d(c, qin, aux, qout, dt);
   if (has_source(c)) source_step(c, qout, dt);
   return s;
 }

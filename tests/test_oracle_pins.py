@@ -1021,3 +1021,110 @@ def test_axisymmetric_source_step_second_order_and_exact_cases():
     q0[2] = 0.0
     np.testing.assert_array_equal(oracle.source_step(spec, q0, 0.01), q0)
     np.testing.assert_array_equal(oracle.source_step(spec, q, 0.01)[4], q[4])
+
+
+# --------------------------------------------------------------------------
+# P22: dimensionally split classic steps (Godunov x-then-y, Strang x/2 y x/2)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("lim", ["none", "mc"])
+@pytest.mark.parametrize("sgn", [(1, 1), (1, -1), (-1, 1), (-1, -1)])
+def test_split_advection_courant_one_is_an_exact_shift(lim, sgn):
+    """Each 1D sweep at Courant number 1 moves the data exactly one cell
+    (the correction flux vanishes), whatever the limiter.  Non-square grid
+    with dx != dy, so swapped axes or spacings fail."""
+    nx, ny = 16, 12
+    dt = 1.0 / 16
+    rng = np.random.default_rng(11)
+    q0 = rng.standard_normal((1, ny, nx))
+    # Godunov: u dt/dx = 1 and v dt/dy = 1
+    u, v = sgn[0] * 1.0, sgn[1] * (1.0 / 12) / dt
+    s = spec2d("advection", (nx, ny), problem_data=[u, v], limiter=lim,
+               dimensional_split="godunov")
+    q, sp = oracle.step(s, q0, dt)
+    assert sp * dt == pytest.approx(1.0)
+    np.testing.assert_allclose(q, np.roll(q0, (sgn[1], sgn[0]), axis=(1, 2)), rtol=0, atol=1e-13)
+    # Strang: the x half-steps run at Courant 1 when u dt/dx = 2
+    s = dict(s, problem_data=[2.0 * u, v], dimensional_split="strang")
+    q, sp = oracle.step(s, q0, dt)
+    assert sp * dt == pytest.approx(2.0)
+    np.testing.assert_allclose(q, np.roll(q0, (sgn[1], 2 * sgn[0]), axis=(1, 2)), rtol=0,
+                               atol=1e-13)
+
+
+@pytest.mark.parametrize("split", ["godunov", "strang"])
+@pytest.mark.parametrize("axis", [0, 1])
+def test_split_one_dimensional_data_reduces_to_1d_steps(split, axis):
+    """Data varying along one axis only: the sweep across it sees no jumps, so
+    the split step is the 1D step along the other axis (two half steps for
+    the x sweeps of Strang splitting when the data vary in x)."""
+    n, w = 80, 5
+    spec1, q1 = W.dam_break_1d(n)
+    shape = (w, n) if axis == 0 else (n, w)
+    s2 = dict(ndim=2, num_cells=(n, w) if axis == 0 else (w, n),
+              lower=(-5.0, 0.0) if axis == 0 else (0.0, -5.0),
+              upper=(5.0, 1.0) if axis == 0 else (1.0, 5.0), scheme="classic", riemann="sw_roe",
+              limiter="mc", transverse=2, entropy_fix=1, problem_data=[1.0],
+              dimensional_split=split, bc_lower=("extrap", "wall"), bc_upper=("extrap", "wall"))
+    if axis == 1:
+        s2.update(bc_lower=("wall", "extrap"), bc_upper=("wall", "extrap"))
+    q2 = np.zeros((3,) + shape)
+    q2[0] = q1[0, 0][None, :] if axis == 0 else q1[0, 0][:, None]
+    dt = 0.9 * (10.0 / n) / 2.0
+    halves = split == "strang" and axis == 0
+    for _ in range(20):
+        if halves:
+            q1, _ = oracle.step(spec1, q1, 0.5 * dt)
+            q1, _ = oracle.step(spec1, q1, 0.5 * dt)
+        else:
+            q1, _ = oracle.step(spec1, q1, dt)
+        q2, _ = oracle.step(s2, q2, dt)
+    mom = 1 if axis == 0 else 2
+    for r in range(w):
+        row_h = q2[0, r, :] if axis == 0 else q2[0, :, r]
+        row_m = q2[mom, r, :] if axis == 0 else q2[mom, :, r]
+        np.testing.assert_allclose(row_h, q1[0, 0], rtol=0, atol=1e-13)
+        np.testing.assert_allclose(row_m, q1[1, 0], rtol=0, atol=1e-13)
+    np.testing.assert_array_equal(q2[3 - mom], 0.0)
+
+
+@pytest.mark.parametrize("split", ["godunov", "strang"])
+def test_split_conservation_sw_periodic(split):
+    spec, q = W.random_smooth_sw(40, seed=5)
+    spec = dict(spec, dimensional_split=split)
+    t0 = oracle.totals(spec, q)
+    qf, info = oracle.advance(spec, q, 0.15)
+    assert info["accepted"] >= 8
+    np.testing.assert_allclose(oracle.totals(spec, qf), t0, rtol=0, atol=1e-12)
+
+
+def _split_sw_run(n, split, t_end=0.08):
+    spec, _ = W.random_smooth_sw(n, seed=7, amplitude=0.1)
+    _, q = W.random_smooth_sw(n, seed=7, amplitude=0.1)
+    spec = dict(spec, dimensional_split=split, limiter="none")
+    nsteps = int(round(t_end / (0.4 / n)))
+    dt = t_end / nsteps
+    for _ in range(nsteps):
+        q, _ = oracle.step(spec, q, dt)
+    return q
+
+
+def _restrict(q):
+    return 0.25 * (q[:, 0::2, 0::2] + q[:, 1::2, 0::2] + q[:, 0::2, 1::2] + q[:, 1::2, 1::2])
+
+
+def test_split_strang_second_order_self_convergence():
+    """Strang splitting of second-order 1D sweeps is second order on smooth
+    nonlinear data (self-convergence of the unlimited method, dt/dx fixed)."""
+    qs = {n: _split_sw_run(n, "strang") for n in (32, 64, 128, 256)}
+    d = [np.sum(np.abs(qs[n] - _restrict(qs[2 * n]))) / n**2 for n in (32, 64, 128)]
+    rates = [math.log2(d[i] / d[i + 1]) for i in range(2)]
+    assert min(rates) > 1.8, rates
+
+
+def test_split_godunov_first_order_splitting_error():
+    """Godunov (x then y) splitting of the same sweeps: the splitting error is
+    first order, so the self-convergence rate falls towards 1."""
+    qs = {n: _split_sw_run(n, "godunov") for n in (32, 64, 128, 256)}
+    d = [np.sum(np.abs(qs[n] - _restrict(qs[2 * n]))) / n**2 for n in (32, 64, 128)]
+    rate = math.log2(d[1] / d[2])
+    assert 0.8 < rate < 1.5, rate
