@@ -52,7 +52,7 @@ class OCfg(C.Structure):
         ("transverse", C.c_int), ("efix", C.c_int), ("bc", C.c_int * 4),
         ("bcstate", (C.c_double * 8) * 4), ("weno_eps", C.c_double), ("pd", C.c_double * 8),
         ("integrator", C.c_int), ("weno_order", C.c_int), ("tracer", C.c_int), ("source", C.c_int),
-        ("split", C.c_int),
+        ("split", C.c_int), ("cfl_max", C.c_double),
     ]
 
 
@@ -152,6 +152,7 @@ def make_cfg(spec: dict) -> OCfg:
     c.tracer = int(spec.get("tracer", 0))
     c.source = SOURCES[spec.get("source", "none")]
     c.split = SPLITS[spec.get("dimensional_split", "none")]
+    c.cfl_max = float(spec.get("cfl_max", 1.0))
     for k, v in enumerate(spec.get("problem_data", [])):
         c.pd[k] = float(v)
     return c

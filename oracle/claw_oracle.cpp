@@ -65,6 +65,7 @@ struct OCfg {
   int tracer;          // Euler Roe: 1 = one passive tracer advected with the flow
   int source;          // classic 2D Euler Roe: 1 = axisymmetric about y = 0 (r = y)
   int split;           // classic 2D: 0 unsplit, 1 Godunov (x then y), 2 Strang (x/2, y, x/2)
+  double cfl_max;      // split steps: a sweep above it ends the step's Courant reading
 };
 
 }  // extern "C"
@@ -799,8 +800,14 @@ double classic_2d(const OCfg& c, const double* qin, const double* auxin, double*
 // 1D wave-propagation update (normal solves, limited correction fluxes, no
 // transverse terms) along x to every row, or along y to every column, of the
 // 2D state.  Godunov splitting: x sweep over dt, then y sweep over dt.
-// Strang splitting: x over dt/2, y over dt, x over dt/2.  The Courant number
-// is the step's dt times the largest speed / spacing met in any sweep.
+// Strang splitting: x over dt/2, y over dt, x over dt/2.
+// Courant number (the paper is silent on split steps): the step's dt times
+// the running maximum of the sweeps' largest speed / spacing, taken in sweep
+// order and stopped at the first sweep whose own value (step dt times its
+// speed) exceeds cfl_max or is not finite: that sweep rejects the step (or
+// flags it non-physical), and the sweeps after it, which act on an unstable
+// intermediate, do not count.  A sweep's speed is NaN if any of its faces'
+// is.
 // ---------------------------------------------------------------------------
 double classic_sweep(const OCfg& c, int d, const double* qin, const double* auxin, double* qout,
                      double dt) {
@@ -812,7 +819,8 @@ double classic_sweep(const OCfg& c, int d, const double* qin, const double* auxi
   load_field(c, A, auxin, na, 2, true);
   const int n = d == 0 ? nx : ny, lines = d == 0 ? ny : nx;
   double smax = 0.0;
-#pragma omp parallel for schedule(static) reduction(max : smax)
+  int nan_seen = 0;
+#pragma omp parallel for schedule(static) reduction(max : smax) reduction(| : nan_seen)
   for (int L = 0; L < lines; ++L) {
     auto at = [&](int k, int s) { return d == 0 ? Q.at(k, L, s) : Q.at(k, s, L); };
     auto aux_at = [&](int k, int s) { return d == 0 ? A.at(k, L, s) : A.at(k, s, L); };
@@ -831,7 +839,8 @@ double classic_sweep(const OCfg& c, int d, const double* qin, const double* auxi
       limit_waves(c, m, mw, F[f], me, F[f + 2], Wl);
       for (int p = 0; p < mw; ++p) {
         const double as = std::fabs(me.s[p]);
-        smax = std::max(smax, as / h);
+        if (std::isnan(as)) nan_seen = 1;
+        else smax = std::max(smax, as / h);
         for (int k = 0; k < m; ++k) Ft[(size_t)f * m + k] += 0.5 * as * (1.0 - dth * as) * Wl[p][k];
       }
     }
@@ -842,7 +851,7 @@ double classic_sweep(const OCfg& c, int d, const double* qin, const double* auxi
                     dth * (Ft[(size_t)(s + 1) * m + k] - Ft[(size_t)s * m + k]);
       }
   }
-  return smax;
+  return nan_seen ? std::numeric_limits<double>::quiet_NaN() : smax;
 }
 
 double classic_2d_split(const OCfg& c, const double* qin, const double* auxin, double* qout,
@@ -850,13 +859,19 @@ double classic_2d_split(const OCfg& c, const double* qin, const double* auxin, d
   const size_t N = (size_t)num_eqn(c) * c.nx * c.ny;
   std::vector<double> a(N), b(N);
   double s = 0.0;
+  bool open = true;   // no sweep has ended the Courant reading yet
+  auto fold = [&](double sk) {
+    if (!open) return;
+    s = std::isnan(sk) ? sk : std::max(s, sk);
+    if (!(dt * sk <= c.cfl_max)) open = false;
+  };
   if (c.split == 2) {
-    s = std::max(s, classic_sweep(c, 0, qin, auxin, a.data(), 0.5 * dt));
-    s = std::max(s, classic_sweep(c, 1, a.data(), auxin, b.data(), dt));
-    s = std::max(s, classic_sweep(c, 0, b.data(), auxin, qout, 0.5 * dt));
+    fold(classic_sweep(c, 0, qin, auxin, a.data(), 0.5 * dt));
+    fold(classic_sweep(c, 1, a.data(), auxin, b.data(), dt));
+    fold(classic_sweep(c, 0, b.data(), auxin, qout, 0.5 * dt));
   } else {
-    s = std::max(s, classic_sweep(c, 0, qin, auxin, a.data(), dt));
-    s = std::max(s, classic_sweep(c, 1, a.data(), auxin, qout, dt));
+    fold(classic_sweep(c, 0, qin, auxin, a.data(), dt));
+    fold(classic_sweep(c, 1, a.data(), auxin, qout, dt));
   }
   return s;
 }

@@ -1128,3 +1128,26 @@ def test_split_godunov_first_order_splitting_error():
     d = [np.sum(np.abs(qs[n] - _restrict(qs[2 * n]))) / n**2 for n in (32, 64, 128)]
     rate = math.log2(d[1] / d[2])
     assert 0.8 < rate < 1.5, rate
+
+
+def test_split_courant_reading_stops_at_the_first_unstable_sweep():
+    """A step far above the stability limit: the first sweep already rejects
+    it, so its Courant number is dt times the largest x-face speed of Q^n
+    (later sweeps act on a blown-up intermediate and do not count); a NaN in
+    the state makes the first sweep's speed, and so the step's, NaN."""
+    spec, q = W.radial_dam_break(20, ny=18)
+    spec = dict(spec, dimensional_split="strang")
+    dx = 5.0 / 20
+    smax = 0.0
+    for j in range(18):
+        for f in range(21):
+            ql, qr = q[:, j, max(f - 1, 0)], q[:, j, min(f, 19)]
+            _, s, _, _ = oracle.riemann(spec, 0, ql, qr)
+            smax = max(smax, float(np.max(np.abs(s))))
+    _, sp = oracle.step(spec, q, 5.0)
+    assert np.isfinite(sp) and 5.0 * sp > 1.0
+    assert sp == pytest.approx(smax / dx, rel=1e-14)
+    qn = q.copy()
+    qn[0, 7, 3] = np.nan
+    _, sp = oracle.step(spec, qn, 1e-3)
+    assert np.isnan(sp)
