@@ -100,6 +100,13 @@ enum claw_integrator {
   CLAW_SSP33 = 1,   /* Shu-Osher SSPRK(3,3): 3 stages (launches), two stage arrays */
   CLAW_SSP104 = 2   /* SSPRK(10,4): 10 stages, SSP coefficient 6, three stage arrays */
 };
+enum claw_split {
+  CLAW_SPLIT_NONE = 0,     /* unsplit 2D step (transverse corrections per `transverse`) */
+  CLAW_SPLIT_GODUNOV = 1,  /* classic 2D, dimensionally split (Section 2.1): a 1D wave-propagation
+                              sweep along x over dt on every row, then one along y over dt on
+                              every column; `transverse` is not used */
+  CLAW_SPLIT_STRANG = 2    /* as GODUNOV, but x over dt/2, y over dt, x over dt/2 */
+};
 enum claw_precision {
   CLAW_FP64 = 1,       /* all arithmetic in float64 */
   CLAW_FP32_KAHAN = 2  /* reconstruction, Riemann and limiter arithmetic in float32; the state is
@@ -134,6 +141,9 @@ typedef struct claw_config {
   int tracer;            /* CLAW_RP_EULER_ROE: 1 adds a passive tracer as the last component,
                             advected by the flow (q_t + u phi_x + v phi_y = 0); else 0 */
   int source;            /* claw_source (0 = none) */
+  int dimensional_split; /* classic 2D: claw_split (0 = unsplit).  The Courant number of a split
+                            step is dt times the largest |speed| / spacing met in any sweep.  Not
+                            allowed in 1D, with SharpClaw, or for a batch member (CLAW_E_INVAL) */
 } claw_config;
 
 /* Clock and counters of a handle; also the checkpoint record of the

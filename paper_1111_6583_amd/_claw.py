@@ -16,6 +16,7 @@ ERRORS = {-1: "CLAW_E_INVAL", -2: "CLAW_E_NOMEM", -3: "CLAW_E_DEVICE", -4: "CLAW
 SCHEMES = {"classic": 1, "sharpclaw": 2}
 SOLVERS = {"advection": 1, "sw_roe": 2, "euler_hlle": 3, "elastic_vc": 4, "euler_roe": 5}
 SOURCES = {"none": 0, "axisymmetric": 1}
+SPLITS = {"none": 0, "godunov": 1, "strang": 2}
 LIMITERS = {"none": 0, "minmod": 1, "mc": 2}
 BCS = {"extrap": 1, "periodic": 2, "wall": 3, "dirichlet": 4}
 PRECISIONS = {"fp64": 1, "fp32_kahan": 2}
@@ -32,7 +33,7 @@ class ClawConfig(C.Structure):
         ("cfl_desired", C.c_double), ("cfl_max", C.c_double), ("dt_initial", C.c_double),
         ("dt_max", C.c_double), ("weno_eps", C.c_double), ("precision", C.c_int),
         ("problem_data", C.c_double * 8), ("time_integrator", C.c_int), ("weno_order", C.c_int),
-        ("tracer", C.c_int), ("source", C.c_int),
+        ("tracer", C.c_int), ("source", C.c_int), ("dimensional_split", C.c_int),
     ]
 
 
@@ -172,6 +173,7 @@ def make_config(spec: dict) -> ClawConfig:
     c.weno_order = int(spec.get("weno_order", 5))
     c.tracer = int(spec.get("tracer", 0))
     c.source = SOURCES[spec.get("source", "none")]
+    c.dimensional_split = SPLITS[spec.get("dimensional_split", "none")]
     for k, v in enumerate(spec.get("problem_data", [])):
         c.problem_data[k] = float(v)
     return c

@@ -30,6 +30,8 @@ size_t classic1d_run_smem(int m, int nx, int fp32);
 hipError_t launch_sharp_stage(int ndim, int riemann, int fp32, int weno_r, int kind, int nblocks,
                               hipStream_t st, const GridDesc* d_grids, int mode, double dt,
                               const StageArgs& sa);
+hipError_t launch_sweep(int dir, int riemann, int fp32, int lim, hipStream_t st,
+                        const GridDesc* d_grid, int mode, double dt, int src, const SweepArgs& sa);
 hipError_t launch_load_state(int fp32, void* q, void* c, const double* in, size_t n,
                              hipStream_t st);
 hipError_t launch_store_state(int fp32, double* out, const void* q, const void* c, size_t n,
@@ -101,12 +103,16 @@ int validate(const claw_config* c) {
     if (c->riemann < 1 || c->riemann > 5) return CLAW_E_INVAL;
     if (c->limiter < CLAW_LIM_NONE || c->limiter > CLAW_LIM_MC) return CLAW_E_INVAL;
     if (c->transverse < 0 || c->transverse > 2) return CLAW_E_INVAL;
+    if (c->dimensional_split < CLAW_SPLIT_NONE || c->dimensional_split > CLAW_SPLIT_STRANG)
+      return CLAW_E_INVAL;
+    if (c->dimensional_split != CLAW_SPLIT_NONE && c->ndim != 2) return CLAW_E_INVAL;
   } else if (c->scheme == CLAW_SHARPCLAW) {
     if (c->riemann != CLAW_RP_ADVECTION && c->riemann != CLAW_RP_EULER_HLLE) return CLAW_E_INVAL;
     if (c->time_integrator != 0 && c->time_integrator != CLAW_SSP33 &&
         c->time_integrator != CLAW_SSP104)
       return CLAW_E_INVAL;
     if (c->weno_order != 0 && c->weno_order != 5 && c->weno_order != 7) return CLAW_E_INVAL;
+    if (c->dimensional_split != CLAW_SPLIT_NONE) return CLAW_E_INVAL;
   } else {
     return CLAW_E_INVAL;
   }
@@ -114,12 +120,17 @@ int validate(const claw_config* c) {
   return CLAW_OK;
 }
 
-// Process-wide tiling cache: (scheme, riemann, precision, WENO order, nx, ny) -> seg_rows.
+// Process-wide tiling cache: (4 scheme + split mode, riemann, precision, WENO order, nx, ny)
+// -> seg_rows.
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int, int, int, int>, int> g_tune;
 
 int weno_r_of(const claw_config& c) { return c.weno_order == 7 ? 4 : 3; }
 bool ssp104(const claw_config& c) { return c.time_integrator == CLAW_SSP104; }
+bool split(const claw_config& c) {
+  return c.scheme == CLAW_CLASSIC && c.dimensional_split != CLAW_SPLIT_NONE;
+}
+bool strang(const claw_config& c) { return split(c) && c.dimensional_split == CLAW_SPLIT_STRANG; }
 
 int default_seg_rows(int ny) { return std::min(ny, 16); }
 
@@ -130,6 +141,7 @@ struct claw_solver {
   int device = 0;
   int m = 0, na = 0, fp32 = 0;
   int kr = 0;                    // kernel variant of the Riemann solver
+  void* split_c[2] = {nullptr, nullptr};   // compensations of the split step's intermediates
   size_t ncell = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -196,6 +208,13 @@ size_t layout(const claw_config& c, size_t off[16]) {
     take(9, m * N * rb);                                   // s1
     take(10, m * N * rb);                                  // s2
     if (ssp104(c)) take(12, m * N * rb);                   // s3
+  } else if (split(c)) {
+    take(9, m * N * rb);                                   // state after the first sweep
+    if (fp32) take(13, m * N * rb);                        //   and its compensation
+    if (strang(c)) {
+      take(10, m * N * rb);                                // state after the second sweep
+      if (fp32) take(14, m * N * rb);
+    }
   }
   if (na) take(11, na * N * rb);                           // aux
   return p;
@@ -203,7 +222,7 @@ size_t layout(const claw_config& c, size_t off[16]) {
 
 int seg_rows_for(claw_t h) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  auto key = std::make_tuple(h->cfg.scheme, h->kr, h->cfg.precision, h->cfg.weno_order,
+  auto key = std::make_tuple(h->cfg.scheme * 4 + h->cfg.dimensional_split, h->kr, h->cfg.precision, h->cfg.weno_order,
                              h->cfg.num_cells[0], h->cfg.ndim == 2 ? h->cfg.num_cells[1] : 1);
   auto it = g_tune.find(key);
   return it != g_tune.end() ? it->second : default_seg_rows(h->cfg.ndim == 2 ? h->cfg.num_cells[1] : 1);
@@ -322,10 +341,53 @@ int launch_sharp_stages(claw_t h, int from, int to, int mode, double dt) {
   return CLAW_OK;
 }
 
+// The sweeps of one dimensionally split step (see k_split.hip):
+//   Godunov: x over dt  Q^n -> W1;  y over dt  W1 -> Q^{n+1}
+//   Strang:  x over dt/2  Q^n -> W1;  y over dt  W1 -> W2;  x over dt/2  W2 -> Q^{n+1}
+// Q^n is never overwritten, so a rejected step leaves it intact.
+int launch_split(claw_t h, int mode, double dt) {
+  const GridDesc& g = h->hg;
+  const int rows = std::max(1, std::min(g.seg_rows, g.ny));
+  const int segs = (g.ny + rows - 1) / rows;
+  int index = 0;
+  auto sweep = [&](int dir, const void* in, const void* cin, void* out, void* cout, double frac,
+                   int fin) -> int {
+    SweepArgs sa;
+    std::memset(&sa, 0, sizeof(sa));
+    sa.in = in;
+    sa.cin = cin;
+    sa.out = out;
+    sa.cout = cout;
+    sa.frac = frac;
+    sa.index = index++;
+    sa.final_sweep = fin;
+    sa.strips = dir == 0 ? (g.nx + kMarchLanesClassic - 1) / kMarchLanesClassic
+                         : (g.nx + kLanes - 1) / kLanes;
+    sa.seg_rows = rows;
+    sa.nblocks = sa.strips * segs;
+    HIPCHK(launch_sweep(dir, h->kr, h->fp32, g.limiter, h->stream, h->d_grid, mode, dt, h->src,
+                        sa));
+    return CLAW_OK;
+  };
+  void* w1 = g.s1;
+  void* c1 = h->split_c[0];
+  int rc;
+  if (strang(h->cfg)) {
+    void* w2 = g.s2;
+    void* c2 = h->split_c[1];
+    if ((rc = sweep(0, nullptr, nullptr, w1, c1, 0.5, 0))) return rc;
+    if ((rc = sweep(1, w1, c1, w2, c2, 1.0, 0))) return rc;
+    return sweep(0, w2, c2, nullptr, nullptr, 0.5, 1);
+  }
+  if ((rc = sweep(0, nullptr, nullptr, w1, c1, 1.0, 0))) return rc;
+  return sweep(1, w1, c1, nullptr, nullptr, 1.0, 1);
+}
+
 // One attempt's kernels in host-dt mode (classic: one kernel; SharpClaw: the
 // first stage only when `stage1_only`).
 int launch_attempt_host(claw_t h, double dt, bool stage1_only) {
   const GridDesc& g = h->hg;
+  if (split(h->cfg)) return launch_split(h, kHostDt, dt);
   if (h->cfg.scheme == CLAW_CLASSIC) {
     if (h->cfg.ndim == 2)
       HIPCHK(launch_classic2d(h->kr, h->fp32, g.limiter, g.transverse, g.nblocks, h->stream, h->d_grid, nullptr, 1,
@@ -344,6 +406,7 @@ int sharp_finish_host(claw_t h, double dt) { return launch_sharp_stages(h, 1, 10
 // One attempt in device-controller mode (what a graph node sequence holds).
 int launch_attempt_device(claw_t h) {
   const GridDesc& g = h->hg;
+  if (split(h->cfg)) return launch_split(h, kDeviceCtrl, 0.0);
   if (h->cfg.scheme == CLAW_CLASSIC) {
     if (h->cfg.ndim == 2)
       HIPCHK(launch_classic2d(h->kr, h->fp32, g.limiter, g.transverse, g.nblocks, h->stream, h->d_grid, nullptr, 1,
@@ -503,6 +566,7 @@ int claw_create(const claw_config* cfg, void* d_ws, size_t ws_bytes, void* hip_s
   g.ylo = cfg->ndim == 2 ? cfg->lower[1] : 0.0;
   g.source = cfg->source;
   g.weno_eps = h->cfg.weno_eps;
+  g.cfl_max = cfg->cfl_max;
   std::memcpy(g.bcstate, cfg->bc_state, sizeof(g.bcstate));
   std::memcpy(g.pd, cfg->problem_data, sizeof(g.pd));
   g.q[0] = buf(h, off, 5, base);
@@ -515,6 +579,8 @@ int claw_create(const claw_config* cfg, void* d_ws, size_t ws_bytes, void* hip_s
   g.weno_r = weno_r_of(h->cfg);
   g.aux = buf(h, off, 11, base);
   g.ctrl = h->d_ctrl;
+  h->split_c[0] = buf(h, off, 13, base);
+  h->split_c[1] = buf(h, off, 14, base);
   set_tiling(h, seg_rows_for(h));
   Ctrl c0;
   std::memset(&c0, 0, sizeof(c0));
@@ -837,7 +903,7 @@ int claw_autotune(claw_t h, int reps, claw_tuning* out) {
   if (rc) return rc;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[std::make_tuple(h->cfg.scheme, h->kr, h->cfg.precision, h->cfg.weno_order,
+    g_tune[std::make_tuple(h->cfg.scheme * 4 + h->cfg.dimensional_split, h->kr, h->cfg.precision, h->cfg.weno_order,
                            h->hg.nx, ny)] = best;
   }
   set_tiling(h, best);
@@ -968,7 +1034,7 @@ int claw_batch_destroy(claw_batch_t b) {
 int claw_batch_add(claw_batch_t b, claw_t h, double t_end) {
   if (!b || !h) return CLAW_E_INVAL;
   if ((int)b->members.size() >= b->max_grids) return CLAW_E_BUDGET;
-  if (h->cfg.scheme != CLAW_CLASSIC || h->cfg.ndim != 2) return CLAW_E_INVAL;
+  if (h->cfg.scheme != CLAW_CLASSIC || h->cfg.ndim != 2 || split(h->cfg)) return CLAW_E_INVAL;
   if (h->device != b->device) return CLAW_E_INVAL;
   if (!h->state_set || (h->na && !h->aux_set)) return CLAW_E_STATE;
   for (claw_t o : b->members)

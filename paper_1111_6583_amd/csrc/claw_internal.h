@@ -28,6 +28,7 @@ struct Ctrl {
   long long accepted, rejected, attempts, max_attempts;
   double max_courant;
   double last_speed;              // speed of the most recent attempt (diagnostics / host mode)
+  unsigned long long sweep_bits[2];   // split steps: speed maxima of the sweeps before the last
 };
 
 // Everything a kernel needs about one grid.  Lives in device memory.
@@ -41,6 +42,7 @@ struct GridDesc {
   double dx, dy;
   double ylo;                     // lower y of the domain (radius of the source term)
   double weno_eps;
+  double cfl_max;                 // split steps: a sweep above it ends the Courant reading
   double bcstate[4][8];
   double pd[8];
   void* q[2];                     // state ping-pong (Real)
@@ -66,6 +68,23 @@ struct StageArgs {
   double w;          // FINAL, FP32 increment form: a1 (P1 - w Q) + b1 ((S - Q) + gamma dt L)
   int first;         // first stage of an attempt: Courant number + controller
   int p1_is_q;       // FINAL: P1 is Q itself
+};
+
+// One 1D sweep of a dimensionally split classic step (see k_split.hip).  A
+// null state pointer stands for the step's own buffers: `in` / `cin` for
+// q / c[src] (Q^n), `out` / `cout` for q / c[src ^ 1] (Q^{n+1}), so that a
+// captured sweep follows the controller's ping-pong.
+struct SweepArgs {
+  const void* in;
+  const void* cin;   // compensation of `in` (FP32 mode)
+  void* out;
+  void* cout;
+  double frac;       // the sweep advances frac * dt
+  int index;         // position of the sweep in the step (0, 1, 2)
+  int final_sweep;   // last sweep of the step: applies the source, closes the Courant reduction
+  int nblocks;       // workgroups of this launch
+  int strips;        // column strips (workgroups per row segment)
+  int seg_rows;      // rows per workgroup
 };
 
 // How a kernel obtains dt and the source buffer.

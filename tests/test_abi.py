@@ -108,3 +108,30 @@ def test_euler_roe_tracer_and_source_options():
     assert _bytes(dict(sw, source="axisymmetric"))[0] == 0
     assert _bytes(dict(spec, scheme="sharpclaw"))[0] == 0
     assert _bytes(dict(spec, lower=(0.0, -0.5)))[0] == 0   # the radius must be >= 0
+
+
+def test_dimensional_split_options():
+    sw, _ = W.radial_dam_break(256, ny=128)
+    n0, m = _bytes(sw)
+    arr = m * 256 * 128 * 8
+    ng, _ = _bytes(dict(sw, dimensional_split="godunov"))
+    ns, _ = _bytes(dict(sw, dimensional_split="strang"))
+    # Godunov keeps one intermediate state, Strang two
+    assert arr <= ng - n0 < arr + 4096
+    assert 2 * arr <= ns - n0 < 2 * arr + 8192
+    # FP32: each intermediate carries its compensation (same bytes as FP64)
+    n32 = _bytes(dict(sw, precision="fp32_kahan"))[0]
+    ns32 = _bytes(dict(sw, precision="fp32_kahan", dimensional_split="strang"))[0]
+    assert abs((ns32 - n32) - (ns - n0)) < 8192
+    # 2D classic only
+    d1, _ = W.dam_break_1d(100)
+    assert _bytes(dict(d1, dimensional_split="godunov"))[0] == 0
+    eu, _ = W.shock_bubble(64, 32)
+    assert _bytes(dict(eu, dimensional_split="strang"))[0] == 0
+    lib = _claw.load_library()
+    c = _claw.make_config(sw)
+    c.dimensional_split = 3
+    assert lib.claw_workspace_bytes(C.byref(c)) == 0
+    # every classic 2D solver splits, with or without the axisymmetric source
+    for spec in (W.layered_elastic(64)[0], W.shock_bubble_axisym(64, 16)[0]):
+        assert _bytes(dict(spec, dimensional_split="strang"))[0] > _bytes(spec)[0]

@@ -702,3 +702,139 @@ def test_autotune_keeps_results():
     for _ in range(5):
         s.step(1e-3)
     np.testing.assert_array_equal(s.get_state(), base)
+
+
+# --------------------------------------------------------------------------
+# Dimensionally split classic steps (Godunov x-then-y, Strang x/2 y x/2)
+# --------------------------------------------------------------------------
+SPLITS = ["godunov", "strang"]
+
+
+@pytest.mark.parametrize("split", SPLITS)
+def test_split_radial_dam_break_ragged_replay(split):
+    say("case: split", split, "radial dam break 150x100 (ragged strips and segments), 30 steps")
+    spec, q = W.radial_dam_break(150, ny=100)
+    spec = dict(spec, dimensional_split=split)
+    qo, info = oracle.advance(spec, q, 1.0, max_steps=30)
+    dts = info["dts"][info["acc"] == 1]
+    assert len(dts) == 30
+    g = replay(spec, q, dts, seg_rows=9)
+    assert fp64_err(g, qo, spec) <= 1e-12
+
+
+@pytest.mark.parametrize("split", SPLITS)
+@pytest.mark.parametrize("bcl,bcu", BC_CASES[1:])
+def test_split_sw_boundary_conditions(split, bcl, bcu):
+    say("case: split", split, "SW hump 70x66 bcs", bcl, bcu)
+    spec, q = W.sw_hump(70, amplitude=0.6, width=0.15, x0=(0.3, 0.65))
+    q = q[:, :66, :].copy()
+    spec = dict(spec, num_cells=(70, 66), upper=(1.0, 66 / 70), bc_lower=bcl, bc_upper=bcu,
+                dimensional_split=split)
+    q[1] = 0.2 * q[0]
+    q[2] = -0.1 * q[0]
+    qo, info = oracle.advance(spec, q, 1.0, max_steps=25)
+    g = replay(spec, q, info["dts"][info["acc"] == 1])
+    assert fp64_err(g, qo, spec) <= 1e-12
+
+
+@pytest.mark.parametrize("split", SPLITS)
+def test_split_sw_dirichlet_sides(split):
+    say("case: split", split, "SW with Dirichlet sides")
+    spec, q = W.sw_hump(64, amplitude=0.5, width=0.2)
+    spec = dict(spec, bc_lower=("dirichlet", "wall"), bc_upper=("extrap", "dirichlet"),
+                bc_state={"x_lower": [1.5, 0.3, 0.0], "y_upper": [1.2, 0.0, -0.2]},
+                dimensional_split=split)
+    qo, info = oracle.advance(spec, q, 1.0, max_steps=25)
+    g = replay(spec, q, info["dts"][info["acc"] == 1])
+    assert fp64_err(g, qo, spec) <= 1e-12
+
+
+@pytest.mark.parametrize("lim", ["none", "minmod"])
+def test_split_limiters_and_advection_exact_shift(lim):
+    say("case: split advection 64x48, Courant 1 per sweep, limiter", lim)
+    nx, ny = 64, 48
+    dt = 1.0 / nx
+    spec = dict(ndim=2, num_cells=(nx, ny), lower=(0, 0), upper=(1, 1), riemann="advection",
+                limiter=lim, bc_lower=("periodic", "periodic"), bc_upper=("periodic", "periodic"),
+                problem_data=[2.0, (1.0 / ny) / dt], dimensional_split="strang")
+    q0 = np.random.default_rng(21).standard_normal((1, ny, nx))
+    g = replay(spec, q0, [dt] * 5)
+    np.testing.assert_allclose(g, np.roll(q0, (5, 10), axis=(1, 2)), rtol=0, atol=1e-12)
+    spec = dict(spec, problem_data=[0.7, -0.45], dimensional_split="godunov")
+    qo = q0
+    for _ in range(12):
+        qo, _ = oracle.step(spec, qo, 0.8 / nx)
+    g = replay(spec, q0, [0.8 / nx] * 12)
+    assert fp64_err(g, qo, spec) <= 1e-12
+
+
+@pytest.mark.parametrize("split", SPLITS)
+def test_split_layered_elastic_replay(split):
+    say("case: split", split, "layered elasticity 96x80, 20 steps")
+    spec, q, aux = W.layered_elastic(96, ny=80)
+    spec = dict(spec, dimensional_split=split)
+    qo, info = oracle.advance(spec, q, 1.0, aux=aux, max_steps=20)
+    g = replay(spec, q, info["dts"][info["acc"] == 1], aux=aux)
+    assert fp64_err(g, qo, spec) <= 1e-12
+
+
+@pytest.mark.parametrize("split", SPLITS)
+def test_split_axisym_shock_bubble_replay(split):
+    say("case: split", split, "axisymmetric shock-bubble 160x40 (tracer, source), 25 steps")
+    spec, q = W.shock_bubble_axisym(160, 40)
+    spec = dict(spec, dimensional_split=split)
+    qo, info = oracle.advance(spec, q, 1.0, max_steps=25)
+    g = replay(spec, q, info["dts"][info["acc"] == 1])
+    assert fp64_err(g, qo, spec) <= 1e-12
+
+
+@pytest.mark.parametrize("split", SPLITS)
+@pytest.mark.parametrize("graph", [False, True])
+def test_split_controller_with_rejection(split, graph):
+    say("case: split", split, "forced rejection 2D 40x36, graph", graph)
+    spec, q = W.radial_dam_break(40, ny=36)
+    spec = dict(spec, dt_initial=5.0, dimensional_split=split)
+    qo, info = oracle.advance(spec, q, 0.4)
+    s = solver(spec, q)
+    st = s.advance(0.4, graph=graph, steps_per_graph=4)
+    assert (st["accepted"], st["rejected"]) == (info["accepted"], info["rejected"])
+    assert st["rejected"] >= 1 and st["t"] == 0.4
+    assert st["max_courant"] == pytest.approx(info["max_courant"], rel=1e-12)
+    assert fp64_err(s.get_state(), qo, spec) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_kahan"])
+def test_split_tiling_does_not_change_results(prec):
+    say("case: split strang seg_rows 4/16/100 bitwise equal", prec)
+    spec, q = W.radial_dam_break(150, ny=100)
+    spec = dict(spec, precision=prec, dimensional_split="strang")
+    outs = [replay(spec, q, [2e-3] * 10, seg_rows=sr) for sr in (4, 16, 100)]
+    np.testing.assert_array_equal(outs[0], outs[1])
+    np.testing.assert_array_equal(outs[0], outs[2])
+
+
+@pytest.mark.parametrize("split", SPLITS)
+def test_fp32_kahan_split_radial_dam_break_l1(split):
+    say("case: FP32+Kahan split", split, "radial dam break 256^2 to t=0.25 (replayed dt)")
+    spec, q = W.radial_dam_break(256)
+    spec = dict(spec, dimensional_split=split)
+    qo, dts, _ = oracle_run(spec, q, 0.25)
+    g = replay(dict(spec, precision="fp32_kahan"), q, dts)
+    err = l1_rel_groups(g, qo, spec)
+    say("L1 relative errors (unit-group scale)", err)
+    assert max(err) <= 1e-5
+
+
+@pytest.mark.parametrize("split", SPLITS)
+def test_full_size_split_radial_dam_break_one_step(split):
+    say("case: split", split, "radial dam break 1024^2, one-step parity after 30 GPU steps")
+    spec, q = W.radial_dam_break(1024)
+    spec = dict(spec, dimensional_split=split)
+    s = solver(spec, q)
+    s.autotune(reps=2)
+    s.advance(1.0, max_steps=30)
+    q1 = s.get_state()
+    dt = s.clock()["dt_next"]
+    s.step(dt)
+    o, _ = oracle.step(spec, q1, dt)
+    assert fp64_err(s.get_state(), o, spec) <= 1e-12
