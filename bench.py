@@ -81,6 +81,8 @@ def timed_run(spec, q, aux, steps, warmup, t_end, tune=True, graph_k=16):
     out = dict(cells=ncell, steps=acc, rejected=st["rejected"] - c0["rejected"], wall_s=wall,
                gpu_ms=st["gpu_ms"], seg_rows=seg, kernel_ms=kernel_ms, t=st["t"],
                value=ncell * acc / wall, ms_per_step=1e3 * wall / max(acc, 1))
+    if spec.get("dimensional_split", "none") != "none":
+        out["seg_rows_x"] = s.get_tuning_x()
     s.close()
     return out
 
@@ -113,8 +115,12 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 #            solve 156 + limiter for 5 waves 90 + correction 60 + transverse
 #            split and accumulation 214) + cell primitives 16 + update 50 +
 #            source (Heun) 48 + Courant maxima 10; HBM 80 B (5 FP64 in + out)
+#   sw_sweep   one 1D sweep of a dimensionally split shallow-water step, per
+#            cell: 1 face x (Roe solve 73 + limiter 46 + correction 32) + cell
+#            primitives 4 + update 15 + Courant maximum 3 = 173; HBM 48 B (FP64
+#            q in + out); Godunov splitting is 2 sweeps a step, Strang 3
 FLOPS_PER_CELL = {"sw": 554.0, "euler_stage": 1040.0, "euler_stage_weno7": 1840.0,
-                  "euler_roe": 1160.0}
+                  "euler_roe": 1160.0, "sw_sweep": 173.0}
 
 
 def roofline(bound, cells, gpu_ms, launches, kernel_name, bytes_per_launch, flops_per_launch=None,
@@ -239,10 +245,16 @@ WORKLOADS = {
     "sw": ("2D shallow water radial dam break 1024^2", lambda W: W.radial_dam_break(1024) + (None,)),
     "euler": ("2D Euler shock-bubble 2048x1024 SharpClaw", lambda W: W.shock_bubble(2048, 1024) + (None,)),
     "elastic": ("2D layered elasticity 2048^2", lambda W: W.layered_elastic(2048)),
+    "sw_godunov": ("2D shallow water radial dam break 1024^2, Godunov split",
+                   lambda W: (dict(W.radial_dam_break(1024)[0], dimensional_split="godunov"),
+                              W.radial_dam_break(1024)[1], None)),
+    "sw_strang": ("2D shallow water radial dam break 1024^2, Strang split",
+                  lambda W: (dict(W.radial_dam_break(1024)[0], dimensional_split="strang"),
+                             W.radial_dam_break(1024)[1], None)),
 }
 
 
-def kernel_only(workload, precision, launches, seg_rows=0):
+def kernel_only(workload, precision, launches, seg_rows=0, seg_rows_x=0):
     """Launch only the step kernel (classic) or stages 1-2 (SharpClaw) of a
     workload `launches` times, for hardware-counter runs.  seg_rows > 0 fixes
     the tiling (no autotuning launches in the profile)."""
@@ -255,7 +267,7 @@ def kernel_only(workload, precision, launches, seg_rows=0):
     if aux is not None:
         s.set_aux(aux)
     if seg_rows > 0:
-        s.set_tuning(seg_rows)
+        s.set_tuning(seg_rows, seg_rows_x)
     else:
         s.autotune(reps=2)
     s.advance(1e9, max_steps=10)
@@ -293,13 +305,15 @@ def main():
     ap.add_argument("--launches", type=int, default=20)
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--seg-rows", type=int, default=0, help="kernel mode: fixed rows per segment")
+    ap.add_argument("--seg-rows-x", type=int, default=0,
+                    help="kernel mode, split steps: fixed rows per segment of the x sweeps")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU: this build runs the step on a single MI355X "
               "(multi-GPU decomposition is designed but not built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     if a.mode == "kernel":
-        return kernel_only(a.workload, a.precision, a.launches, a.seg_rows)
+        return kernel_only(a.workload, a.precision, a.launches, a.seg_rows, a.seg_rows_x)
     if a.mode == "copy":
         return copy_only(a.copy_mib, a.launches)
 
@@ -369,6 +383,15 @@ def main():
                                  "k_classic2d<double,EulerRoe+tracer>", 80 * r["cells"],
                                  FLOPS_PER_CELL["euler_roe"] * r["cells"], "f64")
         extras["euler_shock_bubble_axisym_1280x320_classic_fp64"] = r
+
+        log("dimensionally split radial dam break 1024^2 (Godunov, Strang), FP64")
+        for split, nsw in (("godunov", 2), ("strang", 3)):
+            r = timed_run(dict(spec, dimensional_split=split), q, None, a.steps, a.warmup, 1.0)
+            r["roofline"] = roofline("alu", r["cells"], r["gpu_ms"], nsw * (r["steps"] + r["rejected"]),
+                                     f"k_sweep_x/y<double,ShallowWater> ({split})", 48 * r["cells"],
+                                     FLOPS_PER_CELL["sw_sweep"] * r["cells"], "f64")
+            r["sweeps_per_step"] = nsw
+            extras[f"sw_radial_1024_fp64_split_{split}"] = r
 
         log("layered elasticity 2048^2")
         el_spec, el_q, el_aux = W.layered_elastic(2048)

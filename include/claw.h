@@ -160,8 +160,11 @@ typedef struct claw_stats {
 
 /* Kernel tiling.  Results do not depend on it (bit for bit). */
 typedef struct claw_tuning {
-  int seg_rows;          /* rows per work item of the 2D kernels (>= 1) */
-  int reserved[3];
+  int seg_rows;          /* rows per work item of the 2D kernels (>= 1); of the y sweeps of a
+                            dimensionally split step */
+  int seg_rows_x;        /* rows per work item of the x sweeps of a dimensionally split step
+                            (rows are independent there); <= 0: seg_rows.  Ignored otherwise */
+  int reserved[2];
 } claw_tuning;
 
 typedef struct claw_solver* claw_t;
@@ -232,7 +235,8 @@ int claw_set_tuning(claw_t h, const claw_tuning* tn);
 int claw_get_tuning(claw_t h, claw_tuning* tn);
 
 /* Time one step (without applying it) for each candidate seg_rows and keep
- * the fastest; *out (may be NULL) receives it.  reps: timed repetitions. */
+ * the fastest; *out (may be NULL) receives it.  reps: timed repetitions.
+ * Split steps tune seg_rows (y sweeps) first, then seg_rows_x. */
 int claw_autotune(claw_t h, int reps, claw_tuning* out);
 
 /* Launch the step's main kernel `reps` times back to back on the handle's

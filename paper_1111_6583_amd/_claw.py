@@ -47,7 +47,7 @@ class ClawStats(C.Structure):
 
 
 class ClawTuning(C.Structure):
-    _fields_ = [("seg_rows", C.c_int), ("reserved", C.c_int * 3)]
+    _fields_ = [("seg_rows", C.c_int), ("seg_rows_x", C.c_int), ("reserved", C.c_int * 2)]
 
 
 class ClawError(RuntimeError):

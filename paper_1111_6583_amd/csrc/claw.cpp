@@ -42,7 +42,6 @@ hipError_t launch_cell_speed(int ndim, int riemann, int fp32, const GridDesc* g,
 int totals_blocks();
 hipError_t launch_totals(int fp32, const void* q, const void* c, int m, size_t n, double cell,
                          double* part, double* out, hipStream_t st);
-hipError_t launch_ctrl_reset(Ctrl* c, hipStream_t st);
 }  // namespace claw
 
 using namespace claw;
@@ -121,9 +120,9 @@ int validate(const claw_config* c) {
 }
 
 // Process-wide tiling cache: (4 scheme + split mode, riemann, precision, WENO order, nx, ny)
-// -> seg_rows.
+// -> (seg_rows, seg_rows_x).
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int, int, int>, int> g_tune;
+std::map<std::tuple<int, int, int, int, int, int>, std::pair<int, int>> g_tune;
 
 int weno_r_of(const claw_config& c) { return c.weno_order == 7 ? 4 : 3; }
 bool ssp104(const claw_config& c) { return c.time_integrator == CLAW_SSP104; }
@@ -133,6 +132,9 @@ bool split(const claw_config& c) {
 bool strang(const claw_config& c) { return split(c) && c.dimensional_split == CLAW_SPLIT_STRANG; }
 
 int default_seg_rows(int ny) { return std::min(ny, 16); }
+// x sweeps of a split step: rows are independent, so short row segments buy
+// more wavefronts at no extra work
+int default_seg_rows_x(int ny) { return std::min(ny, 4); }
 
 }  // namespace
 
@@ -142,6 +144,7 @@ struct claw_solver {
   int m = 0, na = 0, fp32 = 0;
   int kr = 0;                    // kernel variant of the Riemann solver
   void* split_c[2] = {nullptr, nullptr};   // compensations of the split step's intermediates
+  int seg_rows_x = 0;            // rows per workgroup of the split step's x sweeps
   size_t ncell = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -198,6 +201,7 @@ size_t layout(const claw_config& c, size_t off[16]) {
   take(2, (size_t)m * totals_blocks() * sizeof(double));   // totals partials
   take(3, 8 * sizeof(double));                             // totals out
   take(4, sizeof(unsigned long long));                     // a-priori speed
+  take(15, kSpeedSlots * sizeof(SpeedSlot));               // launch-end Courant reduction
   take(5, m * N * rb);                                     // q[0]
   if (classic) take(6, m * N * rb);                        // q[1]
   if (fp32) {
@@ -220,12 +224,18 @@ size_t layout(const claw_config& c, size_t off[16]) {
   return p;
 }
 
-int seg_rows_for(claw_t h) {
+std::tuple<int, int, int, int, int, int> tune_key(claw_t h) {
+  return std::make_tuple(h->cfg.scheme * 4 + h->cfg.dimensional_split, h->kr, h->cfg.precision,
+                         h->cfg.weno_order, h->cfg.num_cells[0],
+                         h->cfg.ndim == 2 ? h->cfg.num_cells[1] : 1);
+}
+
+std::pair<int, int> seg_rows_for(claw_t h) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  auto key = std::make_tuple(h->cfg.scheme * 4 + h->cfg.dimensional_split, h->kr, h->cfg.precision, h->cfg.weno_order,
-                             h->cfg.num_cells[0], h->cfg.ndim == 2 ? h->cfg.num_cells[1] : 1);
-  auto it = g_tune.find(key);
-  return it != g_tune.end() ? it->second : default_seg_rows(h->cfg.ndim == 2 ? h->cfg.num_cells[1] : 1);
+  auto it = g_tune.find(tune_key(h));
+  const int ny = h->cfg.ndim == 2 ? h->cfg.num_cells[1] : 1;
+  return it != g_tune.end() ? it->second
+                            : std::make_pair(default_seg_rows(ny), default_seg_rows_x(ny));
 }
 
 void set_tiling(claw_t h, int seg_rows) {
@@ -347,8 +357,8 @@ int launch_sharp_stages(claw_t h, int from, int to, int mode, double dt) {
 // Q^n is never overwritten, so a rejected step leaves it intact.
 int launch_split(claw_t h, int mode, double dt) {
   const GridDesc& g = h->hg;
-  const int rows = std::max(1, std::min(g.seg_rows, g.ny));
-  const int segs = (g.ny + rows - 1) / rows;
+  const int rows_y = std::max(1, std::min(g.seg_rows, g.ny));
+  const int rows_x = std::max(1, std::min(h->seg_rows_x > 0 ? h->seg_rows_x : g.seg_rows, g.ny));
   int index = 0;
   auto sweep = [&](int dir, const void* in, const void* cin, void* out, void* cout, double frac,
                    int fin) -> int {
@@ -363,8 +373,8 @@ int launch_split(claw_t h, int mode, double dt) {
     sa.final_sweep = fin;
     sa.strips = dir == 0 ? (g.nx + kMarchLanesClassic - 1) / kMarchLanesClassic
                          : (g.nx + kLanes - 1) / kLanes;
-    sa.seg_rows = rows;
-    sa.nblocks = sa.strips * segs;
+    sa.seg_rows = dir == 0 ? rows_x : rows_y;
+    sa.nblocks = sa.strips * ((g.ny + sa.seg_rows - 1) / sa.seg_rows);
     HIPCHK(launch_sweep(dir, h->kr, h->fp32, g.limiter, h->stream, h->d_grid, mode, dt, h->src,
                         sa));
     return CLAW_OK;
@@ -579,13 +589,19 @@ int claw_create(const claw_config* cfg, void* d_ws, size_t ws_bytes, void* hip_s
   g.weno_r = weno_r_of(h->cfg);
   g.aux = buf(h, off, 11, base);
   g.ctrl = h->d_ctrl;
+  g.slots = (SpeedSlot*)buf(h, off, 15, base);
   h->split_c[0] = buf(h, off, 13, base);
   h->split_c[1] = buf(h, off, 14, base);
-  set_tiling(h, seg_rows_for(h));
+  {
+    const std::pair<int, int> t = seg_rows_for(h);
+    set_tiling(h, t.first);
+    h->seg_rows_x = t.second;
+  }
   Ctrl c0;
   std::memset(&c0, 0, sizeof(c0));
   rc = CLAW_OK;
   if (hipMemcpyAsync(h->d_ctrl, &c0, sizeof(Ctrl), hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+      hipMemsetAsync(g.slots, 0, kSpeedSlots * sizeof(SpeedSlot), h->stream) != hipSuccess ||
       upload_grid(h) != CLAW_OK || hipStreamSynchronize(h->stream) != hipSuccess)
     rc = CLAW_E_DEVICE;
   if (rc) {
@@ -841,6 +857,7 @@ int claw_set_tuning(claw_t h, const claw_tuning* tn) {
   if (!h || !tn || tn->seg_rows < 1) return CLAW_E_INVAL;
   HIPCHK(hipSetDevice(h->device));
   set_tiling(h, tn->seg_rows);
+  h->seg_rows_x = tn->seg_rows_x > 0 ? tn->seg_rows_x : 0;
   int rc = upload_grid(h);
   if (rc) return rc;
   if (h->graph) { hipGraphExecDestroy(h->graph); h->graph = nullptr; }
@@ -851,6 +868,7 @@ int claw_get_tuning(claw_t h, claw_tuning* tn) {
   if (!h || !tn) return CLAW_E_INVAL;
   std::memset(tn, 0, sizeof(*tn));
   tn->seg_rows = h->hg.seg_rows;
+  tn->seg_rows_x = h->seg_rows_x > 0 ? h->seg_rows_x : h->hg.seg_rows;
   return CLAW_OK;
 }
 
@@ -875,43 +893,57 @@ int claw_autotune(claw_t h, int reps, claw_tuning* out) {
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  int best = cands[0];
-  float best_ms = std::numeric_limits<float>::infinity();
-  for (int c : cands) {
-    set_tiling(h, c);
-    if ((rc = upload_grid(h))) break;
-    // warm-up, then timed repetitions; host-dt launches write the other
-    // buffer (classic) or the stage buffers (SharpClaw stages 1-2) and leave
-    // the state untouched
-    auto run = [&]() -> int {
-      if (h->cfg.scheme == CLAW_CLASSIC) return launch_attempt_host(h, dt, true);
-      return launch_sharp_stages(h, 0, 2, kHostDt, dt);
-    };
-    if ((rc = run())) break;
-    HIPCHK(hipEventRecord(e0, h->stream));
-    for (int r = 0; r < reps; ++r)
-      if ((rc = run())) break;
-    if (rc) break;
-    HIPCHK(hipEventRecord(e1, h->stream));
-    HIPCHK(hipEventSynchronize(e1));
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best_ms) { best_ms = ms; best = c; }
+  // warm-up, then timed repetitions; host-dt launches write the other
+  // buffer (classic), the split step's intermediates or the stage buffers
+  // (SharpClaw stages 1-2) and leave the state untouched
+  auto run = [&]() -> int {
+    if (h->cfg.scheme == CLAW_CLASSIC) return launch_attempt_host(h, dt, true);
+    return launch_sharp_stages(h, 0, 2, kHostDt, dt);
+  };
+  // time every candidate of one tiling parameter (`apply` installs it) and
+  // leave the fastest installed
+  auto tune = [&](const std::vector<int>& cs, auto apply) -> int {
+    int best = cs[0];
+    float best_ms = std::numeric_limits<float>::infinity();
+    for (int c : cs) {
+      apply(c);
+      if ((rc = upload_grid(h))) return best;
+      if ((rc = run())) return best;
+      if (hipEventRecord(e0, h->stream) != hipSuccess) { rc = CLAW_E_DEVICE; return best; }
+      for (int r = 0; r < reps && !rc; ++r) rc = run();
+      if (rc) return best;
+      float ms = 0.f;
+      if (hipEventRecord(e1, h->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        rc = CLAW_E_DEVICE;
+        return best;
+      }
+      if (ms < best_ms) { best_ms = ms; best = c; }
+    }
+    apply(best);
+    return best;
+  };
+  const int best = tune(cands, [&](int c) { set_tiling(h, c); });
+  int best_x = 0;
+  if (!rc && split(h->cfg)) {
+    std::vector<int> cx;
+    for (int c : {1, 2, 3, 4, 6, 8, 12, 16, 24, 32})
+      if (c <= ny) cx.push_back(c);
+    best_x = tune(cx, [&](int c) { h->seg_rows_x = c; });
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (rc) return rc;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[std::make_tuple(h->cfg.scheme * 4 + h->cfg.dimensional_split, h->kr, h->cfg.precision, h->cfg.weno_order,
-                           h->hg.nx, ny)] = best;
+    g_tune[tune_key(h)] = std::make_pair(best, best_x);
   }
-  set_tiling(h, best);
   if ((rc = upload_grid(h))) return rc;
   if (h->graph) { hipGraphExecDestroy(h->graph); h->graph = nullptr; }
   if (out) {
     std::memset(out, 0, sizeof(*out));
     out->seg_rows = best;
+    out->seg_rows_x = best_x > 0 ? best_x : best;
   }
   return sync(h);
 }

@@ -13,8 +13,7 @@ constexpr int kMaxAux = 3;
 // Device-resident step controller of one grid (Section 5: after each step
 // the Courant number is checked and the next step size chosen).
 struct Ctrl {
-  unsigned long long speed_bits;  // atomic max of max|s|/spacing (bit pattern of a non-negative double)
-  unsigned int counter;           // workgroups of the current launch that have finished
+  unsigned int counter;           // speed slots of the current launch that are complete
   int src;                        // buffer index holding Q^n (classic ping-pong)
   int active;                     // 1 while t < t_end and attempts remain
   int ok;                         // SharpClaw: the current attempt passed the stage-1 check
@@ -29,6 +28,15 @@ struct Ctrl {
   double max_courant;
   double last_speed;              // speed of the most recent attempt (diagnostics / host mode)
   unsigned long long sweep_bits[2];   // split steps: speed maxima of the sweeps before the last
+};
+
+// One slot of the two-level Courant reduction at the end of a launch (see
+// finish_workgroup): a maximum and a count of the workgroups folded into it.
+constexpr int kSpeedSlots = 64;
+struct SpeedSlot {
+  unsigned long long max_bits;    // max|s|/spacing (bit pattern of a non-negative double)
+  unsigned int count;
+  unsigned int pad[61];           // one slot per 256 bytes
 };
 
 // Everything a kernel needs about one grid.  Lives in device memory.
@@ -53,6 +61,7 @@ struct GridDesc {
   int weno_r;                     // SharpClaw: WENO order 2r-1 (r = 3 or 4)
   const void* aux;                // aux fields (Real)
   Ctrl* ctrl;
+  SpeedSlot* slots;               // kSpeedSlots slots of the launch-end reduction
 };
 
 // One SharpClaw Runge-Kutta stage (see k_sharp.hip): y = S + gamma dt L(S),

@@ -221,36 +221,66 @@ __device__ inline bool ctrl_decide(Ctrl* c, double speed) {
   return ok;
 }
 
-// End-of-workgroup bookkeeping: fold this wave's max speed into the grid's
-// slot; the last workgroup of the launch (over this grid) reads the total,
-// hands it to `decide` (the device controller, or just recording it for the
-// host controller), and clears the slot and counter for the next launch.
+// End-of-workgroup bookkeeping: fold this wave's max speed into the launch's
+// reduction; the last workgroup of the launch (over this grid) hands the
+// total to `decide` (the device controller, or just recording it for the
+// host controller) and clears the reduction for the next launch.
 //
-// Ordering without fences: both atomics are device-scope read-modify-writes
-// on one cache line, performed at the device's coherence point.  A workgroup
-// issues its counter increment only after its maximum has returned (the
-// increment's operand depends on the returned value), so whoever sees the
-// final count sees every maximum.  No release/acquire fence is used: on this
-// GPU a device-scope fence writes back and invalidates the whole L2 of the
-// XCD, which every workgroup would do at once at the end of each launch.
-// The controller fields the last workgroup writes with plain stores are read
-// by the next launch (kernel boundaries order them).
+// Two levels, so that no single address takes one atomic per workgroup
+// (device-scope atomics on one address are performed one after another, about
+// 11 ns each on this GPU, and the workgroups of a launch end nearly together):
+// workgroup b folds into slot b mod S (S = min(64, nblocks) slots, 256 bytes
+// apart) and counts itself there; the workgroup completing a slot counts the
+// slot in the controller's counter; the one completing the counter reduces
+// the S slot maxima with its whole wave and decides.
+//
+// Ordering without fences: every step is a device-scope read-modify-write
+// whose result is returned, and each next step's operand depends on the
+// previous result (the asm ties), so a completed slot count implies every
+// maximum of that slot was performed, and a completed controller count
+// implies every slot was.  The final loads are device-scope atomic loads
+// issued after that.  No release/acquire fence is used: on this GPU a
+// device-scope fence writes back and invalidates the whole L2 of the XCD,
+// which every workgroup would do at once at the end of each launch.  The
+// controller fields the last workgroup writes with plain stores are read by
+// the next launch (kernel boundaries order them).
 template <class Decide>
-__device__ inline void finish_workgroup(Ctrl* c, double local_max, int nblocks, Decide decide) {
+__device__ inline void finish_workgroup(Ctrl* c, SpeedSlot* slots, int blk, int nblocks,
+                                        double local_max, Decide decide) {
   local_max = wave_max(local_max);   // NaN-preserving: NaN bits compare above every finite speed
+  const int ns = nblocks < kSpeedSlots ? nblocks : kSpeedSlots;
+  CLAW_GLOBAL SpeedSlot* sl = (CLAW_GLOBAL SpeedSlot*)slots;
+  CLAW_GLOBAL Ctrl* g = (CLAW_GLOBAL Ctrl*)c;
+  int last = 0;
   if (threadIdx.x == 0) {
-    CLAW_GLOBAL Ctrl* g = (CLAW_GLOBAL Ctrl*)c;
+    const int k = blk % ns;
+    const unsigned int nk = (unsigned int)(nblocks / ns + (k < nblocks % ns ? 1 : 0));
     const unsigned long long prev = __hip_atomic_fetch_max(
-        &g->speed_bits, dbits(local_max), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        &sl[k].max_bits, dbits(local_max), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     unsigned int one = 1u;
     asm volatile("" : "+v"(one) : "v"(prev));
     const unsigned int done =
-        __hip_atomic_fetch_add(&g->counter, one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (done == (unsigned int)(nblocks - 1)) {
-      const double speed = bitsd(
-          __hip_atomic_fetch_add(&g->speed_bits, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        __hip_atomic_fetch_add(&sl[k].count, one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (done == nk - 1) {
+      __hip_atomic_store(&sl[k].count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      unsigned int one2 = 1u;
+      asm volatile("" : "+v"(one2) : "v"(done));
+      const unsigned int full =
+          __hip_atomic_fetch_add(&g->counter, one2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      last = full == (unsigned int)(ns - 1) ? 1 : 0;
+    }
+  }
+  last = __builtin_amdgcn_readfirstlane(last);
+  if (last) {
+    const int j = threadIdx.x;
+    double v = 0.0;
+    if (j < ns) {
+      v = bitsd(__hip_atomic_load(&sl[j].max_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      __hip_atomic_store(&sl[j].max_bits, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const double speed = wave_max(v);
+    if (threadIdx.x == 0) {
       decide(c, speed);
-      __hip_atomic_store(&g->speed_bits, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&g->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }

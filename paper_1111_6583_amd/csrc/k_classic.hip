@@ -384,11 +384,12 @@ __global__ __launch_bounds__(kLanes) void k_classic2d(const GridDesc* __restrict
   const double speed = own ? max_nan((double)smx / G.dx, (double)smy / G.dy)
                            : (own_face ? (double)smx / G.dx : 0.0);
   if (mode == kDeviceCtrl) {
-    finish_workgroup(ctrl, speed, G.nblocks, [](Ctrl* c, double sp) {
+    finish_workgroup(ctrl, G.slots, lb, G.nblocks, speed, [](Ctrl* c, double sp) {
       if (ctrl_decide(c, sp)) c->src ^= 1;
     });
   } else {
-    finish_workgroup(ctrl, speed, G.nblocks, [](Ctrl* c, double sp) { c->last_speed = sp; });
+    finish_workgroup(ctrl, G.slots, lb, G.nblocks, speed,
+                     [](Ctrl* c, double sp) { c->last_speed = sp; });
   }
 }
 
@@ -475,11 +476,12 @@ __global__ __launch_bounds__(kLanes) void k_classic1d(const GridDesc* __restrict
   }
   const double speed = own_face ? (double)smx / G.dx : 0.0;
   if (mode == kDeviceCtrl) {
-    finish_workgroup(ctrl, speed, G.nblocks, [](Ctrl* c, double sp) {
+    finish_workgroup(ctrl, G.slots, blockIdx.x, G.nblocks, speed, [](Ctrl* c, double sp) {
       if (ctrl_decide(c, sp)) c->src ^= 1;
     });
   } else {
-    finish_workgroup(ctrl, speed, G.nblocks, [](Ctrl* c, double sp) { c->last_speed = sp; });
+    finish_workgroup(ctrl, G.slots, blockIdx.x, G.nblocks, speed,
+                     [](Ctrl* c, double sp) { c->last_speed = sp; });
   }
 }
 

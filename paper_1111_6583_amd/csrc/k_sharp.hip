@@ -155,17 +155,20 @@ __device__ __forceinline__ bool stage_dt(Ctrl* ctrl, int mode, double dt_host, i
   return true;
 }
 
-__device__ __forceinline__ void stage_finish(Ctrl* ctrl, int mode, int first, double speed,
-                                             int nblocks) {
+__device__ __forceinline__ void stage_finish(const GridDesc& G, int mode, int first,
+                                             double speed) {
   if (!first) return;
+  Ctrl* ctrl = G.ctrl;
+  const int b = blockIdx.x, nblocks = G.nblocks;
   if (mode == kDeviceCtrl) {
-    finish_workgroup(ctrl, speed, nblocks, [](Ctrl* c, double sp) {
+    finish_workgroup(ctrl, G.slots, b, nblocks, speed, [](Ctrl* c, double sp) {
       const double d = c->dt_try;
       c->ok = ctrl_decide(c, sp) ? 1 : 0;
       c->dt_stage = d;
     });
   } else {
-    finish_workgroup(ctrl, speed, nblocks, [](Ctrl* c, double sp) { c->last_speed = sp; });
+    finish_workgroup(ctrl, G.slots, b, nblocks, speed,
+                     [](Ctrl* c, double sp) { c->last_speed = sp; });
   }
 }
 
@@ -312,7 +315,7 @@ __global__ __launch_bounds__(kLanes) void k_sharp2d(const GridDesc* __restrict__
   }
   const double speed = own ? max_nan((double)smx * (1.0 / G.dx), (double)smy * (1.0 / G.dy))
                            : (own_face ? (double)smx * (1.0 / G.dx) : 0.0);
-  stage_finish(ctrl, mode, sa.first, speed, G.nblocks);
+  stage_finish(G, mode, sa.first, speed);
 }
 
 template <typename R, class P, int RH, int KIND, bool KAHAN>
@@ -369,7 +372,7 @@ __global__ __launch_bounds__(kLanes) void k_sharp1d(const GridDesc* __restrict__
                                    as_gmut<R>(G.c[0]), (size_t)i, (size_t)nx, c, Lv, gdt,
                                    (R)sa.a1, (R)sa.b1, (R)sa.a2, (R)sa.b2, (R)sa.w, pp, pq, pc);
   const double speed = own_face ? (double)sx * (1.0 / G.dx) : 0.0;
-  stage_finish(ctrl, mode, sa.first, speed, G.nblocks);
+  stage_finish(G, mode, sa.first, speed);
 }
 
 // ---------------------------------------------------------------------------

@@ -26,9 +26,9 @@
 // whose own value (dt times its speed) exceeds cfl_max or is not finite;
 // that sweep rejects the step (or flags it non-physical) and the sweeps
 // after it, which act on an unstable intermediate, do not count.  Each
-// non-final sweep folds its maximum into a slot of its own; the final sweep's
-// last workgroup combines them (host dt: records the speed; device
-// controller: decides the step and flips the ping-pong).  The axisymmetric
+// non-final sweep's last workgroup stores the sweep's maximum in a field of
+// its own; the final sweep's last workgroup combines them (host dt: records
+// the speed; device controller: decides the step and flips the ping-pong).  The axisymmetric
 // source is applied by the final sweep, after the hyperbolic update of the
 // cell, over the full dt (a fractional step, as in the unsplit kernel).
 #include "dev_common.h"
@@ -36,18 +36,7 @@
 
 namespace claw {
 
-// Fold a wave's largest speed/spacing into the slot of sweep `k` (NaN bits
-// compare above every finite speed, so a NaN survives the maximum).
-__device__ inline void fold_speed(Ctrl* c, int k, double local_max) {
-  local_max = wave_max(local_max);
-  if (threadIdx.x == 0) {
-    CLAW_GLOBAL Ctrl* g = (CLAW_GLOBAL Ctrl*)c;
-    __hip_atomic_fetch_max(&g->sweep_bits[k], dbits(local_max), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-  }
-}
-
-// The step's speed from the earlier sweeps' slots (cleared for the next
+// The step's speed from the earlier sweeps' totals (cleared for the next
 // step) and the final sweep's own maximum `last`.
 __device__ inline double split_speed(Ctrl* c, int nprev, double dt, double cfl_max, double last) {
   CLAW_GLOBAL Ctrl* g = (CLAW_GLOBAL Ctrl*)c;
@@ -64,17 +53,25 @@ __device__ inline double split_speed(Ctrl* c, int nprev, double dt, double cfl_m
   return open ? max_nan(s, last) : s;
 }
 
-__device__ inline void close_sweep(Ctrl* ctrl, int mode, const SweepArgs& sa, double dt,
-                                   double cfl_max, double speed) {
+// End of a sweep's workgroup: a non-final sweep stores its total in its own
+// controller field; the final sweep combines them and closes the step.
+__device__ inline void close_sweep(const GridDesc& G, int mode, const SweepArgs& sa, double dt,
+                                   double speed) {
+  Ctrl* ctrl = G.ctrl;
   const int nprev = sa.index;
+  const double cfl_max = G.cfl_max;
   if (!sa.final_sweep) {
-    fold_speed(ctrl, sa.index, speed);
+    finish_workgroup(ctrl, G.slots, blockIdx.x, sa.nblocks, speed, [=](Ctrl* c, double sp) {
+      CLAW_GLOBAL Ctrl* g = (CLAW_GLOBAL Ctrl*)c;
+      __hip_atomic_store(&g->sweep_bits[nprev], dbits(sp), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    });
   } else if (mode == kDeviceCtrl) {
-    finish_workgroup(ctrl, speed, sa.nblocks, [=](Ctrl* c, double sp) {
+    finish_workgroup(ctrl, G.slots, blockIdx.x, sa.nblocks, speed, [=](Ctrl* c, double sp) {
       if (ctrl_decide(c, split_speed(c, nprev, dt, cfl_max, sp))) c->src ^= 1;
     });
   } else {
-    finish_workgroup(ctrl, speed, sa.nblocks, [=](Ctrl* c, double sp) {
+    finish_workgroup(ctrl, G.slots, blockIdx.x, sa.nblocks, speed, [=](Ctrl* c, double sp) {
       c->last_speed = split_speed(c, nprev, dt, cfl_max, sp);
     });
   }
@@ -218,7 +215,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep_x(const GridDesc* __restrict__
       for (int k = 0; k < NA; ++k) ac[k] = apre[k];
     }
   }
-  close_sweep(ctrl, mode, sa, dt, G.cfl_max, own_face ? (double)smx / G.dx : 0.0);
+  close_sweep(G, mode, sa, dt, own_face ? (double)smx / G.dx : 0.0);
 }
 
 template <typename R, class P, bool KAHAN, int LIM>
@@ -389,7 +386,7 @@ __global__ __launch_bounds__(kLanes) void k_sweep_y(const GridDesc* __restrict__
       for (int k = 0; k < M; ++k) yW1[p][k] = yW2[p][k];
     }
   }
-  close_sweep(ctrl, mode, sa, dt, G.cfl_max, own ? (double)smy / G.dy : 0.0);
+  close_sweep(G, mode, sa, dt, own ? (double)smy / G.dy : 0.0);
 }
 
 // ---------------------------------------------------------------------------

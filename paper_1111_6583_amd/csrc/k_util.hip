@@ -92,15 +92,6 @@ __global__ void k_totals_final(const double* __restrict__ part, int m, int nb, d
   }
 }
 
-// Clear the Courant slot and counter of a grid (a kernel, so that it can sit
-// inside a captured graph).
-__global__ void k_ctrl_reset(Ctrl* c) {
-  if (threadIdx.x == 0) {
-    c->speed_bits = 0ull;
-    c->counter = 0u;
-  }
-}
-
 // ---------------------------------------------------------------------------
 static dim3 grid_for(size_t n) {
   size_t b = (n + 255) / 256;
@@ -181,11 +172,6 @@ hipError_t launch_totals(int fp32, const void* q, const void* c, int m, size_t n
     hipLaunchKernelGGL(k_totals_partial<double>, dim3(kTotBlocks), dim3(kTotThreads), 0, st,
                        (const double*)q, (const double*)c, m, n, part);
   hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(64), 0, st, part, m, kTotBlocks, cell, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_ctrl_reset(Ctrl* c, hipStream_t st) {
-  hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, st, c);
   return hipGetLastError();
 }
 

@@ -123,15 +123,23 @@ class Solver:
         return ms.value
 
     # -- tiling ------------------------------------------------------------
-    def set_tuning(self, seg_rows: int):
+    def set_tuning(self, seg_rows: int, seg_rows_x: int = 0):
+        """Rows per workgroup of the 2D kernels (the y sweeps of a split
+        step) and of the x sweeps of a split step (0: seg_rows)."""
         tn = ClawTuning()
         tn.seg_rows = int(seg_rows)
+        tn.seg_rows_x = int(seg_rows_x)
         check(self.lib.claw_set_tuning(self.h, C.byref(tn)), "claw_set_tuning")
 
     def get_tuning(self) -> int:
         tn = ClawTuning()
         check(self.lib.claw_get_tuning(self.h, C.byref(tn)), "claw_get_tuning")
         return tn.seg_rows
+
+    def get_tuning_x(self) -> int:
+        tn = ClawTuning()
+        check(self.lib.claw_get_tuning(self.h, C.byref(tn)), "claw_get_tuning")
+        return tn.seg_rows_x
 
     def autotune(self, reps: int = 3) -> int:
         tn = ClawTuning()

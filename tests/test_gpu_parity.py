@@ -811,6 +811,13 @@ def test_split_tiling_does_not_change_results(prec):
     outs = [replay(spec, q, [2e-3] * 10, seg_rows=sr) for sr in (4, 16, 100)]
     np.testing.assert_array_equal(outs[0], outs[1])
     np.testing.assert_array_equal(outs[0], outs[2])
+    for sr, sx in ((5, 1), (100, 7), (16, 100)):   # x sweeps tiled on their own
+        s = solver(spec, q)
+        s.set_tuning(sr, sx)
+        for _ in range(10):
+            s.step(2e-3)
+        np.testing.assert_array_equal(s.get_state(), outs[0])
+        s.close()
 
 
 @pytest.mark.parametrize("split", SPLITS)
