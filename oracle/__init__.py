@@ -35,7 +35,8 @@ _lock = threading.Lock()
 _lib = None
 
 SCHEMES = {"classic": 1, "sharpclaw": 2}
-SOLVERS = {"advection": 1, "sw_roe": 2, "euler_hlle": 3, "elastic_vc": 4, "euler_roe": 5}
+SOLVERS = {"advection": 1, "sw_roe": 2, "euler_hlle": 3, "elastic_vc": 4, "euler_roe": 5,
+           "psystem": 6}
 SOURCES = {"none": 0, "axisymmetric": 1}
 SPLITS = {"none": 0, "godunov": 1, "strang": 2}
 LIMITERS = {"none": 0, "minmod": 1, "mc": 2}
@@ -86,7 +87,7 @@ def _load():
                                C.c_double, C.c_long, dp, ip, C.c_long, lp, lp, dp]
     lib.or_riemann.argtypes = [cp, C.c_int, dp, dp, dp, dp, dp, dp, dp, dp]
     lib.or_transverse.argtypes = [cp, C.c_int, dp, dp, dp, dp, dp, dp, dp, dp]
-    lib.or_num_flux.argtypes = [cp, C.c_int, dp, dp, dp]
+    lib.or_num_flux.argtypes = [cp, C.c_int, dp, dp, dp, dp, dp]
     lib.or_source_step.argtypes = [cp, dp, C.c_double]
     lib.or_source_step.restype = C.c_int
     lib.or_num_flux.restype = C.c_double
@@ -269,14 +270,17 @@ def transverse(spec, d, ql, qr, asdq, aux_m=None, aux_c=None, aux_p=None):
     return bm[:m], bp[:m]
 
 
-def num_flux(spec, d, ql, qr):
+def num_flux(spec, d, ql, qr, auxl=None, auxr=None):
+    """SharpClaw interface flux and speed (aux: the two cells' materials)."""
     c = make_cfg(spec)
     lib = _load()
     m = lib.or_num_eqn(C.byref(c))
     ql = np.pad(np.asarray(ql, float), (0, 5 - m))
     qr = np.pad(np.asarray(qr, float), (0, 5 - m))
+    al = np.zeros(3) if auxl is None else np.pad(np.asarray(auxl, float), (0, 3 - len(auxl)))
+    ar = np.zeros(3) if auxr is None else np.pad(np.asarray(auxr, float), (0, 3 - len(auxr)))
     F = np.zeros(5)
-    s = lib.or_num_flux(C.byref(c), int(d), _ptr(ql), _ptr(qr), _ptr(F))
+    s = lib.or_num_flux(C.byref(c), int(d), _ptr(ql), _ptr(qr), _ptr(al), _ptr(ar), _ptr(F))
     return F[:m], s
 
 

@@ -72,7 +72,7 @@ struct OCfg {
 
 namespace {
 
-enum { S_ADV = 1, S_SW = 2, S_EULER = 3, S_ELASTIC = 4, S_EULER_ROE = 5 };
+enum { S_ADV = 1, S_SW = 2, S_EULER = 3, S_ELASTIC = 4, S_EULER_ROE = 5, S_PSYS = 6 };
 enum { BC_EXTRAP = 1, BC_PERIODIC = 2, BC_WALL = 3, BC_DIRICHLET = 4 };
 
 int num_eqn(const OCfg& c) {
@@ -82,6 +82,7 @@ int num_eqn(const OCfg& c) {
     case S_EULER: return c.ndim == 1 ? 3 : 4;
     case S_ELASTIC: return 5;
     case S_EULER_ROE: return (c.ndim == 1 ? 3 : 4) + (c.tracer ? 1 : 0);
+    case S_PSYS: return c.ndim == 1 ? 2 : 3;
   }
   return 0;
 }
@@ -92,10 +93,11 @@ int num_waves(const OCfg& c) {
     case S_EULER: return 2;
     case S_ELASTIC: return 4;
     case S_EULER_ROE: return (c.ndim == 1 ? 3 : 4) + (c.tracer ? 1 : 0);
+    case S_PSYS: return 2;
   }
   return 0;
 }
-int num_aux(const OCfg& c) { return c.solver == S_ELASTIC ? 3 : 0; }
+int num_aux(const OCfg& c) { return c.solver == S_ELASTIC ? 3 : (c.solver == S_PSYS ? 2 : 0); }
 
 double dx_of(const OCfg& c) { return (c.xhi - c.xlo) / c.nx; }
 double dy_of(const OCfg& c) { return c.ndim == 2 ? (c.yhi - c.ylo) / c.ny : 1.0; }
@@ -106,7 +108,8 @@ bool odd_under_reflection(const OCfg& c, int d, int k) {
   switch (c.solver) {
     case S_SW:
     case S_EULER:
-    case S_EULER_ROE: return k == 1 + d;             // normal momentum
+    case S_EULER_ROE:
+    case S_PSYS: return k == 1 + d;                  // normal momentum
     case S_ELASTIC: return k == 2 || k == 3 + d;      // shear stress and normal velocity
   }
   return false;
@@ -1170,19 +1173,63 @@ double flux_advection(const OCfg& c, int d, const double* ql, const double* qr, 
   return std::fabs(u);
 }
 
-double num_flux(const OCfg& c, int d, const double* ql, const double* qr, double* F) {
+// Nonlinear p-system with spatially varying coefficients (Section 7.4,
+// eq. p-system): q = (strain eps, x-momentum rho u, y-momentum rho v), aux =
+// (bulk modulus K, density rho) per cell, stress sigma(eps) = exp(K eps) - 1
+// (eq. nonlinear const relation up to its additive constant, which cancels
+// in every flux difference).  Flux normal to direction d: f = -(u_n, sigma
+// e_n) with u_n = (rho u_n) / rho.  Its Jacobian has speeds -c, 0, +c with
+// c = sqrt(sigma'(eps) / rho) = sqrt(K exp(K eps) / rho) and, for -c / +c,
+// eigenvectors (1, Z e_n) / (1, -Z e_n), Z = rho c (impedance).
+//
+// Interface flux (f-wave decomposition for a flux that varies in space: the
+// jump of the physical flux across the face, each side in its own material,
+// is split into a left-going f-wave on the left material's eigenvector and a
+// right-going one on the right material's):
+//   f_r - f_l = b1 (1, Z_l e_n) + b2 (1, -Z_r e_n),
+//   F = f_l + b1 (1, Z_l e_n)          (= f_r - b2 (1, -Z_r e_n)).
+// Speed for the Courant number: max(c_l, c_r).
+double flux_psystem(const OCfg& c, int d, const double* ql, const double* qr, const double* al,
+                    const double* ar, double* F) {
+  const int m = num_eqn(c), n = 1 + d;
+  const double Kl = al[0], rl = al[1], Kr = ar[0], rr = ar[1];
+  const double sl = std::expm1(Kl * ql[0]), sr = std::expm1(Kr * qr[0]);
+  const double cl = std::sqrt(Kl * std::exp(Kl * ql[0]) / rl);
+  const double cr = std::sqrt(Kr * std::exp(Kr * qr[0]) / rr);
+  const double Zl = rl * cl, Zr = rr * cr;
+  double fl[3] = {0.0, 0.0, 0.0}, fr[3] = {0.0, 0.0, 0.0};
+  fl[0] = -ql[n] / rl;
+  fl[n] = -sl;
+  fr[0] = -qr[n] / rr;
+  fr[n] = -sr;
+  const double d0 = fr[0] - fl[0], dn = fr[n] - fl[n];
+  const double b1 = (Zr * d0 + dn) / (Zl + Zr);
+  for (int k = 0; k < m; ++k) F[k] = fl[k];
+  F[0] += b1;
+  F[n] += b1 * Zl;
+  return std::max(cl, cr);
+}
+
+double num_flux(const OCfg& c, int d, const double* ql, const double* qr, const double* al,
+                const double* ar, double* F) {
   if (c.solver == S_EULER) return flux_hlle(c, d, ql, qr, F);
+  if (c.solver == S_PSYS) return flux_psystem(c, d, ql, qr, al, ar, F);
   return flux_advection(c, d, ql, qr, F);
 }
 
 // Semi-discrete operator L(Q) = -(F_{i+1/2}-F_{i-1/2})/dx - (G_{j+1/2}-G_{j-1/2})/dy.
 // Returns the largest |speed|/spacing over faces bounding interior cells.
-double sharpclaw_L(const OCfg& c, const double* qin, double* L) {
-  const int m = num_eqn(c), nx = c.nx, ny = c.ny;
+// A face flux sees the aux fields (material) of the two cells it separates.
+double sharpclaw_L(const OCfg& c, const double* qin, const double* auxin, double* L) {
+  const int m = num_eqn(c), nx = c.nx, ny = c.ny, na = num_aux(c);
   const double dx = dx_of(c), dy = dy_of(c);
   const int r = weno_r_of(c), w = 2 * r - 1;
-  Field Q;
+  Field Q, A;
   load_field(c, Q, qin, m, r, false);
+  load_field(c, A, auxin, na, r, true);
+  auto aux_of = [&](int j, int i, double* a) {
+    for (int k = 0; k < na; ++k) a[k] = A.at(k, j, i);
+  };
   std::fill(L, L + (size_t)m * nx * ny, 0.0);
   double smax = 0.0;
   // x direction: one row at a time
@@ -1198,12 +1245,14 @@ double sharpclaw_L(const OCfg& c, const double* qin, double* L) {
       }
     std::vector<double> Fx((size_t)(nx + 1) * m);
     for (int f = 0; f <= nx; ++f) {
-      double ql[5], qr[5];
+      double ql[5], qr[5], al[3] = {0, 0, 0}, ar[3] = {0, 0, 0};
       for (int k = 0; k < m; ++k) {
         ql[k] = eL[(size_t)f * m + k];         // right edge of cell f-1
         qr[k] = eR[(size_t)(f + 1) * m + k];   // left edge of cell f
       }
-      const double sp = num_flux(c, 0, ql, qr, &Fx[(size_t)f * m]);
+      aux_of(j, f - 1, al);
+      aux_of(j, f, ar);
+      const double sp = num_flux(c, 0, ql, qr, al, ar, &Fx[(size_t)f * m]);
       smax = std::max(smax, sp / dx);
     }
     for (int i = 0; i < nx; ++i)
@@ -1222,12 +1271,14 @@ double sharpclaw_L(const OCfg& c, const double* qin, double* L) {
         }
       std::vector<double> Gy((size_t)(ny + 1) * m);
       for (int g = 0; g <= ny; ++g) {
-        double ql[5], qr[5];
+        double ql[5], qr[5], al[3] = {0, 0, 0}, ar[3] = {0, 0, 0};
         for (int k = 0; k < m; ++k) {
           ql[k] = eL[(size_t)g * m + k];
           qr[k] = eR[(size_t)(g + 1) * m + k];
         }
-        const double sp = num_flux(c, 1, ql, qr, &Gy[(size_t)g * m]);
+        aux_of(g - 1, i, al);
+        aux_of(g, i, ar);
+        const double sp = num_flux(c, 1, ql, qr, al, ar, &Gy[(size_t)g * m]);
         smax = std::max(smax, sp / dy);
       }
       for (int j = 0; j < ny; ++j)
@@ -1280,10 +1331,12 @@ double ssp_step(int integrator, Op&& Lop, size_t N, const double* qin, double* q
   return smax;
 }
 
-double sharpclaw_step(const OCfg& c, const double* qin, double* qout, double dt) {
+double sharpclaw_step(const OCfg& c, const double* qin, const double* aux, double* qout,
+                      double dt) {
   const size_t N = (size_t)num_eqn(c) * c.nx * c.ny;
-  return ssp_step(c.integrator, [&](const double* q, double* L) { return sharpclaw_L(c, q, L); },
-                  N, qin, qout, dt);
+  return ssp_step(c.integrator,
+                  [&](const double* q, double* L) { return sharpclaw_L(c, q, aux, L); }, N, qin,
+                  qout, dt);
 }
 
 // Geometric source of the axisymmetric Euler equations (eq. euler-rz with the
@@ -1326,7 +1379,7 @@ void source_step(const OCfg& c, double* q, double dt) {
 bool has_source(const OCfg& c) { return c.source == 1 && c.solver == S_EULER_ROE && c.ndim == 2; }
 
 double one_step(const OCfg& c, const double* qin, const double* aux, double* qout, double dt) {
-  if (c.scheme == 2) return sharpclaw_step(c, qin, qout, dt);
+  if (c.scheme == 2) return sharpclaw_step(c, qin, aux, qout, dt);
   if (c.ndim == 1) return classic_1d(c, qin, qout, dt);
   const double s = c.split ? classic_2d_split(c, qin, aux, qout, dt) : classic_2d(c, qin, aux, qout, dt);
   if (has_source(c)) source_step(c, qout, dt);
@@ -1365,6 +1418,12 @@ double max_cell_speed(const OCfg& c, const double* q, const double* aux) {
       case S_ELASTIC: {
         const double cp = std::sqrt((aux[N + n] + 2.0 * aux[2 * N + n]) / aux[n]);
         s = std::max(cp / dx, cp / dy);
+      } break;
+      case S_PSYS: {
+        const double K = aux[n], rho = aux[N + n];
+        const double cs = std::sqrt(K * std::exp(K * q[n]) / rho);
+        s = cs / dx;
+        if (c.ndim == 2) s = std::max(s, cs / dy);
       } break;
     }
     best = std::max(best, s);
@@ -1493,8 +1552,10 @@ int or_transverse(const OCfg* c, int d, const double* ql, const double* qr, cons
   return 0;
 }
 
-double or_num_flux(const OCfg* c, int d, const double* ql, const double* qr, double* F) {
-  return num_flux(*c, d, ql, qr, F);
+double or_num_flux(const OCfg* c, int d, const double* ql, const double* qr, const double* al,
+                   const double* ar, double* F) {
+  const double z[3] = {0.0, 0.0, 0.0};
+  return num_flux(*c, d, ql, qr, al ? al : z, ar ? ar : z, F);
 }
 
 void or_weno5(const double* v, double eps, double* qL, double* qR) { weno5(v, eps, qL, qR); }

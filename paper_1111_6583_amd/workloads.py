@@ -323,3 +323,56 @@ def random_smooth_euler(n, seed=0):
     p = 1.0 + 0.1 * np.sin(2 * np.pi * (X - Y) + ph[3])
     q = np.array(euler_conserved(rho, u, v, p))
     return spec, q
+
+
+# ---------------------------------------------------------------------------
+# Nonlinear p-system in a checkerboard medium (the paper's cylindrical
+# solitary-wave problem): positive quadrant [0, P]^2 in units of the medium
+# period, `cpp` cells per period (the paper: 240 cells, P = 200).  Squares of
+# (K, rho) = (1, 1) where (x - floor(x) - 1/2)(y - floor(y) - 1/2) < 0, else
+# (5, 5), at the cell centre.  Initial stress a Gaussian of amplitude 5 and
+# variance 5 in x and y centred at the origin, zero velocity; the strain is
+# the one whose stress sigma = exp(K eps) - 1 equals it.  Reflecting walls
+# at x = 0 and y = 0, zero-order extrapolation at the far sides.  SharpClaw,
+# WENO5, SSPRK(10,4).  Returns (spec, q, aux).
+# ---------------------------------------------------------------------------
+def psystem_material(x, y):
+    """(K, rho) of the checkerboard at points (x, y)."""
+    s = (x - np.floor(x) - 0.5) * (y - np.floor(y) - 0.5)
+    K = np.where(s < 0, 1.0, 5.0)
+    return K, K.copy()
+
+
+def psystem_checkerboard(cpp=240, periods=200, ny_periods=None, amplitude=5.0, variance=5.0,
+                         **kw):
+    py = periods if ny_periods is None else ny_periods
+    n, m = cpp * periods, cpp * py
+    spec = _base(2, (n, m), (0.0, 0.0), (float(periods), float(py)), "psystem",
+                 scheme="sharpclaw", limiter="none", transverse=0,
+                 bc_lower=("wall", "wall"), bc_upper=("extrap", "extrap"),
+                 time_integrator="ssp104", weno_order=5, cfl_desired=2.45, cfl_max=2.5)
+    spec.update(kw)
+    x, y = centers(spec)
+    X, Y = np.meshgrid(x, y)
+    K, rho = psystem_material(X, Y)
+    sig = amplitude * np.exp(-(X * X + Y * Y) / (2.0 * variance))
+    q = np.zeros((3, m, n))
+    q[0] = np.log1p(sig) / K
+    return spec, q, np.array([K, rho])
+
+
+def psystem_layered_1d(n, lo=0.0, hi=1.0, interfaces=(), materials=((1.0, 1.0),), **kw):
+    """1D p-system on [lo, hi] with piecewise-constant (K, rho): material
+    k between interfaces[k-1] and interfaces[k] (cell centres).  Returns
+    (spec, aux); the caller sets q (strain, momentum)."""
+    spec = _base(1, (n,), (lo,), (hi,), "psystem", scheme="sharpclaw", limiter="none",
+                 transverse=0, time_integrator="ssp104", weno_order=5, cfl_desired=2.45,
+                 cfl_max=2.5)
+    spec.update(kw)
+    x, _ = centers(spec)
+    idx = np.searchsorted(np.asarray(interfaces, float), x)
+    mat = np.asarray(materials, float)[idx]
+    aux = np.zeros((2, 1, n))
+    aux[0, 0] = mat[:, 0]
+    aux[1, 0] = mat[:, 1]
+    return spec, aux

@@ -1151,3 +1151,133 @@ def test_split_courant_reading_stops_at_the_first_unstable_sweep():
     qn[0, 7, 3] = np.nan
     _, sp = oracle.step(spec, qn, 1e-3)
     assert np.isnan(sp)
+
+
+# --------------------------------------------------------------------------
+# P23: nonlinear p-system with spatially varying coefficients (SharpClaw)
+# --------------------------------------------------------------------------
+def psys_spec(ndim=1, **kw):
+    if ndim == 1:
+        s, _ = W.psystem_layered_1d(8)
+    else:
+        s, _, _ = W.psystem_checkerboard(4, 2)
+    s.update(kw)
+    return s
+
+
+def psys_phys(q, a, d):
+    """Physical flux, speed and impedance of one cell (written out here)."""
+    K, rho = a
+    n = 1 + d
+    f = np.zeros(len(q))
+    f[0] = -q[n] / rho
+    f[n] = -math.expm1(K * q[0])
+    c = math.sqrt(K * math.exp(K * q[0]) / rho)
+    return f, c, rho * c
+
+
+@pytest.mark.parametrize("ndim,d", [(1, 0), (2, 0), (2, 1)])
+def test_psystem_interface_flux_is_an_fwave_split(ndim, d):
+    """F = f_l + (left-going f-wave on the left material's eigenvector)
+    = f_r - (right-going f-wave on the right material's eigenvector); the
+    transverse momentum has no flux; equal states and materials give f."""
+    spec = psys_spec(ndim)
+    rng = np.random.default_rng(31)
+    m = 2 if ndim == 1 else 3
+    for _ in range(20):
+        ql = rng.uniform(-0.3, 0.3, m)
+        qr = rng.uniform(-0.3, 0.3, m)
+        al = rng.uniform(0.5, 5.0, 2)
+        ar = rng.uniform(0.5, 5.0, 2)
+        F, s = oracle.num_flux(spec, d, ql, qr, al, ar)
+        fl, cl, Zl = psys_phys(ql, al, d)
+        fr, cr, Zr = psys_phys(qr, ar, d)
+        n = 1 + d
+        assert s == pytest.approx(max(cl, cr), rel=1e-14)
+        wl, wr = F - fl, fr - F
+        assert wl[n] == pytest.approx(Zl * wl[0], rel=1e-12, abs=1e-14)
+        assert wr[n] == pytest.approx(-Zr * wr[0], rel=1e-12, abs=1e-14)
+        if ndim == 2:
+            assert F[3 - n] == 0.0
+        Fs, _ = oracle.num_flux(spec, d, ql, ql, al, al)
+        np.testing.assert_allclose(Fs, fl, rtol=0, atol=1e-15)
+
+
+def _psys_pulse_run(n, t_end, width=0.05, amp=1e-5):
+    """Right-going linear pulse from material 1 (K = rho = 1, Z = 1) into
+    material 2 (K = rho = 5, Z = 5) at x = 0.5; both have sound speed 1."""
+    spec, aux = W.psystem_layered_1d(n, interfaces=(0.5,), materials=((1.0, 1.0), (5.0, 5.0)))
+    x = (np.arange(n) + 0.5) / n
+    a = amp * np.exp(-((x - 0.25) / width) ** 2)
+    q = np.zeros((2, 1, n))
+    q[0, 0] = a              # strain of the right-going eigenvector (1, -Z)
+    q[1, 0] = -1.0 * a
+    qo, info = oracle.advance(spec, q, t_end, aux=aux)
+    assert info["rc"] == 0
+    sig = np.expm1(aux[0, 0] * qo[0, 0])
+    return x, sig
+
+
+def test_psystem_interface_reflection_and_transmission():
+    """Linear regime: at an impedance jump Z1 -> Z2 the stress pulse is
+    reflected with (Z2 - Z1)/(Z1 + Z2) = 2/3 and transmitted with
+    2 Z2/(Z1 + Z2) = 5/3 of its amplitude."""
+    amp = 1e-5
+    x, sig = _psys_pulse_run(400, 0.5, amp=amp)
+    refl = sig[x < 0.5]
+    trans = sig[x > 0.5]
+    assert np.max(refl) / amp == pytest.approx(2.0 / 3.0, rel=5e-3)
+    assert np.max(trans) / amp == pytest.approx(5.0 / 3.0, rel=5e-3)
+    # the pulses sit where the sound speed 1 puts them
+    assert abs(x[x < 0.5][np.argmax(refl)] - 0.25) < 2.0 / 400
+    assert abs(x[x > 0.5][np.argmax(trans)] - 0.75) < 2.0 / 400
+
+
+def test_psystem_conservation_periodic_checkerboard():
+    spec, q, aux = W.psystem_checkerboard(8, 3, bc_lower=("periodic", "periodic"),
+                                          bc_upper=("periodic", "periodic"))
+    q[1] = 0.3 * np.sin(2 * np.pi * np.arange(24) / 24.0)[None, :]
+    t0 = oracle.totals(spec, q)
+    qf, info = oracle.advance(spec, q, 1.0, aux=aux)
+    assert info["accepted"] >= 5
+    np.testing.assert_allclose(oracle.totals(spec, qf), t0, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("integ", ["ssp104", "ssp33"])
+def test_psystem_checkerboard_xy_symmetry(integ):
+    """The checkerboard, the pulse and the boundary conditions are symmetric
+    under x <-> y, so strain(x, y) = strain(y, x) and the momenta swap."""
+    spec, q, aux = W.psystem_checkerboard(8, 3, time_integrator=integ,
+                                          cfl_desired=2.45 if integ == "ssp104" else 0.5,
+                                          cfl_max=2.5 if integ == "ssp104" else 0.6)
+    qf, info = oracle.advance(spec, q, 1.5, aux=aux)
+    assert info["accepted"] >= 5
+    sc = np.max(np.abs(qf), axis=(1, 2))
+    np.testing.assert_allclose(qf[0], qf[0].T, rtol=0, atol=1e-14 * sc[0])
+    np.testing.assert_allclose(qf[1], qf[2].T, rtol=0, atol=1e-14 * sc[1])
+    assert sc[1] > 0.1
+
+
+def test_psystem_smooth_nonlinear_order():
+    """Homogeneous medium, smooth periodic nonlinear data: WENO5 + SSPRK(10,4)
+    at a fixed Courant number converges at fourth order or better."""
+    errs = []
+    T = 0.3
+    for n in (32, 64, 128):
+        spec, aux = W.psystem_layered_1d(n, bc_lower=("periodic",), bc_upper=("periodic",))
+        h = 1.0 / n
+        x = (np.arange(n) + 0.5) * h
+        # cell averages of a smooth strain / momentum
+        avg = lambda f, k: (f(x + h / 2, k) - f(x - h / 2, k)) / h
+        F = lambda xx, k: -np.cos(2 * np.pi * k * xx) / (2 * np.pi * k)
+        q = np.zeros((2, 1, n))
+        q[0, 0] = 0.1 * avg(F, 1)
+        q[1, 0] = 0.05 * avg(F, 2)
+        nsteps = int(round(T / (1.0 * h)))
+        dt = T / nsteps
+        for _ in range(nsteps):
+            q, _ = oracle.step(spec, q, dt, aux=aux)
+        errs.append(q)
+    d1 = np.sum(np.abs(errs[0] - 0.5 * (errs[1][..., 0::2] + errs[1][..., 1::2]))) / 32
+    d2 = np.sum(np.abs(errs[1] - 0.5 * (errs[2][..., 0::2] + errs[2][..., 1::2]))) / 64
+    assert math.log2(d1 / d2) > 3.8, (d1, d2)
