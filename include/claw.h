@@ -82,10 +82,14 @@ enum claw_riemann {
                              SharpClaw only */
   CLAW_RP_ELASTIC_VC = 4, /* 2D linear elasticity, variable coefficients, m = 5,
                              q = (s11, s22, s12, u, v), aux = (rho, lambda, mu); classic, 2D only */
-  CLAW_RP_EULER_ROE = 5   /* Euler, Roe solver (two acoustic, entropy and - in 2D - shear waves)
+  CLAW_RP_EULER_ROE = 5,  /* Euler, Roe solver (two acoustic, entropy and - in 2D - shear waves)
                              with its transverse solver, problem_data = (gamma); m = 3 (1D) or
                              4 (2D), plus one with a tracer; optional Harten-Hyman entropy fix;
                              classic only */
+  CLAW_RP_PSYSTEM = 6     /* nonlinear p-system in a varying medium (Section 7.4, eq. p-system):
+                             q = (strain, rho u[, rho v]), m = 2 (1D) or 3 (2D); aux = (K, rho)
+                             per cell; stress exp(K strain) - 1; f-wave interface flux (each side
+                             in its own material); SharpClaw only */
 };
 enum claw_source {
   CLAW_SOURCE_NONE = 0,
@@ -190,7 +194,7 @@ int claw_create(const claw_config* cfg, void* d_ws, size_t ws_bytes, void* hip_s
  * memory.  Resets the compensation terms (FP32 mode).  Does not touch the clock. */
 int claw_set_state(claw_t h, const double* q, int on_device);
 
-/* Copy the aux fields in (elasticity: rho, lambda, mu), float64[na][ny][nx]. */
+/* Copy the aux fields in (elasticity: rho, lambda, mu; p-system: K, rho), float64[na][ny][nx]. */
 int claw_set_aux(claw_t h, const double* aux, int on_device);
 
 /* Copy the state out as float64[m][ny][nx] (FP32 mode: value minus

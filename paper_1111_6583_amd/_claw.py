@@ -14,7 +14,8 @@ CLAW_OK = 0
 ERRORS = {-1: "CLAW_E_INVAL", -2: "CLAW_E_NOMEM", -3: "CLAW_E_DEVICE", -4: "CLAW_E_REJECTED",
           -5: "CLAW_E_NONPHYSICAL", -6: "CLAW_E_BUDGET", -7: "CLAW_E_STATE", -8: "CLAW_E_MAXSTEPS"}
 SCHEMES = {"classic": 1, "sharpclaw": 2}
-SOLVERS = {"advection": 1, "sw_roe": 2, "euler_hlle": 3, "elastic_vc": 4, "euler_roe": 5}
+SOLVERS = {"advection": 1, "sw_roe": 2, "euler_hlle": 3, "elastic_vc": 4, "euler_roe": 5,
+           "psystem": 6}
 SOURCES = {"none": 0, "axisymmetric": 1}
 SPLITS = {"none": 0, "godunov": 1, "strang": 2}
 LIMITERS = {"none": 0, "minmod": 1, "mc": 2}

@@ -68,14 +68,18 @@ int num_eqn_of(const claw_config& c) {
     case CLAW_RP_EULER_HLLE: return c.ndim == 1 ? 3 : 4;
     case CLAW_RP_ELASTIC_VC: return 5;
     case CLAW_RP_EULER_ROE: return (c.ndim == 1 ? 3 : 4) + (c.tracer ? 1 : 0);
+    case CLAW_RP_PSYSTEM: return c.ndim == 1 ? 2 : 3;
   }
   return 0;
 }
 // Kernel variant of the Riemann solver (the tracer is a separate instance).
 int kernel_riemann(const claw_config& c) {
+  if (c.riemann == CLAW_RP_PSYSTEM) return 7;
   return c.riemann == CLAW_RP_EULER_ROE && c.tracer ? 6 : c.riemann;
 }
-int num_aux_of(const claw_config& c) { return c.riemann == CLAW_RP_ELASTIC_VC ? 3 : 0; }
+int num_aux_of(const claw_config& c) {
+  return c.riemann == CLAW_RP_ELASTIC_VC ? 3 : (c.riemann == CLAW_RP_PSYSTEM ? 2 : 0);
+}
 
 bool valid_bc(int b) { return b >= CLAW_BC_EXTRAP && b <= CLAW_BC_DIRICHLET; }
 
@@ -106,7 +110,9 @@ int validate(const claw_config* c) {
       return CLAW_E_INVAL;
     if (c->dimensional_split != CLAW_SPLIT_NONE && c->ndim != 2) return CLAW_E_INVAL;
   } else if (c->scheme == CLAW_SHARPCLAW) {
-    if (c->riemann != CLAW_RP_ADVECTION && c->riemann != CLAW_RP_EULER_HLLE) return CLAW_E_INVAL;
+    if (c->riemann != CLAW_RP_ADVECTION && c->riemann != CLAW_RP_EULER_HLLE &&
+        c->riemann != CLAW_RP_PSYSTEM)
+      return CLAW_E_INVAL;
     if (c->time_integrator != 0 && c->time_integrator != CLAW_SSP33 &&
         c->time_integrator != CLAW_SSP104)
       return CLAW_E_INVAL;
@@ -346,7 +352,7 @@ int launch_sharp_stages(claw_t h, int from, int to, int mode, double dt) {
   int kind[10];
   const int n = sharp_plan(h, st, kind);
   for (int s = from; s < std::min(to, n); ++s)
-    HIPCHK(launch_sharp_stage(h->cfg.ndim, h->cfg.riemann, h->fp32, h->hg.weno_r, kind[s],
+    HIPCHK(launch_sharp_stage(h->cfg.ndim, h->kr, h->fp32, h->hg.weno_r, kind[s],
                               h->hg.nblocks, h->stream, h->d_grid, mode, dt, st[s]));
   return CLAW_OK;
 }

@@ -97,6 +97,15 @@ __device__ __forceinline__ void weno_edges(const R (&v)[2 * RH - 1], R eps, R& q
   }
 }
 
+// Interface flux of a face whose two cells have aux fields al / ar (used by
+// policies with a spatially varying flux).
+template <int D, class P, typename R>
+__device__ __forceinline__ R face_flux(const P& phys, const R* ql, const R* qr, const R* al,
+                                       const R* ar, R* F) {
+  if constexpr (P::NA > 0) return phys.template flux<D>(ql, qr, al, ar, F);
+  else return phys.template flux<D>(ql, qr, F);
+}
+
 // Stage output for one cell.  S: stage input value, L: operator value,
 // pp: pointwise P1, pq: Q^n (FINAL, FP32), pc: compensation (FINAL, FP32).
 template <typename R, class P, int KIND, bool KAHAN>
@@ -200,6 +209,17 @@ __global__ __launch_bounds__(kLanes) void k_sharp2d(const GridDesc* __restrict__
   const R rdx = (R)(1.0 / G.dx), rdy = (R)(1.0 / G.dy);
   const P phys(G);
   R smx = R(0), smy = R(0);
+  // aux fields (material) of window rows c-1, c (the centre) and c+1 (read a
+  // row ahead)
+  constexpr int NA = P::NA > 0 ? P::NA : 1;
+  const gconst<R> aux = as_gconst<R>(G.aux);
+  R aP[NA], aC[NA], aN[NA];
+#pragma unroll
+  for (int k = 0; k < NA; ++k) aP[k] = aC[k] = aN[k] = R(0);
+  if constexpr (P::NA > 0) {
+    load_aux<R, P>(aC, aux, plane, nx, mx, map_axis(j0 - 2 * RH, ny, bcy0, bcy1, H));
+    load_aux<R, P>(aN, aux, plane, nx, mx, map_axis(j0 - 2 * RH + 1, ny, bcy0, bcy1, H));
+  }
 
   R w[NW][M];          // rows r-NW+1 .. r
   R qyl_prev[M], g_lo[M];
@@ -242,6 +262,11 @@ __global__ __launch_bounds__(kLanes) void k_sharp2d(const GridDesc* __restrict__
       mynext = map_axis(r + 1, ny, bcy0, bcy1, H);
       load_raw<R, M>(pre, S, plane, nx, mx, mynext);
     }
+    if constexpr (P::NA > 0) {
+#pragma unroll
+      for (int k = 0; k < NA; ++k) { aP[k] = aC[k]; aC[k] = aN[k]; }
+      load_aux<R, P>(aN, aux, plane, nx, mx, map_axis(r - RH + 2, ny, bcy0, bcy1, H));
+    }
     const int fn = r + 1 - RH;   // row finalised next iteration
     if (kPoint && fn >= j0 && fn < j1) {
       const size_t idx = (size_t)fn * nx + ic;
@@ -269,7 +294,7 @@ __global__ __launch_bounds__(kLanes) void k_sharp2d(const GridDesc* __restrict__
       if (r >= j0 + RH - 1) {
         // y-face flux at c-1/2
         R g_up[M];
-        const R sy = phys.template flux<1>(qyl_prev, qyr, g_up);
+        const R sy = face_flux<1>(phys, qyl_prev, qyr, aP, aC, g_up);
         smy = max_nan(smy, sy);
         if (r >= j0 + RH) {
           // row f = c-1 (window row RH-2) is complete: x edge values, x-face fluxes
@@ -285,10 +310,12 @@ __global__ __launch_bounds__(kLanes) void k_sharp2d(const GridDesc* __restrict__
             }
             weno_edges<RH>(row, eps, xl[k], xr[k]);
           }
-          R ql[M], F[M];
+          R ql[M], F[M], al[NA];
 #pragma unroll
           for (int k = 0; k < M; ++k) ql[k] = shfl_prev(xl[k]);
-          const R sx = phys.template flux<0>(ql, xr, F);
+#pragma unroll
+          for (int k = 0; k < NA; ++k) al[k] = P::NA > 0 ? shfl_prev(aP[k]) : R(0);
+          const R sx = face_flux<0>(phys, ql, xr, al, aP, F);
           if (own_face) smx = max_nan(smx, sx);
 #pragma unroll
           for (int k = 0; k < M; ++k) {
@@ -341,6 +368,11 @@ __global__ __launch_bounds__(kLanes) void k_sharp1d(const GridDesc* __restrict__
   const P phys(G);
   R c[M], xl[M], xr[M];
   load_state<R, P>(c, S, (size_t)nx, nx, mx, my, edge_states<R, M>(G, mx));
+  constexpr int NA = P::NA > 0 ? P::NA : 1;
+  R ac[NA], al[NA];
+  load_aux<R, P>(ac, as_gconst<R>(G.aux), (size_t)nx, nx, mx, my);
+#pragma unroll
+  for (int k = 0; k < NA; ++k) al[k] = P::NA > 0 ? shfl_prev(ac[k]) : R(0);
 #pragma unroll
   for (int k = 0; k < M; ++k) {
     R row[NW];
@@ -355,7 +387,7 @@ __global__ __launch_bounds__(kLanes) void k_sharp1d(const GridDesc* __restrict__
   R ql[M], F[M], Lv[M];
 #pragma unroll
   for (int k = 0; k < M; ++k) ql[k] = shfl_prev(xl[k]);
-  const R sx = phys.template flux<0>(ql, xr, F);
+  const R sx = face_flux<0>(phys, ql, xr, al, ac, F);
 #pragma unroll
   for (int k = 0; k < M; ++k) Lv[k] = -(shfl_next(F[k]) - F[k]) * rdx;
   R pp[M], pq[M], pc[M];
@@ -391,6 +423,10 @@ static hipError_t sharp_t(int riemann, dim3 grid, hipStream_t st, const GridDesc
         hipLaunchKernelGGL((k_sharp2d<R, EulerHLLE<R, 2>, RH, KIND, K>), grid, dim3(kLanes), 0, st,
                            g, mode, dt, sa);
         break;
+      case 7:
+        hipLaunchKernelGGL((k_sharp2d<R, PSystem<R, 2>, RH, KIND, K>), grid, dim3(kLanes), 0, st,
+                           g, mode, dt, sa);
+        break;
       default: return hipErrorInvalidValue;
     }
   } else {
@@ -401,6 +437,10 @@ static hipError_t sharp_t(int riemann, dim3 grid, hipStream_t st, const GridDesc
         break;
       case 3:
         hipLaunchKernelGGL((k_sharp1d<R, EulerHLLE<R, 1>, RH, KIND, K>), grid, dim3(kLanes), 0, st,
+                           g, mode, dt, sa);
+        break;
+      case 7:
+        hipLaunchKernelGGL((k_sharp1d<R, PSystem<R, 1>, RH, KIND, K>), grid, dim3(kLanes), 0, st,
                            g, mode, dt, sa);
         break;
       default: return hipErrorInvalidValue;

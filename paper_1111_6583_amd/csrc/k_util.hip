@@ -47,8 +47,7 @@ __global__ void k_cell_speed(const GridDesc* __restrict__ grids, int src,
     R v[P::M], a[kMaxAux];
 #pragma unroll
     for (int k = 0; k < P::M; ++k) v[k] = q[k * n + t];
-    if (aux)
-      for (int k = 0; k < kMaxAux; ++k) a[k] = aux[k * n + t];
+    for (int k = 0; k < P::NA; ++k) a[k] = aux[k * n + t];
     best = fmax(best, phys.cell_speed(v, a, rdx, rdy));
   }
   best = wave_max(best);
@@ -140,6 +139,7 @@ static hipError_t cell_speed_t(int ndim, int riemann, const GridDesc* g, int src
       case 4: hipLaunchKernelGGL((k_cell_speed<R, Elastic<R>>), grid, blk, 0, st, g, src, out); break;
       case 5: hipLaunchKernelGGL((k_cell_speed<R, EulerRoe<R, 2, false>>), grid, blk, 0, st, g, src, out); break;
       case 6: hipLaunchKernelGGL((k_cell_speed<R, EulerRoe<R, 2, true>>), grid, blk, 0, st, g, src, out); break;
+      case 7: hipLaunchKernelGGL((k_cell_speed<R, PSystem<R, 2>>), grid, blk, 0, st, g, src, out); break;
       default: return hipErrorInvalidValue;
     }
   } else {
@@ -149,6 +149,7 @@ static hipError_t cell_speed_t(int ndim, int riemann, const GridDesc* g, int src
       case 3: hipLaunchKernelGGL((k_cell_speed<R, EulerHLLE<R, 1>>), grid, blk, 0, st, g, src, out); break;
       case 5: hipLaunchKernelGGL((k_cell_speed<R, EulerRoe<R, 1, false>>), grid, blk, 0, st, g, src, out); break;
       case 6: hipLaunchKernelGGL((k_cell_speed<R, EulerRoe<R, 1, true>>), grid, blk, 0, st, g, src, out); break;
+      case 7: hipLaunchKernelGGL((k_cell_speed<R, PSystem<R, 1>>), grid, blk, 0, st, g, src, out); break;
       default: return hipErrorInvalidValue;
     }
   }

@@ -24,8 +24,10 @@
 //   cell_speed(q, a, rdx, rdy)     largest characteristic speed/spacing of a
 //                                  cell (a-priori first step)
 //
-// SharpClaw policies provide flux<D>(ql, qr, F) -> max |speed| (Section 2.1:
-// normal Riemann problems only).
+// SharpClaw policies provide M, NA, odd(d, k) and flux<D>(ql, qr, F) ->
+// max |speed| (Section 2.1: normal Riemann problems only); with NA > 0 the
+// flux is flux<D>(ql, qr, al, ar, F), al / ar the aux fields (material) of
+// the two cells the face separates.
 #pragma once
 
 #include "dev_common.h"
@@ -661,7 +663,7 @@ struct EulerRoe {
 // Upwind flux for scalar advection.
 template <typename R, int NDIM>
 struct AdvectionFlux {
-  static constexpr int M = 1;
+  static constexpr int M = 1, NA = 0;
   R u, v;
   __device__ explicit AdvectionFlux(const GridDesc& G) : u((R)G.pd[0]), v((R)G.pd[1]) {}
   static constexpr bool odd(int, int) { return false; }
@@ -682,7 +684,7 @@ struct AdvectionFlux {
 // q = (rho, rho u, E) in 1D, (rho, rho u, rho v, E) in 2D.
 template <typename R, int NDIM>
 struct EulerHLLE {
-  static constexpr int M = NDIM == 1 ? 3 : 4;
+  static constexpr int M = NDIM == 1 ? 3 : 4, NA = 0;
   R gamma, gm1;
   __device__ explicit EulerHLLE(const GridDesc& G) : gamma((R)G.pd[0]), gm1((R)G.pd[0] - R(1)) {}
   static constexpr bool odd(int d, int k) { return k == 1 + d; }
@@ -746,6 +748,52 @@ struct EulerHLLE {
     double s = (fabs(u) + c) * rdx;
     if (NDIM == 2) s = fmax(s, (fabs(v) + c) * rdy);
     return s;
+  }
+};
+
+// Nonlinear p-system with spatially varying coefficients (Section 7.4,
+// eq. p-system), q = (strain eps, rho u[, rho v]), aux = (K, rho) per cell,
+// stress sigma = exp(K eps) - 1.  Interface flux from the f-wave split of
+// the flux jump (left-going wave on the left material's eigenvector
+// (1, Z_l e_n), right-going on the right's (1, -Z_r e_n), Z = rho c,
+// c = sqrt(K exp(K eps) / rho)), written in its symmetric closed form:
+//   F_0 = -(Z_l u_l + Z_r u_r + sigma_r - sigma_l) / (Z_l + Z_r)
+//   F_n = -(Z_r sigma_l + Z_l sigma_r + Z_l Z_r (u_r - u_l)) / (Z_l + Z_r)
+// (the interface velocity and stress of the linearised impedance problem),
+// the transverse momentum's flux 0.  Speed max(c_l, c_r).
+template <typename R, int NDIM>
+struct PSystem {
+  static constexpr int M = NDIM == 1 ? 2 : 3, NA = 2;
+  __device__ explicit PSystem(const GridDesc&) {}
+  static constexpr bool odd(int d, int k) { return k == 1 + d; }
+
+  __device__ __forceinline__ static R em1(R x) {
+    if constexpr (sizeof(R) == 8) return expm1(x);
+    else return expm1f(x);
+  }
+
+  template <int D>
+  __device__ __forceinline__ R flux(const R* ql, const R* qr, const R* al, const R* ar,
+                                    R* F) const {
+    constexpr int N = 1 + D;
+    const R Kl = al[0], rl = al[1], Kr = ar[0], rr = ar[1];
+    const R sl = em1(Kl * ql[0]), sr = em1(Kr * qr[0]);
+    // Z = rho c = sqrt(K exp(K eps) rho), c = Z / rho
+    const R irl = frcp(rl), irr = frcp(rr);
+    const R Zl = fsqrt(Kl * (sl + R(1)) * rl), Zr = fsqrt(Kr * (sr + R(1)) * rr);
+    const R ul = ql[N] * irl, ur = qr[N] * irr;
+    const R iz = frcp(Zl + Zr);
+    F[0] = -(Zl * ul + Zr * ur + (sr - sl)) * iz;
+    F[N] = -(Zr * sl + Zl * sr + Zl * Zr * (ur - ul)) * iz;
+    if constexpr (NDIM == 2) F[3 - N] = R(0);
+    return rmax(Zl * irl, Zr * irr);
+  }
+
+  __device__ __forceinline__ double cell_speed(const R* q, const R* a, double rdx,
+                                               double rdy) const {
+    const double K = a[0], rho = a[1];
+    const double c = sqrt(K * exp(K * (double)q[0]) / rho);
+    return NDIM == 2 ? fmax(c * rdx, c * rdy) : c * rdx;
   }
 };
 

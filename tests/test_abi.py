@@ -135,3 +135,18 @@ def test_dimensional_split_options():
     # every classic 2D solver splits, with or without the axisymmetric source
     for spec in (W.layered_elastic(64)[0], W.shock_bubble_axisym(64, 16)[0]):
         assert _bytes(dict(spec, dimensional_split="strang"))[0] > _bytes(spec)[0]
+
+
+def test_psystem_options():
+    spec, q, aux = W.psystem_checkerboard(8, 4)
+    n, m = _bytes(spec)
+    assert m == 3 and q.shape == (3, 32, 32) and aux.shape == (2, 32, 32)
+    lib = _claw.load_library()
+    c = _claw.make_config(spec)
+    assert lib.claw_num_aux(C.byref(c)) == 2
+    # Q, S1, S2, S3 (SSPRK(10,4)) and 2 aux fields
+    assert n >= (4 * 3 + 2) * 32 * 32 * 8
+    s1, _ = W.psystem_layered_1d(64)
+    assert _bytes(s1)[1] == 2
+    # SharpClaw only
+    assert _bytes(dict(spec, scheme="classic"))[0] == 0

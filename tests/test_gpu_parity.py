@@ -48,6 +48,8 @@ def unit_groups(spec):
         return g + ([[len(g) + (0 if nd == 1 else 1)]] if spec.get("tracer") else [])
     if r == "elastic_vc":
         return [[0, 1, 2], [3, 4]]
+    if r == "psystem":
+        return [[0], [1]] if nd == 1 else [[0], [1, 2]]
     return [[0]]
 
 
@@ -845,3 +847,97 @@ def test_full_size_split_radial_dam_break_one_step(split):
     s.step(dt)
     o, _ = oracle.step(spec, q1, dt)
     assert fp64_err(s.get_state(), o, spec) <= 1e-12
+
+
+# --------------------------------------------------------------------------
+# Nonlinear p-system in a checkerboard medium (SharpClaw, f-wave flux)
+# --------------------------------------------------------------------------
+PSYS_VARIANTS = [("ssp104", 5), ("ssp33", 5), ("ssp104", 7)]
+
+
+@pytest.mark.parametrize("integ,order", PSYS_VARIANTS)
+def test_psystem_checkerboard_ragged_replay(integ, order):
+    say("case: p-system checkerboard 70x50 (10 cells/period),", integ, "WENO", order, "12 steps")
+    spec, q, aux = W.psystem_checkerboard(10, 7, ny_periods=5, time_integrator=integ,
+                                          weno_order=order,
+                                          cfl_desired=2.45 if integ == "ssp104" else 0.5,
+                                          cfl_max=2.5 if integ == "ssp104" else 0.6)
+    qo, info = oracle.advance(spec, q, 100.0, aux=aux, max_steps=12)
+    g = replay(spec, q, info["dts"][info["acc"] == 1], aux=aux, seg_rows=7)
+    assert fp64_err(g, qo, spec) <= 1e-12
+
+
+def test_psystem_periodic_and_mixed_boundaries():
+    say("case: p-system checkerboard 64x48, periodic x / wall-extrap y, 10 steps")
+    spec, q, aux = W.psystem_checkerboard(8, 8, ny_periods=6, bc_lower=("periodic", "wall"),
+                                          bc_upper=("periodic", "extrap"))
+    q[1] = 0.2 * np.cos(2 * np.pi * np.arange(64) / 64.0)[None, :]
+    qo, info = oracle.advance(spec, q, 100.0, aux=aux, max_steps=10)
+    g = replay(spec, q, info["dts"][info["acc"] == 1], aux=aux)
+    assert fp64_err(g, qo, spec) <= 1e-12
+
+
+def test_psystem_1d_interface_device_controller():
+    say("case: 1D p-system impedance interface, 300 cells, device controller to t=0.5")
+    n = 300
+    spec, aux = W.psystem_layered_1d(n, interfaces=(0.5,), materials=((1.0, 1.0), (5.0, 5.0)))
+    x = (np.arange(n) + 0.5) / n
+    q = np.zeros((2, 1, n))
+    q[0, 0] = 0.05 * np.exp(-((x - 0.25) / 0.05) ** 2)
+    q[1, 0] = -q[0, 0]
+    qo, dts, info = oracle_run(spec, q, 0.5, aux=aux)
+    s = solver(spec, q, aux)
+    st = s.advance(0.5, steps_per_graph=8)
+    assert st["accepted"] == info["accepted"] and st["rejected"] == info["rejected"]
+    assert fp64_err(s.get_state(), qo, spec) <= 1e-12
+    g = replay(spec, q, dts, aux=aux)
+    assert fp64_err(g, qo, spec) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_kahan"])
+def test_psystem_tiling_does_not_change_results(prec):
+    say("case: p-system checkerboard 96x80 seg_rows 4/16/80 bitwise equal", prec)
+    spec, q, aux = W.psystem_checkerboard(8, 12, ny_periods=10, precision=prec)
+    outs = [replay(spec, q, [0.02] * 3, aux=aux, seg_rows=sr) for sr in (4, 16, 80)]
+    np.testing.assert_array_equal(outs[0], outs[1])
+    np.testing.assert_array_equal(outs[0], outs[2])
+
+
+def test_fp32_kahan_psystem_l1():
+    say("case: FP32+Kahan p-system checkerboard 120x120 (12 cells/period), 30 steps")
+    spec, q, aux = W.psystem_checkerboard(12, 10)
+    qo, info = oracle.advance(spec, q, 100.0, aux=aux, max_steps=30)
+    g = replay(dict(spec, precision="fp32_kahan"), q, info["dts"][info["acc"] == 1], aux=aux)
+    err = l1_rel_groups(g, qo, spec)
+    say("L1 relative errors (unit-group scale)", err)
+    assert max(err) <= 1e-5
+
+
+def test_full_size_psystem_window_one_step():
+    """The benchmark's grid (20 x 20 periods at 240 cells per period, 4800^2)
+    in its tiling: evolve on the GPU, take one GPU step, and check a 64^2
+    window of it against the oracle run on the window plus a 40-cell margin
+    (one SSPRK(10,4) step depends on 10 x 3 cells each way)."""
+    say("case: p-system checkerboard 4800^2, windowed one-step parity after 6 GPU steps")
+    spec, q, aux = W.psystem_checkerboard(240, 20)
+    s = solver(spec, q, aux)
+    s.autotune(reps=1)
+    s.advance(1e9, max_steps=6)
+    q1 = s.get_state()
+    dt = s.clock()["dt_next"]
+    s.step(dt)
+    g = s.get_state()
+    s.close()
+    h = 1.0 / 240
+    for (j0, i0) in ((700, 1900), (0, 0), (4736, 2500)):
+        lo_j, hi_j = max(j0 - 40, 0), min(j0 + 64 + 40, 4800)
+        lo_i, hi_i = max(i0 - 40, 0), min(i0 + 64 + 40, 4800)
+        ws = dict(spec, num_cells=(hi_i - lo_i, hi_j - lo_j), lower=(lo_i * h, lo_j * h),
+                  upper=(hi_i * h, hi_j * h),
+                  bc_lower=("wall" if lo_i == 0 else "extrap", "wall" if lo_j == 0 else "extrap"),
+                  bc_upper=("extrap", "extrap"))
+        o, _ = oracle.step(ws, q1[:, lo_j:hi_j, lo_i:hi_i], dt, aux=aux[:, lo_j:hi_j, lo_i:hi_i])
+        oj, oi = j0 - lo_j, i0 - lo_i
+        ow = o[:, oj:oj + 64, oi:oi + 64]
+        gw = g[:, j0:j0 + 64, i0:i0 + 64]
+        assert fp64_err(gw, ow, spec) <= 1e-12, (j0, i0)
