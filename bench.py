@@ -119,8 +119,17 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 #            cell: 1 face x (Roe solve 73 + limiter 46 + correction 32) + cell
 #            primitives 4 + update 15 + Courant maximum 3 = 173; HBM 48 B (FP64
 #            q in + out); Godunov splitting is 2 sweeps a step, Strang 3
+#   psystem_stage  2D p-system, SharpClaw WENO5, per cell and stage: 3
+#            components x 2 directions x WENO5 edge pair 100 + 2 faces x
+#            f-wave flux 35 (two exponentials, two impedances, interface
+#            velocity and stress, speed) + flux difference 15 + stage
+#            combination 9 + maxima 2 = 696; HBM per cell-stage, FP64,
+#            SSPRK(10,4) averaged over the stages: plain stages 64 B (S in, y
+#            out, 2 aux), stage 5 112 B, stage 10 88 B -> 71.2 B; FP32+Kahan
+#            plain 32 B, stage 5 56 B, stage 10 80 B (Q and its compensation
+#            in and out) -> 39.2 B
 FLOPS_PER_CELL = {"sw": 554.0, "euler_stage": 1040.0, "euler_stage_weno7": 1840.0,
-                  "euler_roe": 1160.0, "sw_sweep": 173.0}
+                  "euler_roe": 1160.0, "sw_sweep": 173.0, "psystem_stage": 696.0}
 
 
 def roofline(bound, cells, gpu_ms, launches, kernel_name, bytes_per_launch, flops_per_launch=None,
@@ -245,6 +254,10 @@ WORKLOADS = {
     "sw": ("2D shallow water radial dam break 1024^2", lambda W: W.radial_dam_break(1024) + (None,)),
     "euler": ("2D Euler shock-bubble 2048x1024 SharpClaw", lambda W: W.shock_bubble(2048, 1024) + (None,)),
     "elastic": ("2D layered elasticity 2048^2", lambda W: W.layered_elastic(2048)),
+    "euler_axisym": ("classic axisymmetric Euler shock-bubble 1280x320 (Roe, tracer, source)",
+                     lambda W: W.shock_bubble_axisym(1280, 320) + (None,)),
+    "psystem": ("2D p-system checkerboard 4800^2 (20 x 20 periods, 240 cells each) SharpClaw",
+                lambda W: W.psystem_checkerboard(240, 20)),
     "sw_godunov": ("2D shallow water radial dam break 1024^2, Godunov split",
                    lambda W: (dict(W.radial_dam_break(1024)[0], dimensional_split="godunov"),
                               W.radial_dam_break(1024)[1], None)),
@@ -392,6 +405,19 @@ def main():
                                      FLOPS_PER_CELL["sw_sweep"] * r["cells"], "f64")
             r["sweeps_per_step"] = nsw
             extras[f"sw_radial_1024_fp64_split_{split}"] = r
+
+        log("p-system checkerboard 4800^2 (20 x 20 periods at 240 cells), SharpClaw WENO5 + SSPRK(10,4)")
+        ps_spec, ps_q, ps_aux = W.psystem_checkerboard(240, 20)
+        for prec in ("fp64", "fp32_kahan"):
+            r = timed_run(dict(ps_spec, precision=prec), ps_q, ps_aux, 10, 2, 1e9)
+            r["roofline"] = roofline("alu", r["cells"], r["gpu_ms"], 10 * (r["steps"] + r["rejected"]),
+                                     f"k_sharp2d<{'double' if prec == 'fp64' else 'float'},PSystem,SSPRK104>",
+                                     (71.2 if prec == "fp64" else 39.2) * r["cells"],
+                                     FLOPS_PER_CELL["psystem_stage"] * r["cells"],
+                                     "f64" if prec == "fp64" else "f32")
+            r["cfl"] = [2.45, 2.5]
+            extras[f"psystem_checkerboard_4800_{prec}_ssp104_weno5"] = r
+        del ps_q, ps_aux
 
         log("layered elasticity 2048^2")
         el_spec, el_q, el_aux = W.layered_elastic(2048)
