@@ -941,3 +941,27 @@ def test_full_size_psystem_window_one_step():
         ow = o[:, oj:oj + 64, oi:oi + 64]
         gw = g[:, j0:j0 + 64, i0:i0 + 64]
         assert fp64_err(gw, ow, spec) <= 1e-12, (j0, i0)
+
+
+def test_batch_rejects_split_and_sharpclaw_members():
+    say("case: claw_batch_add refuses split-step and SharpClaw handles (CLAW_E_INVAL)")
+    from paper_1111_6583_amd import Batch
+    from paper_1111_6583_amd._claw import ClawError
+    b = Batch(2)
+    spec, q = W.radial_dam_break(64)
+    for bad in (dict(spec, dimensional_split="godunov"),):
+        s = solver(bad, q)
+        with pytest.raises(ClawError):
+            b.add(s, 0.1)
+        s.close()
+    ps, pq, pa = W.psystem_checkerboard(8, 4)
+    s = solver(ps, pq, pa)
+    with pytest.raises(ClawError):
+        b.add(s, 0.1)
+    s.close()
+    ok = solver(spec, q)
+    b.add(ok, 0.05)
+    while b.advance(8) > 0:
+        pass
+    b.remove(ok)
+    ok.close()
