@@ -46,24 +46,23 @@ __device__ __forceinline__ R wave_max(R v) {
 }
 
 // ---------------------------------------------------------------------------
-// Reciprocal and reciprocal square root: the hardware estimate refined by two
-// Newton steps (FP64: relative error at the level of a few ulp, far inside
-// the 1e-12 parity bar; far cheaper than the IEEE-exact expansions).  FP32
-// uses the single-instruction estimates (about 1 ulp).
+// Reciprocal and reciprocal square root: the hardware estimate refined by one
+// Newton step.  Measured on MI355X over 2^20 arguments spanning 2^-12..2^12:
+// the FP64 estimates are within 4.6e-8 (rcp) and 5.2e-8 (rsq) relative, one
+// step brings them to 2.1e-15 and 4.1e-15, a second to 1.1e-16 and 2.6e-16.
+// One step is far inside the 1e-12 parity bar and saves two (rcp) or three
+// (rsq) FP64 instructions per call on the kernels' instruction-issue-bound
+// path.  FP32 uses the single-instruction estimates (about 1 ulp).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double frcp(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = __builtin_fma(-x, r, 1.0);
-  r = __builtin_fma(r, e, r);
-  e = __builtin_fma(-x, r, 1.0);
+  const double r = __builtin_amdgcn_rcp(x);
+  const double e = __builtin_fma(-x, r, 1.0);
   return __builtin_fma(r, e, r);
 }
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double frsq(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  const double h = 0.5 * x;
-  y = y * __builtin_fma(-h, y * y, 1.5);
-  return y * __builtin_fma(-h, y * y, 1.5);
+  const double y = __builtin_amdgcn_rsq(x);
+  return y * __builtin_fma(-0.5 * x, y * y, 1.5);
 }
 __device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
 // sqrt(x) for x > 0
