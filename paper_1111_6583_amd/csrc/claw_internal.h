@@ -97,6 +97,6 @@ struct SweepArgs {
 };
 
 // How a kernel obtains dt and the source buffer.
-enum StepMode { kHostDt = 0, kDeviceCtrl = 1, kProbe = 2 };
+enum StepMode { kHostDt = 0, kDeviceCtrl = 1 };
 
 }  // namespace claw
