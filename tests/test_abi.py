@@ -150,3 +150,12 @@ def test_psystem_options():
     assert _bytes(s1)[1] == 2
     # SharpClaw only
     assert _bytes(dict(spec, scheme="classic"))[0] == 0
+
+
+def test_size_limit():
+    """Grids above 2e9 cells are refused; the largest accepted ones report
+    their exact workspace size."""
+    spec, _ = W.radial_dam_break(64)
+    assert _bytes(dict(spec, num_cells=(50000, 50000)))[0] == 0
+    n, m = _bytes(dict(spec, num_cells=(44000, 44000)))
+    assert n >= 2 * 3 * 44000 * 44000 * 8

@@ -965,3 +965,65 @@ def test_batch_rejects_split_and_sharpclaw_members():
         pass
     b.remove(ok)
     ok.close()
+
+
+# --------------------------------------------------------------------------
+# Degenerate and edge cases: minimum grids, uniform states
+# --------------------------------------------------------------------------
+def _min_cases():
+    sw, swq = W.radial_dam_break(4)
+    swq = swq + 0.1 * np.random.default_rng(41).random(swq.shape)
+    eu, euq = W.random_smooth_euler(4, seed=3)
+    ps, psq, psa = W.psystem_checkerboard(2, 2)
+    el, elq, ela = W.layered_elastic(4)
+    d1, d1q = W.dam_break_1d(4)
+    return [("classic sw 4x4", sw, swq, None),
+            ("classic sw 4x4 walls", dict(sw, bc_lower=("wall", "wall"), bc_upper=("wall", "wall")), swq, None),
+            ("split strang sw 4x4", dict(sw, dimensional_split="strang"), swq, None),
+            ("sharpclaw euler weno5 4x4", eu, euq, None),
+            ("sharpclaw euler weno7 ssp104 4x4", dict(eu, weno_order=7, time_integrator="ssp104",
+                                                      cfl_desired=2.45, cfl_max=2.5), euq, None),
+            ("p-system 4x4", ps, psq, psa),
+            ("elastic 4x4", el, elq, ela),
+            ("classic sw 1d 4 cells", d1, d1q, None)]
+
+
+@pytest.mark.parametrize("case", range(8))
+def test_minimum_grid_every_path(case):
+    name, spec, q, aux = _min_cases()[case]
+    say("case: minimum grid,", name)
+    qo, info = oracle.advance(spec, q, 1e9, aux=aux, max_steps=6)
+    g = replay(spec, q, info["dts"][info["acc"] == 1], aux=aux)
+    assert fp64_err(g, qo, spec) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_kahan"])
+def test_uniform_state_is_preserved_exactly(prec):
+    """A uniform state on a periodic grid has no jumps: every solver must
+    leave it unchanged -- bit for bit for the classic solvers, to rounding of
+    the state's magnitude for SharpClaw (its WENO edge values of a constant,
+    and the stage combinations, are exact only to rounding; the p-system at
+    rest shows a ~1e-20 drift of the x-momentum against a strain of 0.05)."""
+    say("case: uniform periodic states stay put,", prec)
+    per = dict(bc_lower=("periodic", "periodic"), bc_upper=("periodic", "periodic"), precision=prec)
+    sw, _ = W.radial_dam_break(70, ny=66)
+    eu, _ = W.random_smooth_euler(70, seed=1)
+    ps, _, psa = W.psystem_checkerboard(6, 7, ny_periods=6)
+    ax, _ = W.shock_bubble_axisym(70, 30)
+    cases = [(dict(sw, **per), [1.3, 0.2, -0.1], None),
+             (dict(sw, **per, dimensional_split="godunov"), [1.3, 0.2, -0.1], None),
+             (dict(eu, **per), [1.1, 0.3, -0.2, 2.7], None),
+             (dict(eu, **per, weno_order=7, time_integrator="ssp104", cfl_desired=2.45, cfl_max=2.5),
+              [1.1, 0.3, -0.2, 2.7], None),
+             (dict(ax, **per, source="none"), [1.1, 0.3, -0.2, 2.7, 0.4], None),
+             (dict(ps, **per), [0.05, 0.0, 0.0], np.ones_like(psa))]
+    for spec, vals, aux in cases:
+        nx, ny = spec["num_cells"]
+        q = np.array(vals)[:, None, None] * np.ones((len(vals), ny, nx))
+        g = replay(spec, q, [1e-3] * 4, aux=aux)
+        q = replay(spec, q, [], aux=aux)   # the state as stored (FP32: rounded)
+        if spec["scheme"] == "classic":
+            np.testing.assert_array_equal(g, q)
+        else:
+            tol = (1e-15 if prec == "fp64" else 1e-6) * np.max(np.abs(q))
+            np.testing.assert_allclose(g, q, rtol=0, atol=tol)
