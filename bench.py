@@ -79,7 +79,7 @@ def timed_run(spec, q, aux, steps, warmup, t_end, tune=True, graph_k=16):
     ncell = int(q.shape[1] * q.shape[2])
     kernel_ms = s.time_kernel(st["dt_next"] * 0.5, reps=20)
     out = dict(cells=ncell, steps=acc, rejected=st["rejected"] - c0["rejected"], wall_s=wall,
-               gpu_ms=st["gpu_ms"], seg_rows=seg, kernel_ms=kernel_ms, t=st["t"],
+               gpu_ms=st["gpu_ms"], seg_rows=seg, segs=s.get_segs(), kernel_ms=kernel_ms, t=st["t"],
                value=ncell * acc / wall, ms_per_step=1e3 * wall / max(acc, 1))
     if spec.get("dimensional_split", "none") != "none":
         out["seg_rows_x"] = s.get_tuning_x()
@@ -267,7 +267,7 @@ WORKLOADS = {
 }
 
 
-def kernel_only(workload, precision, launches, seg_rows=0, seg_rows_x=0):
+def kernel_only(workload, precision, launches, seg_rows=0, seg_rows_x=0, segs=0):
     """Launch only the step kernel (classic) or stages 1-2 (SharpClaw) of a
     workload `launches` times, for hardware-counter runs.  seg_rows > 0 fixes
     the tiling (no autotuning launches in the profile)."""
@@ -279,14 +279,15 @@ def kernel_only(workload, precision, launches, seg_rows=0, seg_rows_x=0):
     s.set_state(q)
     if aux is not None:
         s.set_aux(aux)
-    if seg_rows > 0:
-        s.set_tuning(seg_rows, seg_rows_x)
+    if seg_rows > 0 or segs > 0:
+        s.set_tuning(seg_rows, seg_rows_x, segs)
     else:
         s.autotune(reps=2)
     s.advance(1e9, max_steps=10)
     ms = s.time_kernel(s.clock()["dt_next"] * 0.5, reps=launches)
     print(json.dumps(dict(mode="kernel", workload=name, precision=precision, launches=launches,
-                          avg_kernel_us=ms * 1e3, seg_rows=s.get_tuning())), flush=True)
+                          avg_kernel_us=ms * 1e3, seg_rows=s.get_tuning(),
+                          segs=s.get_segs())), flush=True)
 
 
 def copy_only(mib, launches):
@@ -318,6 +319,8 @@ def main():
     ap.add_argument("--launches", type=int, default=20)
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--seg-rows", type=int, default=0, help="kernel mode: fixed rows per segment")
+    ap.add_argument("--segs", type=int, default=0,
+                    help="kernel mode: fixed number of row segments (overrides --seg-rows)")
     ap.add_argument("--seg-rows-x", type=int, default=0,
                     help="kernel mode, split steps: fixed rows per segment of the x sweeps")
     a = ap.parse_args()
@@ -326,7 +329,7 @@ def main():
               "(multi-GPU decomposition is designed but not built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     if a.mode == "kernel":
-        return kernel_only(a.workload, a.precision, a.launches, a.seg_rows, a.seg_rows_x)
+        return kernel_only(a.workload, a.precision, a.launches, a.seg_rows, a.seg_rows_x, a.segs)
     if a.mode == "copy":
         return copy_only(a.copy_mib, a.launches)
 
@@ -345,7 +348,8 @@ def main():
         "config": {"workload": "2D shallow-water radial dam break, classic wave propagation "
                                "(Roe + entropy fix, MC, full transverse), 1024x1024, CFL 0.9, "
                                "device-controlled steps toward t=1.0",
-                   "cells": h["cells"], "seg_rows": h["seg_rows"], "parallelism": "single GPU"},
+                   "cells": h["cells"], "seg_rows": h["seg_rows"], "segs": h["segs"],
+                   "parallelism": "single GPU"},
     }
     line["roofline"] = roofline("alu", h["cells"], h["gpu_ms"], h["steps"] + h["rejected"],
                                 "k_classic2d<double,ShallowWater>", 48 * h["cells"],

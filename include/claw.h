@@ -165,10 +165,14 @@ typedef struct claw_stats {
 /* Kernel tiling.  Results do not depend on it (bit for bit). */
 typedef struct claw_tuning {
   int seg_rows;          /* rows per work item of the 2D kernels (>= 1); of the y sweeps of a
-                            dimensionally split step */
+                            dimensionally split step.  The rows are split into
+                            ceil(ny / seg_rows) segments as evenly as possible */
   int seg_rows_x;        /* rows per work item of the x sweeps of a dimensionally split step
                             (rows are independent there); <= 0: seg_rows.  Ignored otherwise */
-  int reserved[2];
+  int segs;              /* row segments (work items per column strip) of the 2D kernels;
+                            > 0 overrides seg_rows (at most ny).  claw_get_tuning fills both,
+                            seg_rows being the longest segment */
+  int reserved;
 } claw_tuning;
 
 typedef struct claw_solver* claw_t;

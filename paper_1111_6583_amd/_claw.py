@@ -48,7 +48,8 @@ class ClawStats(C.Structure):
 
 
 class ClawTuning(C.Structure):
-    _fields_ = [("seg_rows", C.c_int), ("seg_rows_x", C.c_int), ("reserved", C.c_int * 2)]
+    _fields_ = [("seg_rows", C.c_int), ("seg_rows_x", C.c_int), ("segs", C.c_int),
+                ("reserved", C.c_int)]
 
 
 class ClawError(RuntimeError):

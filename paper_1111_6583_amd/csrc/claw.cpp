@@ -126,7 +126,7 @@ int validate(const claw_config* c) {
 }
 
 // Process-wide tiling cache: (4 scheme + split mode, riemann, precision, WENO order, nx, ny)
-// -> (seg_rows, seg_rows_x).
+// -> (row segments, seg_rows_x).
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int, int, int, int>, std::pair<int, int>> g_tune;
 
@@ -137,7 +137,7 @@ bool split(const claw_config& c) {
 }
 bool strang(const claw_config& c) { return split(c) && c.dimensional_split == CLAW_SPLIT_STRANG; }
 
-int default_seg_rows(int ny) { return std::min(ny, 16); }
+int default_segs(int ny) { return (ny + 15) / 16; }
 // x sweeps of a split step: rows are independent, so short row segments buy
 // more wavefronts at no extra work
 int default_seg_rows_x(int ny) { return std::min(ny, 4); }
@@ -236,22 +236,29 @@ std::tuple<int, int, int, int, int, int> tune_key(claw_t h) {
                          h->cfg.ndim == 2 ? h->cfg.num_cells[1] : 1);
 }
 
-std::pair<int, int> seg_rows_for(claw_t h) {
+std::pair<int, int> tiling_for(claw_t h) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   auto it = g_tune.find(tune_key(h));
   const int ny = h->cfg.ndim == 2 ? h->cfg.num_cells[1] : 1;
   return it != g_tune.end() ? it->second
-                            : std::make_pair(default_seg_rows(ny), default_seg_rows_x(ny));
+                            : std::make_pair(default_segs(ny), default_seg_rows_x(ny));
 }
 
-void set_tiling(claw_t h, int seg_rows) {
+int segs_from_rows(int ny, int seg_rows) {
+  seg_rows = std::max(1, std::min(seg_rows, ny));
+  return (ny + seg_rows - 1) / seg_rows;
+}
+
+// Tile the 2D kernels into column strips x `segs` row segments (rows split
+// as evenly as possible).
+void set_tiling(claw_t h, int segs) {
   GridDesc& g = h->hg;
   const int lanes =
       h->cfg.scheme == CLAW_CLASSIC ? kMarchLanesClassic : march_lanes_sharp(weno_r_of(h->cfg));
   g.strips = (g.nx + lanes - 1) / lanes;
   if (h->cfg.ndim == 2) {
-    g.seg_rows = std::max(1, std::min(seg_rows, g.ny));
-    g.segs = (g.ny + g.seg_rows - 1) / g.seg_rows;
+    g.segs = std::max(1, std::min(segs, g.ny));
+    g.seg_rows = (g.ny + g.segs - 1) / g.segs;
   } else {
     g.seg_rows = 1;
     g.segs = 1;
@@ -363,8 +370,8 @@ int launch_sharp_stages(claw_t h, int from, int to, int mode, double dt) {
 // Q^n is never overwritten, so a rejected step leaves it intact.
 int launch_split(claw_t h, int mode, double dt) {
   const GridDesc& g = h->hg;
-  const int rows_y = std::max(1, std::min(g.seg_rows, g.ny));
-  const int rows_x = std::max(1, std::min(h->seg_rows_x > 0 ? h->seg_rows_x : g.seg_rows, g.ny));
+  const int segs_y = g.segs;
+  const int segs_x = segs_from_rows(g.ny, h->seg_rows_x > 0 ? h->seg_rows_x : g.seg_rows);
   int index = 0;
   auto sweep = [&](int dir, const void* in, const void* cin, void* out, void* cout, double frac,
                    int fin) -> int {
@@ -379,8 +386,8 @@ int launch_split(claw_t h, int mode, double dt) {
     sa.final_sweep = fin;
     sa.strips = dir == 0 ? (g.nx + kMarchLanesClassic - 1) / kMarchLanesClassic
                          : (g.nx + kLanes - 1) / kLanes;
-    sa.seg_rows = dir == 0 ? rows_x : rows_y;
-    sa.nblocks = sa.strips * ((g.ny + sa.seg_rows - 1) / sa.seg_rows);
+    sa.segs = dir == 0 ? segs_x : segs_y;
+    sa.nblocks = sa.strips * sa.segs;
     HIPCHK(launch_sweep(dir, h->kr, h->fp32, g.limiter, h->stream, h->d_grid, mode, dt, h->src,
                         sa));
     return CLAW_OK;
@@ -599,7 +606,7 @@ int claw_create(const claw_config* cfg, void* d_ws, size_t ws_bytes, void* hip_s
   h->split_c[0] = buf(h, off, 13, base);
   h->split_c[1] = buf(h, off, 14, base);
   {
-    const std::pair<int, int> t = seg_rows_for(h);
+    const std::pair<int, int> t = tiling_for(h);
     set_tiling(h, t.first);
     h->seg_rows_x = t.second;
   }
@@ -860,9 +867,9 @@ int claw_set_clock(claw_t h, const claw_stats* st) {
 }
 
 int claw_set_tuning(claw_t h, const claw_tuning* tn) {
-  if (!h || !tn || tn->seg_rows < 1) return CLAW_E_INVAL;
+  if (!h || !tn || (tn->seg_rows < 1 && tn->segs < 1)) return CLAW_E_INVAL;
   HIPCHK(hipSetDevice(h->device));
-  set_tiling(h, tn->seg_rows);
+  set_tiling(h, tn->segs > 0 ? tn->segs : segs_from_rows(h->hg.ny, tn->seg_rows));
   h->seg_rows_x = tn->seg_rows_x > 0 ? tn->seg_rows_x : 0;
   int rc = upload_grid(h);
   if (rc) return rc;
@@ -875,6 +882,7 @@ int claw_get_tuning(claw_t h, claw_tuning* tn) {
   std::memset(tn, 0, sizeof(*tn));
   tn->seg_rows = h->hg.seg_rows;
   tn->seg_rows_x = h->seg_rows_x > 0 ? h->seg_rows_x : h->hg.seg_rows;
+  tn->segs = h->hg.segs;
   return CLAW_OK;
 }
 
@@ -884,11 +892,27 @@ int claw_autotune(claw_t h, int reps, claw_tuning* out) {
   HIPCHK(hipSetDevice(h->device));
   if (reps < 1) reps = 3;
   const int ny = h->hg.ny;
+  // candidate segment counts: those of 4..128 rows per segment, and those
+  // that bring the workgroup count just under a whole number of waves per
+  // SIMD (a launch whose last round leaves some SIMDs with one wave less
+  // takes as long as if they all had it)
   std::vector<int> cands;
   if (h->cfg.ndim == 2) {
     for (int c : {4, 5, 6, 7, 8, 9, 10, 11, 12, 14, 16, 20, 24, 28, 32, 40, 48, 64, 96, 128})
-      if (c <= ny) cands.push_back(c);
-    if (cands.empty()) cands.push_back(ny);
+      if (c <= ny) cands.push_back(segs_from_rows(ny, c));
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) !=
+        hipSuccess)
+      cus = 0;
+    const int simds = 4 * cus;
+    const int strips = h->hg.strips;
+    for (int w = 1; w <= 8 && simds > 0; ++w) {
+      const int s = w * simds / strips;
+      if (s >= 1 && s <= ny && (ny + s - 1) / s >= 4) cands.push_back(s);
+    }
+    if (cands.empty()) cands.push_back(1);
+    std::sort(cands.begin(), cands.end());
+    cands.erase(std::unique(cands.begin(), cands.end()), cands.end());
   } else {
     cands.push_back(1);
   }
@@ -948,8 +972,9 @@ int claw_autotune(claw_t h, int reps, claw_tuning* out) {
   if (h->graph) { hipGraphExecDestroy(h->graph); h->graph = nullptr; }
   if (out) {
     std::memset(out, 0, sizeof(*out));
-    out->seg_rows = best;
-    out->seg_rows_x = best_x > 0 ? best_x : best;
+    out->seg_rows = h->hg.seg_rows;
+    out->seg_rows_x = best_x > 0 ? best_x : h->hg.seg_rows;
+    out->segs = h->hg.segs;
   }
   return sync(h);
 }

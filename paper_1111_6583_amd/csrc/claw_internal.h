@@ -39,10 +39,17 @@ struct SpeedSlot {
   unsigned int pad[61];           // one slot per 256 bytes
 };
 
+// First row of segment `seg` when n rows are split into `segs` segments as
+// evenly as possible (sizes differ by at most one row).
+__host__ __device__ __forceinline__ int seg_begin(int seg, int n, int segs) {
+  return (int)(((long long)seg * n) / segs);
+}
+
 // Everything a kernel needs about one grid.  Lives in device memory.
 struct GridDesc {
   int nx, ny;
-  int strips, segs, seg_rows;
+  int strips, segs;               // column strips x row segments = workgroups
+  int seg_rows;                   // rows of the longest segment
   int nblocks;                    // workgroups of one launch over this grid
   int bc[4];                      // x-lower, x-upper, y-lower, y-upper
   int limiter, transverse, efix, scheme;
@@ -93,7 +100,7 @@ struct SweepArgs {
   int final_sweep;   // last sweep of the step: applies the source, closes the Courant reduction
   int nblocks;       // workgroups of this launch
   int strips;        // column strips (workgroups per row segment)
-  int seg_rows;      // rows per workgroup
+  int segs;          // row segments (rows split as evenly as possible)
 };
 
 // How a kernel obtains dt and the source buffer.

@@ -95,8 +95,8 @@ __global__ __launch_bounds__(kLanes) void k_classic2d(const GridDesc* __restrict
   const int i = strip * U - H + lane;
   const bool own = lane >= H && lane < H + U && i < nx;
   const bool own_face = lane >= H && lane <= H + U && i <= nx;
-  const int j0 = seg * G.seg_rows;
-  const int j1 = min(j0 + G.seg_rows, ny);
+  const int j0 = seg_begin(seg, ny, G.segs);
+  const int j1 = seg_begin(seg + 1, ny, G.segs);
   const AxisMap mx = map_axis(i, nx, G.bc[0], G.bc[1], H);
   const int bcy0 = G.bc[2], bcy1 = G.bc[3];
   const int ic = i < 0 ? 0 : (i >= nx ? nx - 1 : i);   // clamped column for pointwise reads
@@ -144,9 +144,17 @@ __global__ __launch_bounds__(kLanes) void k_classic2d(const GridDesc* __restrict
     load_state<R, P>(qnext, q, plane, nx, mx, my, es);
     load_aux<R, P>(anext, aux, plane, nx, mx, my);
     if constexpr (PF == 2) {
-      myb[1] = map_axis(j0 - 1, ny, bcy0, bcy1, H);
-      load_raw<R, M>(qb[1], q, plane, nx, mx, myb[1]);
-      load_aux<R, P>(ab[1], aux, plane, nx, mx, myb[1]);
+      // row j0-1 goes to the buffer the first row reads (see the loop below)
+      const AxisMap m1 = map_axis(j0 - 1, ny, bcy0, bcy1, H);
+      if ((j0 - 2) & 1) {
+        myb[0] = m1;
+        load_raw<R, M>(qb[0], q, plane, nx, mx, m1);
+        load_aux<R, P>(ab[0], aux, plane, nx, mx, m1);
+      } else {
+        myb[1] = m1;
+        load_raw<R, M>(qb[1], q, plane, nx, mx, m1);
+        load_aux<R, P>(ab[1], aux, plane, nx, mx, m1);
+      }
     }
   }
   // One row of the pipeline (the stages that row r runs are in st; phase
@@ -429,7 +437,15 @@ __global__ __launch_bounds__(kLanes) void k_classic2d(const GridDesc* __restrict
   if constexpr (PF == 1) {
     for (int r = j0 - 2; r <= j1 + 1; ++r) row(stages(r), r, std::integral_constant<int, 0>{});
   } else {
-    for (int r = j0 - 2; r <= j1 + 1; r += 2) {
+    // Every row runs in the phase of its parity, whatever the tiling: the two
+    // instantiations of the body may round differently (contractions), and
+    // results must not depend on where segments start.
+    int r = j0 - 2;
+    if (r & 1) {
+      row(stages(r), r, std::integral_constant<int, 1>{});
+      ++r;
+    }
+    for (; r <= j1 + 1; r += 2) {
       row(stages(r), r, std::integral_constant<int, 0>{});
       if (r + 1 <= j1 + 1) row(stages(r + 1), r + 1, std::integral_constant<int, 1>{});
     }

@@ -199,8 +199,8 @@ __global__ __launch_bounds__(kLanes) void k_sharp2d(const GridDesc* __restrict__
   const int i = strip * U - H + lane;
   const bool own = lane >= H && lane < H + U && i < nx;
   const bool own_face = lane >= H && lane <= H + U && i <= nx;
-  const int j0 = seg * G.seg_rows;
-  const int j1 = min(j0 + G.seg_rows, ny);
+  const int j0 = seg_begin(seg, ny, G.segs);
+  const int j1 = seg_begin(seg + 1, ny, G.segs);
   const AxisMap mx = map_axis(i, nx, G.bc[0], G.bc[1], H);
   const int bcy0 = G.bc[2], bcy1 = G.bc[3];
   const EdgeStates<R, M> es = edge_states<R, M>(G, mx);

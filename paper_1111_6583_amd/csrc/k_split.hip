@@ -136,8 +136,8 @@ __global__ __launch_bounds__(kLanes) void k_sweep_x(const GridDesc* __restrict__
   const bool own = lane >= H && lane < H + U && i < nx;
   const bool own_face = lane >= H && lane <= H + U && i <= nx;
   const int ic = i < 0 ? 0 : (i >= nx ? nx - 1 : i);
-  const int j0 = seg * sa.seg_rows;
-  const int j1 = min(j0 + sa.seg_rows, ny);
+  const int j0 = seg_begin(seg, ny, sa.segs);
+  const int j1 = seg_begin(seg + 1, ny, sa.segs);
   const AxisMap mx = map_axis(i, nx, G.bc[0], G.bc[1], H);
   const EdgeStates<R, M> es = edge_states<R, M>(G, mx);
   const gconst<R> q = as_gconst<R>(sa.in ? sa.in : G.q[src]);
@@ -245,8 +245,8 @@ __global__ __launch_bounds__(kLanes) void k_sweep_y(const GridDesc* __restrict__
   const int ic = own ? i : nx - 1;                  // lanes past the edge read the last column
   const AxisMap mx{ic, 0, 0};                       // x boundaries play no part in a y sweep
   const int bcy0 = G.bc[2], bcy1 = G.bc[3];
-  const int j0 = seg * sa.seg_rows;
-  const int j1 = min(j0 + sa.seg_rows, ny);
+  const int j0 = seg_begin(seg, ny, sa.segs);
+  const int j1 = seg_begin(seg + 1, ny, sa.segs);
   const EdgeStates<R, M> es = edge_states<R, M>(G, mx);
   const gconst<R> q = as_gconst<R>(sa.in ? sa.in : G.q[src]);
   const gmut<R> qo = as_gmut<R>(sa.out ? sa.out : G.q[src ^ 1]);
@@ -431,7 +431,7 @@ static hipError_t launch_sweep_t(int dir, int riemann, int lim, hipStream_t st, 
 hipError_t launch_sweep(int dir, int riemann, int fp32, int lim, hipStream_t st,
                         const GridDesc* d_grid, int mode, double dt, int src,
                         const SweepArgs& sa) {
-  if (sa.nblocks < 1 || sa.strips < 1 || sa.seg_rows < 1) return hipErrorInvalidValue;
+  if (sa.nblocks < 1 || sa.strips < 1 || sa.segs < 1) return hipErrorInvalidValue;
   return fp32 ? launch_sweep_t<float, true>(dir, riemann, lim, st, d_grid, mode, dt, src, sa)
               : launch_sweep_t<double, false>(dir, riemann, lim, st, d_grid, mode, dt, src, sa);
 }

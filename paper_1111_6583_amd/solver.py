@@ -123,13 +123,20 @@ class Solver:
         return ms.value
 
     # -- tiling ------------------------------------------------------------
-    def set_tuning(self, seg_rows: int, seg_rows_x: int = 0):
+    def set_tuning(self, seg_rows: int = 0, seg_rows_x: int = 0, segs: int = 0):
         """Rows per workgroup of the 2D kernels (the y sweeps of a split
-        step) and of the x sweeps of a split step (0: seg_rows)."""
+        step) and of the x sweeps of a split step (0: seg_rows); segs > 0
+        sets the number of row segments instead of seg_rows."""
         tn = ClawTuning()
         tn.seg_rows = int(seg_rows)
         tn.seg_rows_x = int(seg_rows_x)
+        tn.segs = int(segs)
         check(self.lib.claw_set_tuning(self.h, C.byref(tn)), "claw_set_tuning")
+
+    def get_segs(self) -> int:
+        tn = ClawTuning()
+        check(self.lib.claw_get_tuning(self.h, C.byref(tn)), "claw_get_tuning")
+        return tn.segs
 
     def get_tuning(self) -> int:
         tn = ClawTuning()

@@ -621,6 +621,29 @@ def test_tiling_does_not_change_results(prec):
         outs.append(replay(spec, q, [2e-3] * 12, seg_rows=sr))
     np.testing.assert_array_equal(outs[0], outs[1])
     np.testing.assert_array_equal(outs[0], outs[2])
+    # segment counts whose segments start on odd and even rows alike
+    for segs in (7, 13, 37):
+        s = solver(spec, q)
+        s.set_tuning(segs=segs)
+        for _ in range(12):
+            s.step(2e-3)
+        np.testing.assert_array_equal(s.get_state(), outs[0])
+        s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_kahan"])
+def test_elastic_tiling_does_not_change_results(prec):
+    say("case: layered elasticity 120x90, seg_rows 8 / segs 7, 13 / one segment, bitwise", prec)
+    spec, q, aux = W.layered_elastic(120, ny=90)
+    spec = dict(spec, precision=prec)
+    ref = replay(spec, q, [1e-3] * 8, aux=aux, seg_rows=8)
+    for segs in (7, 13, 1):
+        s = solver(spec, q, aux)
+        s.set_tuning(segs=segs)
+        for _ in range(8):
+            s.step(1e-3)
+        np.testing.assert_array_equal(s.get_state(), ref)
+        s.close()
 
 
 def test_batch_results_equal_alone_and_in_mix():
