@@ -41,6 +41,17 @@ __device__ __forceinline__ float rmin(float a, float b) { return __builtin_fminf
 __device__ __forceinline__ float rmax(float a, float b) { return __builtin_fmaxf(a, b); }
 template <typename R> __device__ __forceinline__ R rabs(R a) { return a < R(0) ? -a : a; }
 
+// A product rounded on its own.  Interface fluxes end with one: left free,
+// the compiler may fuse a lane's own unrounded flux into the flux difference
+// while the neighbour's arrives rounded through the lane shift, so the two
+// cells of a face would see fluxes differing in the last bit (a uniform state
+// then drifts, and conservation holds one ulp less exactly).
+template <typename R>
+__device__ __forceinline__ R mul_rounded(R a, R b) {
+#pragma clang fp contract(off)
+  return a * b;
+}
+
 // ---------------------------------------------------------------------------
 // Scalar advection q_t + u q_x + v q_y = 0 (test problem: exact translation,
 // convergence).  One wave, the jump, at speed u (x) or v (y).
@@ -735,7 +746,8 @@ struct EulerHLLE {
       const R inv = frcp(s2 - s1);
       const R s12 = s1 * s2;
 #pragma unroll
-      for (int k = 0; k < M; ++k) F[k] = (s2 * fl[k] - s1 * fr[k] + s12 * (qr[k] - ql[k])) * inv;
+      for (int k = 0; k < M; ++k)
+        F[k] = mul_rounded(s2 * fl[k] - s1 * fr[k] + s12 * (qr[k] - ql[k]), inv);
     }
     return max_nan(rabs(s1), rabs(s2));
   }
@@ -783,8 +795,8 @@ struct PSystem {
     const R Zl = fsqrt(Kl * (sl + R(1)) * rl), Zr = fsqrt(Kr * (sr + R(1)) * rr);
     const R ul = ql[N] * irl, ur = qr[N] * irr;
     const R iz = frcp(Zl + Zr);
-    F[0] = -(Zl * ul + Zr * ur + (sr - sl)) * iz;
-    F[N] = -(Zr * sl + Zl * sr + Zl * Zr * (ur - ul)) * iz;
+    F[0] = mul_rounded(-(Zl * ul + Zr * ur + (sr - sl)), iz);
+    F[N] = mul_rounded(-(Zr * sl + Zl * sr + Zl * Zr * (ur - ul)), iz);
     if constexpr (NDIM == 2) F[3 - N] = R(0);
     return rmax(Zl * irl, Zr * irr);
   }

@@ -1023,10 +1023,10 @@ def test_minimum_grid_every_path(case):
 @pytest.mark.parametrize("prec", ["fp64", "fp32_kahan"])
 def test_uniform_state_is_preserved_exactly(prec):
     """A uniform state on a periodic grid has no jumps: every solver must
-    leave it unchanged -- bit for bit for the classic solvers, to rounding of
-    the state's magnitude for SharpClaw (its WENO edge values of a constant,
-    and the stage combinations, are exact only to rounding; the p-system at
-    rest shows a ~1e-20 drift of the x-momentum against a strain of 0.05)."""
+    leave it unchanged, bit for bit (SharpClaw in FP32: to a few ulps, its
+    stage combinations round).  Regression: a face flux fused, unrounded,
+    into its own lane's flux difference while the neighbour used the
+    rounded value made the p-system at rest drift by ~1e-20."""
     say("case: uniform periodic states stay put,", prec)
     per = dict(bc_lower=("periodic", "periodic"), bc_upper=("periodic", "periodic"), precision=prec)
     sw, _ = W.radial_dam_break(70, ny=66)
@@ -1045,8 +1045,7 @@ def test_uniform_state_is_preserved_exactly(prec):
         q = np.array(vals)[:, None, None] * np.ones((len(vals), ny, nx))
         g = replay(spec, q, [1e-3] * 4, aux=aux)
         q = replay(spec, q, [], aux=aux)   # the state as stored (FP32: rounded)
-        if spec["scheme"] == "classic":
+        if spec["scheme"] == "classic" or prec == "fp64":
             np.testing.assert_array_equal(g, q)
         else:
-            tol = (1e-15 if prec == "fp64" else 1e-6) * np.max(np.abs(q))
-            np.testing.assert_allclose(g, q, rtol=0, atol=tol)
+            np.testing.assert_allclose(g, q, rtol=0, atol=1e-6 * np.max(np.abs(q)))
