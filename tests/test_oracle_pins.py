@@ -1281,3 +1281,67 @@ def test_psystem_smooth_nonlinear_order():
     d1 = np.sum(np.abs(errs[0] - 0.5 * (errs[1][..., 0::2] + errs[1][..., 1::2]))) / 32
     d2 = np.sum(np.abs(errs[1] - 0.5 * (errs[2][..., 0::2] + errs[2][..., 1::2]))) / 64
     assert math.log2(d1 / d2) > 3.8, (d1, d2)
+
+
+# --------------------------------------------------------------------------
+# P24: a reflecting wall equals the mirror-symmetric extension of the problem
+# --------------------------------------------------------------------------
+def _mirror_case(kind, axis):
+    """(full spec, full q, full aux, half spec, odd components) with data
+    even across the plane {x = 0} (axis 0) or {y = 0} (axis 1)."""
+    rng = np.random.default_rng(13)
+    n = 24
+    if kind == "sw":
+        riem, m, odd, extra = "sw_roe", 3, (1 + axis,), dict(problem_data=[1.0], entropy_fix=1)
+    elif kind == "euler":
+        riem, m, odd, extra = "euler_hlle", 4, (1 + axis,), dict(problem_data=[1.4], scheme="sharpclaw",
+                                                                 limiter="none", transverse=0,
+                                                                 cfl_desired=0.5, cfl_max=0.6)
+    elif kind == "psys":
+        riem, m, odd, extra = "psystem", 3, (1 + axis,), dict(scheme="sharpclaw", limiter="none",
+                                                              transverse=0, time_integrator="ssp104",
+                                                              cfl_desired=2.45, cfl_max=2.5)
+    else:   # elastic: q = (s11, s22, s12, u, v); s12 and the normal velocity flip
+        riem, m, odd, extra = "elastic_vc", 5, (2, 3 + axis), dict()
+    lo = [-1.0, 0.0] if axis == 0 else [0.0, -1.0]
+    hi = [1.0, 1.0]
+    nc = [2 * n, n] if axis == 0 else [n, 2 * n]
+    full = dict(ndim=2, num_cells=tuple(nc), lower=tuple(lo), upper=tuple(hi), scheme="classic",
+                riemann=riem, limiter="mc", transverse=2, entropy_fix=0,
+                bc_lower=("extrap", "extrap"), bc_upper=("extrap", "extrap"), cfl_desired=0.8,
+                cfl_max=0.9)
+    full.update(extra)
+    half = dict(full, num_cells=(n, n), lower=(0.0, 0.0))
+    bl = list(half["bc_lower"]); bl[axis] = "wall"; half["bc_lower"] = tuple(bl)
+    # smooth random data on the half, mirrored
+    shape = (m, n, n)
+    base = {"sw": [1.0, 0, 0], "euler": [1.0, 0, 0, 2.5], "psys": [0.02, 0, 0], "elastic": [0] * 5}[kind]
+    amp = {"sw": 0.2, "euler": 0.1, "psys": 0.02, "elastic": 0.3}[kind]
+    h = np.array(base, float)[:, None, None] + amp * rng.random(shape)
+    if kind == "euler":   # keep E consistent with a positive pressure
+        h[3] += 0.5 * (h[1] ** 2 + h[2] ** 2) / h[0]
+    flip = np.ones(m)
+    flip[list(odd)] = -1.0
+    mir = np.flip(h, axis=2 - axis) * flip[:, None, None]
+    qf = np.concatenate([mir, h], axis=2 - axis)
+    aux_h = None
+    if kind == "elastic":
+        aux_h = np.stack([1.0 + rng.random((n, n)), 1.0 + 2 * rng.random((n, n)), 1.0 + rng.random((n, n))])
+    elif kind == "psys":
+        aux_h = np.stack([1.0 + 4 * rng.random((n, n)), 1.0 + 4 * rng.random((n, n))])
+    aux_f = None if aux_h is None else np.concatenate([np.flip(aux_h, axis=2 - axis), aux_h], axis=2 - axis)
+    return full, qf, aux_f, half, h, aux_h
+
+
+@pytest.mark.parametrize("kind", ["sw", "euler", "psys", "elastic"])
+@pytest.mark.parametrize("axis", [0, 1])
+def test_wall_equals_mirror_extension(kind, axis):
+    full, qf, aux_f, half, qh, aux_h = _mirror_case(kind, axis)
+    dt = 0.004 if kind != "psys" else 0.01
+    for _ in range(6):
+        qf, _ = oracle.step(full, qf, dt, aux=aux_f)
+        qh, _ = oracle.step(half, qh, dt, aux=aux_h)
+    n = qh.shape[1]
+    right = qf[:, :, n:] if axis == 0 else qf[:, n:, :]
+    sc = np.max(np.abs(right), axis=(1, 2)).max()
+    np.testing.assert_allclose(qh, right, rtol=0, atol=1e-13 * sc)
