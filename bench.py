@@ -44,9 +44,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch from the committed rocprofv3 PMC summary, or None
-    if the kernels changed since the counters were taken."""
+def measured_counters(kernel: str, field: str):
+    """A per-launch figure of a kernel from the committed rocprofv3 PMC
+    summary (profiles/traffic.json), or None if the kernels changed since the
+    counters were taken."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(p) as f:
@@ -56,7 +57,12 @@ def measured_traffic(kernel: str):
     if d.get("source_hash") != kernel_source_hash():
         return None
     v = d.get("kernels", {}).get(kernel)
-    return None if v is None else v.get("bytes_per_launch")
+    return None if v is None else v.get(field)
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated), or None."""
+    return measured_counters(kernel, "bytes_per_launch")
 
 
 def timed_run(spec, q, aux, steps, warmup, t_end, tune=True, graph_k=16):
@@ -143,7 +149,8 @@ def roofline(bound, cells, gpu_ms, launches, kernel_name, bytes_per_launch, flop
     gbs = bytes_per_launch / avg_s / 1e9
     tr = measured_traffic(kernel_name)
     out = dict(kernel=kernel_name, avg_launch_us=round(avg_s * 1e6, 2),
-               algorithmic_bytes_per_launch=bytes_per_launch, traffic=tr)
+               algorithmic_bytes_per_launch=bytes_per_launch, traffic=tr,
+               valu_issue_share=measured_counters(kernel_name, "valu_issue_share"))
     if bound == "alu":
         tf = flops_per_launch / avg_s / 1e12
         peak = PEAK_TFLOPS[dtype]
