@@ -24,9 +24,9 @@
  *                     normal Riemann problems only in 2D; higher WENO
  *                     orders from generated coefficients).
  *
- * Ghost cells carry the boundary conditions (Section 5, "Parallelization");
+ * Ghost cells carry the boundary conditions (Section 4, "Parallelization");
  * after each step the Courant number is checked and the next step size is
- * chosen (Section 5, the single reduction of the maximum wave speed).
+ * chosen (Section 4, the single reduction of the maximum wave speed).
  *
  * Conventions
  * -----------
@@ -86,7 +86,7 @@ enum claw_riemann {
                              with its transverse solver, problem_data = (gamma); m = 3 (1D) or
                              4 (2D), plus one with a tracer; optional Harten-Hyman entropy fix;
                              classic only */
-  CLAW_RP_PSYSTEM = 6     /* nonlinear p-system in a varying medium (Section 7.4, eq. p-system):
+  CLAW_RP_PSYSTEM = 6     /* nonlinear p-system in a varying medium (Section 7.3, eq. p-system):
                              q = (strain, rho u[, rho v]), m = 2 (1D) or 3 (2D); aux = (K, rho)
                              per cell; stress exp(K strain) - 1; f-wave interface flux (each side
                              in its own material); SharpClaw only */

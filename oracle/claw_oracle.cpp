@@ -128,7 +128,7 @@ struct Field {
   double at(int k, int j, int i) const { return v[((size_t)k * NY + (j + gy)) * NX + (i + g)]; }
 };
 
-// Ghost cells (Section 5, "Parallelization": ghost layers set from the boundary
+// Ghost cells (Section 4, "Parallelization": ghost layers set from the boundary
 // conditions before each step).  x ghosts are filled for interior rows first;
 // then y ghosts for every column, ghost columns included, so a corner ghost is
 // the y-boundary image of an x-ghost.
@@ -221,7 +221,7 @@ void rp_advection(const OCfg& c, int d, const double* ql, const double* qr, Face
 }
 
 // Shallow water, Roe linearisation (LeVeque 2002, ch. 15; the "Roe solver
-// with an entropy fix" of the paper's serial timing study, Section 6).
+// with an entropy fix" of the paper's serial timing study, Section 5).
 // q = (h, hu) in 1D, (h, hu, hv) in 2D.  Components: 0 depth, n normal
 // momentum, t tangential momentum.
 struct RoeSW {
@@ -1173,7 +1173,7 @@ double flux_advection(const OCfg& c, int d, const double* ql, const double* qr, 
   return std::fabs(u);
 }
 
-// Nonlinear p-system with spatially varying coefficients (Section 7.4,
+// Nonlinear p-system with spatially varying coefficients (Section 7.3,
 // eq. p-system): q = (strain eps, x-momentum rho u, y-momentum rho v), aux =
 // (bulk modulus K, density rho) per cell, stress sigma(eps) = exp(K eps) - 1
 // (eq. nonlinear const relation up to its additive constant, which cancels
@@ -1473,7 +1473,7 @@ double or_max_cell_speed(const OCfg* c, const double* q, const double* aux) {
   return max_cell_speed(*c, q, aux);
 }
 
-// Time-step controller (Section 5: after each step the Courant number is
+// Time-step controller (Section 4: after each step the Courant number is
 // checked against the stability limit and the next step size is chosen).
 //   dt_try = min(dt, t_end - t); step; C = dt_try * speed;
 //   C <= cfl_max: accept (t = t_end exactly on the clipped step), else keep Q^n;

@@ -10,7 +10,7 @@ constexpr int kLanes = 64;        // one wavefront per workgroup in the marching
 constexpr int kMaxEqn = 5;
 constexpr int kMaxAux = 3;
 
-// Device-resident step controller of one grid (Section 5: after each step
+// Device-resident step controller of one grid (Section 4: after each step
 // the Courant number is checked and the next step size chosen).
 struct Ctrl {
   unsigned int counter;           // speed slots of the current launch that are complete

@@ -98,7 +98,7 @@ struct Advection {
 
 // ---------------------------------------------------------------------------
 // Shallow water, Roe linearisation with an optional Harten-Hyman entropy fix
-// (the Roe solver with an entropy fix of the paper's Section 6; formulas as
+// (the Roe solver with an entropy fix of the paper's Section 5; formulas as
 // in LeVeque 2002, ch. 15).  q = (h, hu) in 1D, (h, hu, hv) in 2D.  Families:
 // 0 = left acoustic (u-c), [1 = shear (u), 2D only], last = right acoustic
 // (u+c).
@@ -763,7 +763,7 @@ struct EulerHLLE {
   }
 };
 
-// Nonlinear p-system with spatially varying coefficients (Section 7.4,
+// Nonlinear p-system with spatially varying coefficients (Section 7.3,
 // eq. p-system), q = (strain eps, rho u[, rho v]), aux = (K, rho) per cell,
 // stress sigma = exp(K eps) - 1.  Interface flux from the f-wave split of
 // the flux jump (left-going wave on the left material's eigenvector

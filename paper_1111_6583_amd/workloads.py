@@ -13,9 +13,9 @@ formulas; these stand in for them at the sizes the benchmark configurations
 name):
 
 * 1D shallow-water dam break (the paper's serial study uses a shallow-water
-  Roe solver with an entropy fix, Section 6);
+  Roe solver with an entropy fix, Section 5);
 * 2D radial dam break;
-* 2D Euler shock-bubble (Section 7.3: planar shock into a low-density bubble;
+* 2D Euler shock-bubble (Section 7.2: planar shock into a low-density bubble;
   here planar geometry, no tracer);
 * 2D linear elasticity in a seeded layered medium;
 * a Poisson trace of shallow-water solves for the serving loop.
@@ -156,7 +156,7 @@ def _bubble_fraction(x, y, dx, dy, center, radius, sub):
 
 
 # ---------------------------------------------------------------------------
-# The paper's classic shock-bubble run (Section 7, eq. euler-rz): axisymmetric
+# The paper's classic shock-bubble run (Section 7.2, eq. euler-rz): axisymmetric
 # Euler on [0,2] x [0,0.5] (x = axial z, y = radius r), a planar shock moving
 # in +z into still gas (rho = p = 1) holding a spherical bubble (rho = 0.1,
 # p = 1) centred on the axis; a tracer is 1 in the bubble.  The post-shock
