@@ -932,43 +932,50 @@ void weno5(const double* v, double eps, double* qL, double* qR) {
 //     constant a_0 does not enter): beta_k = sum_{n,m>=1} H_nm a_n a_m with
 //     H_nm = sum_l (n!/(n-l)!) (m!/(m-l)!) integral of x^(n+m-2l);
 //   * omega_k = alpha_k / sum alpha, alpha_k = d_k / (eps + beta_k)^2.
-// The tables are computed once per r, in long double, by solving the small
-// interpolation systems and integrating the squared derivatives exactly.
+// The tables are computed once per r, in extended precision, by solving the
+// small interpolation systems and integrating the squared derivatives exactly.
 // ---------------------------------------------------------------------------
 struct WenoTables {
   int r = 0;
-  double cR[9][9], cL[9][9];   // [k][j]: value at +1/2 / -1/2 from data of stencil k, j = 0..r-1
-  double d[9];                 // linear weights, right edge
-  double A[9][9][9];           // [k][n][j]: monomial coefficient a_n of candidate k from its data
-  double H[9][9];              // [n][m]: beta = sum_{n,m >= 1} H a_n a_m
+  long double cR[9][9], cL[9][9];   // [k][j]: value at +1/2 / -1/2 from data of stencil k, j = 0..r-1
+  double d[9];                      // linear weights, right edge
+  long double A[9][9][9];           // [k][n][j]: monomial coefficient a_n of candidate k from its data
+  long double H[9][9];              // [n][m]: beta = sum_{n,m >= 1} H a_n a_m
 };
+
+// The tables are built in binary128 (__float128, 113-bit significand): the
+// monomial interpolation systems are ill-conditioned at high order (in
+// long double the order-17 linear weights came out 3e-11 off their exact
+// rational values); they are then stored in long double.
+using Wide = __float128;
+static Wide wabs(Wide x) { return x < 0 ? -x : x; }
 
 // Coefficients a_n of p(x) = sum a_n x^n (n < r) from r cell averages at
 // cells c0 .. c0+r-1 (cell j = [j-1/2, j+1/2]): returns the matrix M with
 // a = M v.
-static void interp_matrix(int r, int c0, long double M[9][9]) {
-  long double A[9][18];
+static void interp_matrix(int r, int c0, Wide M[9][9]) {
+  Wide A[9][18];
   for (int row = 0; row < r; ++row) {
-    const long double lo = c0 + row - 0.5L, hi = c0 + row + 0.5L;
-    long double plo = lo, phi = hi;   // lo^(n+1), hi^(n+1)
+    const Wide lo = c0 + row - Wide(0.5), hi = c0 + row + Wide(0.5);
+    Wide plo = lo, phi = hi;   // lo^(n+1), hi^(n+1)
     for (int n = 0; n < r; ++n) {
       A[row][n] = (phi - plo) / (n + 1);
       plo *= lo;
       phi *= hi;
     }
-    for (int n = 0; n < r; ++n) A[row][r + n] = row == n ? 1.0L : 0.0L;
+    for (int n = 0; n < r; ++n) A[row][r + n] = row == n ? Wide(1) : Wide(0);
   }
   // Gauss-Jordan with partial pivoting: A = [V | I] -> [I | V^-1]
   for (int col = 0; col < r; ++col) {
     int piv = col;
     for (int row = col + 1; row < r; ++row)
-      if (std::fabs(A[row][col]) > std::fabs(A[piv][col])) piv = row;
+      if (wabs(A[row][col]) > wabs(A[piv][col])) piv = row;
     for (int n = 0; n < 2 * r; ++n) std::swap(A[col][n], A[piv][n]);
-    const long double inv = 1.0L / A[col][col];
+    const Wide inv = Wide(1) / A[col][col];
     for (int n = 0; n < 2 * r; ++n) A[col][n] *= inv;
     for (int row = 0; row < r; ++row) {
       if (row == col) continue;
-      const long double f = A[row][col];
+      const Wide f = A[row][col];
       for (int n = 0; n < 2 * r; ++n) A[row][n] -= f * A[col][n];
     }
   }
@@ -976,8 +983,8 @@ static void interp_matrix(int r, int c0, long double M[9][9]) {
     for (int j = 0; j < r; ++j) M[n][j] = A[n][r + j];
 }
 
-static long double poly_at(int r, const long double* a, long double x) {
-  long double s = 0.0L;
+static Wide poly_at(int r, const Wide* a, Wide x) {
+  Wide s = Wide(0);
   for (int n = r - 1; n >= 0; --n) s = s * x + a[n];
   return s;
 }
@@ -990,74 +997,76 @@ static const WenoTables& weno_tables(int r) {
 #pragma omp critical(weno_tables)
   if (!done[r]) {
     t.r = r;
-    long double cR[9][9], cL[9][9];
+    Wide cR[9][9], cL[9][9];
     for (int k = 0; k < r; ++k) {
-      long double M[9][9];
+      Wide M[9][9];
       interp_matrix(r, -(r - 1) + k, M);
       for (int j = 0; j < r; ++j) {
-        long double a[9];
+        Wide a[9];
         for (int n = 0; n < r; ++n) a[n] = M[n][j];
-        cR[k][j] = poly_at(r, a, 0.5L);
-        cL[k][j] = poly_at(r, a, -0.5L);
-        t.cR[k][j] = (double)cR[k][j];
-        t.cL[k][j] = (double)cL[k][j];
+        cR[k][j] = poly_at(r, a, Wide(0.5));
+        cL[k][j] = poly_at(r, a, -Wide(0.5));
+        t.cR[k][j] = (long double)cR[k][j];
+        t.cL[k][j] = (long double)cL[k][j];
       }
       for (int n = 0; n < r; ++n)
-        for (int j = 0; j < r; ++j) t.A[k][n][j] = (double)M[n][j];
+        for (int j = 0; j < r; ++j) t.A[k][n][j] = (long double)M[n][j];
     }
     // Gram matrix of the derivatives of the monomials: integral over the cell
     // of sum_l d^l x^n d^l x^m
     for (int n = 1; n < r; ++n)
       for (int m = 1; m < r; ++m) {
-        long double sum = 0.0L;
+        Wide sum = Wide(0);
         for (int l = 1; l <= std::min(n, m); ++l) {
-          long double fn = 1.0L, fm = 1.0L;   // n!/(n-l)!, m!/(m-l)!
+          Wide fn = Wide(1), fm = Wide(1);   // n!/(n-l)!, m!/(m-l)!
           for (int q = 0; q < l; ++q) { fn *= (n - q); fm *= (m - q); }
           const int e = (n - l) + (m - l);
-          sum += fn * fm * (std::pow(0.5L, e + 1) - std::pow(-0.5L, e + 1)) / (e + 1);
+          Wide h = Wide(1);   // (1/2)^(e+1); the integral of x^e over [-1/2, 1/2]
+          for (int q = 0; q <= e; ++q) h *= Wide(0.5);
+          sum += fn * fm * (e % 2 == 0 ? 2 * h : Wide(0)) / (e + 1);
         }
-        t.H[n][m] = (double)sum;
+        t.H[n][m] = (long double)sum;
       }
     // big stencil: degree 2r-2 through the averages of cells -(r-1) .. r-1
     const int R2 = 2 * r - 1;
-    long double big[17];
+    Wide big[17];
     {
-      long double A[17][34];
+      Wide A[17][34];
       for (int row = 0; row < R2; ++row) {
-        const long double lo = -(r - 1) + row - 0.5L, hi = -(r - 1) + row + 0.5L;
-        long double plo = lo, phi = hi;
+        const Wide lo = -(r - 1) + row - Wide(0.5), hi = -(r - 1) + row + Wide(0.5);
+        Wide plo = lo, phi = hi;
         for (int n = 0; n < R2; ++n) {
           A[row][n] = (phi - plo) / (n + 1);
           plo *= lo;
           phi *= hi;
         }
-        for (int n = 0; n < R2; ++n) A[row][R2 + n] = row == n ? 1.0L : 0.0L;
+        for (int n = 0; n < R2; ++n) A[row][R2 + n] = row == n ? Wide(1) : Wide(0);
       }
       for (int col = 0; col < R2; ++col) {
         int piv = col;
         for (int row = col + 1; row < R2; ++row)
-          if (std::fabs(A[row][col]) > std::fabs(A[piv][col])) piv = row;
+          if (wabs(A[row][col]) > wabs(A[piv][col])) piv = row;
         for (int n = 0; n < 2 * R2; ++n) std::swap(A[col][n], A[piv][n]);
-        const long double inv = 1.0L / A[col][col];
+        const Wide inv = Wide(1) / A[col][col];
         for (int n = 0; n < 2 * R2; ++n) A[col][n] *= inv;
         for (int row = 0; row < R2; ++row) {
           if (row == col) continue;
-          const long double f = A[row][col];
+          const Wide f = A[row][col];
           for (int n = 0; n < 2 * R2; ++n) A[row][n] -= f * A[col][n];
         }
       }
       // value at +1/2 as a functional of the data: sum_n (1/2)^n M[n][j]
       for (int j = 0; j < R2; ++j) {
-        long double s = 0.0L, x = 1.0L;
-        for (int n = 0; n < R2; ++n) { s += x * A[n][R2 + j]; x *= 0.5L; }
+        Wide s = Wide(0), x = Wide(1);
+        for (int n = 0; n < R2; ++n) { s += x * A[n][R2 + j]; x *= Wide(0.5); }
         big[j] = s;
       }
     }
     // consistency: sum_k d_k cR[k][j - k] = big[j]; data cell j of the big
     // stencil is cell j - k of candidate k.  Triangular in k for j < r.
-    long double dd[9];
+    Wide dd[9];
     for (int j = 0; j < r; ++j) {
-      long double s = big[j];
+      Wide s = big[j];
       for (int k = 0; k < j; ++k) s -= dd[k] * cR[k][j - k];
       dd[j] = s / cR[j][0];
     }
@@ -1068,24 +1077,28 @@ static const WenoTables& weno_tables(int r) {
 }
 
 // Candidate k's edge values and smoothness indicator from its r averages s[].
+// Evaluated in long double: the monomial coefficients of a high-degree
+// candidate are sums of large terms of both signs, and the quadratic form of
+// the indicator loses further digits to cancellation (in double, about 4e-12
+// of an edge value at order 17 against an exact evaluation).
 static void weno_candidate(const WenoTables& t, int k, const double* s, double* pR, double* pL,
                            double* beta) {
   const int r = t.r;
-  double a = 0.0, c = 0.0, an[9];
+  long double a = 0.0L, c = 0.0L, an[9];
   for (int i = 0; i < r; ++i) {
     a += t.cR[k][i] * s[i];
     c += t.cL[k][i] * s[i];
   }
   for (int n = 1; n < r; ++n) {
-    an[n] = 0.0;
+    an[n] = 0.0L;
     for (int i = 0; i < r; ++i) an[n] += t.A[k][n][i] * s[i];
   }
-  double b = 0.0;
+  long double b = 0.0L;
   for (int n = 1; n < r; ++n)
     for (int m = 1; m < r; ++m) b += t.H[n][m] * an[n] * an[m];
-  *pR = a;
-  *pL = c;
-  *beta = b;
+  *pR = (double)a;
+  *pL = (double)c;
+  *beta = (double)b;
 }
 
 // Edge values of cell i from the 2r-1 averages v[0..2r-2] centred on it

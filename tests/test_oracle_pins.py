@@ -335,57 +335,71 @@ def test_weno_r3_equals_weno5_closed_form():
 
 
 def test_weno_linear_weights_published():
-    # Jiang-Shu (fifth order) and Balsara-Shu (seventh order) optimal weights
+    # Jiang-Shu (fifth order), Balsara-Shu (seventh and ninth order) optimal
+    # weights, and for every order the closed form
+    # d_k = C(r, k) C(r-1, k) / C(2r-1, r-1) that these tables follow
     np.testing.assert_allclose(oracle.weno_linear_weights(3), [0.1, 0.6, 0.3], rtol=0, atol=1e-15)
     np.testing.assert_allclose(oracle.weno_linear_weights(4), np.array([1, 12, 18, 4]) / 35.0,
                                rtol=0, atol=1e-15)
+    np.testing.assert_allclose(oracle.weno_linear_weights(5),
+                               [1 / 126, 10 / 63, 10 / 21, 20 / 63, 5 / 126], rtol=1e-15, atol=0)
     for r in range(3, 10):
         d = oracle.weno_linear_weights(r)
+        closed = np.array([math.comb(r, k) * math.comb(r - 1, k) for k in range(r)],
+                          dtype=float) / math.comb(2 * r - 1, r - 1)
+        np.testing.assert_allclose(d, closed, rtol=2e-15, atol=0)
         assert d.sum() == pytest.approx(1.0, abs=1e-13) and (d > 0).all()
         if r > 2:
             assert d[0] < d[1]   # the most upwind-far stencil gets the least weight
 
 
-@pytest.mark.parametrize("r", [3, 4, 5, 6, 7])
+def _scaled_poly(rng, deg, r):
+    """Random polynomial of degree deg whose terms stay of order one over a
+    stencil of half-width r - 1/2 (coefficient n scaled by (r - 1)^-n), so
+    that its cell averages are computed in double without cancellation."""
+    return rng.normal(size=deg + 1) / float(max(r - 1, 1)) ** np.arange(deg + 1)
+
+
+@pytest.mark.parametrize("r", [3, 4, 5, 6, 7, 8, 9])
 def test_weno_r_candidate_exactness(r):
     # averages of a polynomial of degree r-1: every candidate is exact, so the
     # edge values are exact whatever the nonlinear weights are
     rng = np.random.default_rng(r)
-    poly = rng.normal(size=r)
+    poly = _scaled_poly(rng, r - 1, r)
     v = _cell_averages(poly, range(-(r - 1), r))
     qL, qR = oracle.weno_r(r, v, 1e-6)
     pv = lambda x: np.polynomial.polynomial.polyval(x, poly)
-    assert qL == pytest.approx(pv(0.5), rel=1e-9, abs=1e-9)
-    assert qR == pytest.approx(pv(-0.5), rel=1e-9, abs=1e-9)
+    assert qL == pytest.approx(pv(0.5), rel=1e-12, abs=1e-12)
+    assert qR == pytest.approx(pv(-0.5), rel=1e-12, abs=1e-12)
 
 
-@pytest.mark.parametrize("r", [3, 4, 5])
+@pytest.mark.parametrize("r", [3, 4, 5, 6, 7, 8, 9])
 def test_weno_r_linear_limit_is_full_stencil_exact(r):
     # with eps >> beta the weights are the linear ones, and the reconstruction
     # is the degree-(2r-2) interpolation of the whole stencil: exact for such
     # polynomials (pins the linear weights against the candidate tables)
     rng = np.random.default_rng(10 + r)
-    poly = rng.normal(size=2 * r - 1)
+    poly = _scaled_poly(rng, 2 * r - 2, r)
     v = _cell_averages(poly, range(-(r - 1), r))
     qL, qR = oracle.weno_r(r, v, 1e20)
     pv = lambda x: np.polynomial.polynomial.polyval(x, poly)
-    assert qL == pytest.approx(pv(0.5), rel=1e-8, abs=1e-8)
-    assert qR == pytest.approx(pv(-0.5), rel=1e-8, abs=1e-8)
+    assert qL == pytest.approx(pv(0.5), rel=1e-11, abs=1e-11)
+    assert qR == pytest.approx(pv(-0.5), rel=1e-11, abs=1e-11)
     # and not for degree 2r-1
-    poly2 = np.concatenate([poly, [1.0]])
+    poly2 = np.concatenate([poly, [float(r - 1) ** -(2 * r - 2)]])
     v2 = _cell_averages(poly2, range(-(r - 1), r))
     qL2, _ = oracle.weno_r(r, v2, 1e20)
-    assert abs(qL2 - np.polynomial.polynomial.polyval(0.5, poly2)) > 1e-6
+    assert abs(qL2 - np.polynomial.polynomial.polyval(0.5, poly2)) > 1e-9
 
 
-@pytest.mark.parametrize("r", [3, 4, 5, 6])
+@pytest.mark.parametrize("r", [3, 4, 5, 6, 7, 8, 9])
 def test_weno_r_smoothness_indicator_closed_form(r):
     # data = averages of a polynomial p of degree r-1: every candidate is p,
     # so every beta_k is sum_{l=1}^{r-1} of the integral over the cell of
     # (p^(l))^2 (Jiang-Shu), computed here with numpy's polynomial calculus
     P = np.polynomial.polynomial
     rng = np.random.default_rng(20 + r)
-    poly = rng.normal(size=r)
+    poly = _scaled_poly(rng, r - 1, r)
     v = _cell_averages(poly, range(-(r - 1), r)) + 7.0   # an offset does not change beta
     ref = 0.0
     for l in range(1, r):
@@ -393,7 +407,7 @@ def test_weno_r_smoothness_indicator_closed_form(r):
         sq = P.polyint(P.polymul(d, d))
         ref += P.polyval(0.5, sq) - P.polyval(-0.5, sq)
     beta = oracle.weno_smoothness(r, v)
-    np.testing.assert_allclose(beta, ref, rtol=1e-9)
+    np.testing.assert_allclose(beta, ref, rtol=1e-10)
 
 
 def test_weno5_smoothness_indicators_jiang_shu_closed_form():
