@@ -112,7 +112,12 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 #   160/3 (FP32+Kahan); elastic 104 (FP64), 92 (FP32+Kahan) per cell-step.
 #   euler_stage_weno7  the same with WENO7: edge pair per component and
 #            direction 200 (candidates 56, smoothness indicators 96, weights
-#            and normalisation 48) -> 8 x 200 + 204 + 20 + 12 + 2 = 1840
+#            and normalisation 48) -> 8 x 200 + 204 + 20 + 12 + 2 = 1838
+#   euler_stage WENO of order 2r-1, r >= 4: edge pair = candidates 2r(2r-1)
+#            + smoothness indicators r(r^2 + 3r - 4) (r - 1 zero-sum rows of
+#            r, r-1, ..., 2 nonzeros, squared, weighted, summed) + weights and
+#            normalisation (48 at r = 4; 11r + 2 with one reciprocal per
+#            candidate above) -> 8 x edge pair + 238 (r = 5: 2854, r = 9: 10982)
 #   SSPRK(10,4) stage bytes, FP64, averaged over the ten stages: eight plain
 #   stages 64 B (S in, y out), stage 5 128 B (S, Q in; two registers out),
 #   stage 10 96 B (S, S3 in; Q out) -> 73.6 B per cell-stage.
@@ -134,8 +139,18 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 #            out, 2 aux), stage 5 112 B, stage 10 88 B -> 71.2 B; FP32+Kahan
 #            plain 32 B, stage 5 56 B, stage 10 80 B (Q and its compensation
 #            in and out) -> 39.2 B
-FLOPS_PER_CELL = {"sw": 554.0, "euler_stage": 1040.0, "euler_stage_weno7": 1840.0,
+FLOPS_PER_CELL = {"sw": 554.0, "euler_stage": 1040.0, "euler_stage_weno7": 1838.0,
                   "euler_roe": 1160.0, "sw_sweep": 173.0, "psystem_stage": 696.0}
+
+
+def euler_stage_flops(order: int) -> float:
+    """Algorithmic flops per cell and stage of the 2D Euler SharpClaw step
+    with WENO of the given order (the counts above)."""
+    if order == 5:
+        return FLOPS_PER_CELL["euler_stage"]
+    r = (order + 1) // 2
+    pair = 2 * r * (2 * r - 1) + r * (r * r + 3 * r - 4) + (48 if r == 4 else 11 * r + 2)
+    return 8.0 * pair + 238.0
 
 
 def roofline(bound, cells, gpu_ms, launches, kernel_name, bytes_per_launch, flops_per_launch=None,
@@ -387,16 +402,14 @@ def main():
                 r["l1_err_sample"] = "256x128 to t=0.1 (shock through the bubble), oracle dt sequence"
             extras[f"euler_shock_bubble_2048x1024_{prec}"] = r
 
-        log("shock-bubble 2048x1024 SharpClaw SSPRK(10,4) (the SharpClaw default), WENO5 / WENO7")
-        for order in (5, 7):
+        log("shock-bubble 2048x1024 SharpClaw SSPRK(10,4) (the SharpClaw default), WENO5/7/9/17")
+        for order in (5, 7, 9, 17):
             spec104 = dict(sb_spec, time_integrator="ssp104", weno_order=order, cfl_desired=2.45,
                            cfl_max=2.5)
             r = timed_run(spec104, sb_q, None, 10, 2, 1.0)
             r["roofline"] = roofline("alu", r["cells"], r["gpu_ms"], 10 * (r["steps"] + r["rejected"]),
                                      "k_sharp2d<double,EulerHLLE,SSPRK104>",
-                                     73.6 * r["cells"],
-                                     (FLOPS_PER_CELL["euler_stage"] if order == 5 else
-                                      FLOPS_PER_CELL["euler_stage_weno7"]) * r["cells"], "f64")
+                                     73.6 * r["cells"], euler_stage_flops(order) * r["cells"], "f64")
             r["cfl"] = [2.45, 2.5]
             extras[f"euler_shock_bubble_2048x1024_fp64_ssp104_weno{order}"] = r
 

@@ -14,8 +14,8 @@
  *                     first-order part as fluctuations), and in 2D the
  *                     unsplit transverse corrections from a secondary
  *                     Riemann solver (Section 2.1);
- *   CLAW_SHARPCLAW -- the SharpClaw method of lines: WENO edge values (fifth
- *                     or seventh order), an interface Riemann flux, flux
+ *   CLAW_SHARPCLAW -- the SharpClaw method of lines: WENO edge values (any
+ *                     odd order from 5 to 17), an interface Riemann flux, flux
  *                     differencing (Section 2, eq. fluxdiff), inside the
  *                     stages of an SSP Runge-Kutta method: SSPRK(3,3), or
  *                     the ten-stage fourth-order SSP method (Ketcheson 2008,
@@ -140,8 +140,10 @@ typedef struct claw_config {
   int precision;         /* claw_precision */
   double problem_data[8];
   int time_integrator;   /* SharpClaw: claw_integrator (0 = CLAW_SSP33); ignored by classic */
-  int weno_order;        /* SharpClaw: 5 or 7 (0 = 5); ignored by classic.  Any other value:
-                            CLAW_E_INVAL */
+  int weno_order;        /* SharpClaw: odd order 5..17 of the WENO edge values (0 = 5; Section 3.3:
+                            generated reconstructions from fifth to seventeenth order); needs
+                            (order + 1) / 2 <= num_cells in each dimension.  Ignored by classic.
+                            Any other value: CLAW_E_INVAL */
   int tracer;            /* CLAW_RP_EULER_ROE: 1 adds a passive tracer as the last component,
                             advected by the flow (q_t + u phi_x + v phi_y = 0); else 0 */
   int source;            /* claw_source (0 = none) */

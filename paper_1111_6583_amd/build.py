@@ -20,7 +20,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libclaw.so")
-SOURCES = ["claw.cpp", "k_classic.hip", "k_sharp.hip", "k_split.hip", "k_util.hip"]
+SOURCES = ["claw.cpp", "k_classic.hip", "k_sharp.hip", "k_split.hip", "k_util.hip",
+           "k_sharp_weno9.hip", "k_sharp_weno11.hip", "k_sharp_weno13.hip",
+           "k_sharp_weno15.hip", "k_sharp_weno17.hip"]
 ARCH = "gfx950"
 
 

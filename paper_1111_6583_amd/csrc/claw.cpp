@@ -116,7 +116,11 @@ int validate(const claw_config* c) {
     if (c->time_integrator != 0 && c->time_integrator != CLAW_SSP33 &&
         c->time_integrator != CLAW_SSP104)
       return CLAW_E_INVAL;
-    if (c->weno_order != 0 && c->weno_order != 5 && c->weno_order != 7) return CLAW_E_INVAL;
+    if (c->weno_order != 0 && (c->weno_order < 5 || c->weno_order > 17 || c->weno_order % 2 == 0))
+      return CLAW_E_INVAL;
+    // the r = (order + 1) / 2 ghost layers map to interior cells (wrap or mirror once)
+    const int r = c->weno_order == 0 ? 3 : (c->weno_order + 1) / 2;
+    if (c->num_cells[0] < r || (c->ndim == 2 && c->num_cells[1] < r)) return CLAW_E_INVAL;
     if (c->dimensional_split != CLAW_SPLIT_NONE) return CLAW_E_INVAL;
   } else {
     return CLAW_E_INVAL;
@@ -130,7 +134,7 @@ int validate(const claw_config* c) {
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int, int, int, int>, std::pair<int, int>> g_tune;
 
-int weno_r_of(const claw_config& c) { return c.weno_order == 7 ? 4 : 3; }
+int weno_r_of(const claw_config& c) { return c.weno_order >= 7 ? (c.weno_order + 1) / 2 : 3; }
 bool ssp104(const claw_config& c) { return c.time_integrator == CLAW_SSP104; }
 bool split(const claw_config& c) {
   return c.scheme == CLAW_CLASSIC && c.dimensional_split != CLAW_SPLIT_NONE;

@@ -89,9 +89,16 @@ def test_sharpclaw_integrator_and_weno_order_options():
     arr = m * 256 * 128 * 8
     # SSPRK(10,4) keeps one more state-sized register than SSPRK(3,3)
     assert arr <= n104 - n33 < arr + 4096
-    assert _bytes(dict(spec, weno_order=7))[0] == n33
-    for bad in (3, 6, 9):
+    for order in (7, 9, 11, 13, 15, 17):
+        assert _bytes(dict(spec, weno_order=order))[0] == n33
+    for bad in (-5, 1, 3, 4, 6, 8, 16, 19, 21):
         assert _bytes(dict(spec, weno_order=bad))[0] == 0
+    # the (order + 1) / 2 ghost layers must map to interior cells
+    small, _ = W.random_smooth_euler(9, seed=1)
+    assert _bytes(dict(small, weno_order=17))[0] > 0
+    assert _bytes(dict(small, weno_order=17, num_cells=(8, 9)))[0] == 0
+    assert _bytes(dict(small, weno_order=17, num_cells=(9, 8)))[0] == 0
+    assert _bytes(dict(small, weno_order=15, num_cells=(8, 8)))[0] > 0
     # classic ignores both
     sw, _ = W.radial_dam_break(64)
     assert _bytes(dict(sw, time_integrator="ssp104", weno_order=7))[0] == _bytes(sw)[0]
