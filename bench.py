@@ -272,6 +272,12 @@ def host_controller(spec, q, steps):
                 value=q.shape[1] * q.shape[2] * acc / wall)
 
 
+def _sb104(W, order):
+    spec, q = W.shock_bubble(2048, 1024)
+    return (dict(spec, time_integrator="ssp104", weno_order=order, cfl_desired=2.45, cfl_max=2.5),
+            q, None)
+
+
 WORKLOADS = {
     "sw": ("2D shallow water radial dam break 1024^2", lambda W: W.radial_dam_break(1024) + (None,)),
     "euler": ("2D Euler shock-bubble 2048x1024 SharpClaw", lambda W: W.shock_bubble(2048, 1024) + (None,)),
@@ -283,6 +289,10 @@ WORKLOADS = {
     "sw_godunov": ("2D shallow water radial dam break 1024^2, Godunov split",
                    lambda W: (dict(W.radial_dam_break(1024)[0], dimensional_split="godunov"),
                               W.radial_dam_break(1024)[1], None)),
+    "euler_weno9": ("2D Euler shock-bubble 2048x1024 SharpClaw SSPRK(10,4) WENO9",
+                    lambda W: _sb104(W, 9)),
+    "euler_weno17": ("2D Euler shock-bubble 2048x1024 SharpClaw SSPRK(10,4) WENO17",
+                     lambda W: _sb104(W, 17)),
     "sw_strang": ("2D shallow water radial dam break 1024^2, Strang split",
                   lambda W: (dict(W.radial_dam_break(1024)[0], dimensional_split="strang"),
                              W.radial_dam_break(1024)[1], None)),
@@ -408,7 +418,7 @@ def main():
                            cfl_max=2.5)
             r = timed_run(spec104, sb_q, None, 10, 2, 1.0)
             r["roofline"] = roofline("alu", r["cells"], r["gpu_ms"], 10 * (r["steps"] + r["rejected"]),
-                                     "k_sharp2d<double,EulerHLLE,SSPRK104>",
+                                     f"k_sharp2d<double,EulerHLLE,SSPRK104,WENO{order}>",
                                      73.6 * r["cells"], euler_stage_flops(order) * r["cells"], "f64")
             r["cfl"] = [2.45, 2.5]
             extras[f"euler_shock_bubble_2048x1024_fp64_ssp104_weno{order}"] = r
