@@ -149,7 +149,9 @@ def make_cfg(spec: dict) -> OCfg:
                 c.bcstate[s][k] = float(v)
     c.weno_eps = float(spec.get("weno_eps", 1e-6))
     c.integrator = INTEGRATORS[spec.get("time_integrator", "ssp33")]
-    c.weno_order = int(spec.get("weno_order", 5))
+    c.weno_order = int(spec.get("weno_order", 5)) or 5
+    if c.weno_order not in (5, 7, 9, 11, 13, 15, 17):
+        raise ValueError(f"weno_order {c.weno_order}: the oracle has WENO of odd orders 5..17")
     c.tracer = int(spec.get("tracer", 0))
     c.source = SOURCES[spec.get("source", "none")]
     c.split = SPLITS[spec.get("dimensional_split", "none")]
