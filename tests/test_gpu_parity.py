@@ -511,6 +511,42 @@ def test_sharpclaw_high_order_1d_planar_shock_device_controller(order):
     assert fp64_err(s.get_state(), qo, spec) <= rounding_tol(spec, q, dts)
 
 
+@pytest.mark.parametrize("order", [9, 17])
+def test_full_size_shock_bubble_high_order_window_one_step(order):
+    """The benchmark's grid (2048x1024, SSPRK(10,4), CFL 2.45) in the tiling
+    the autotuner picks: evolve on the GPU, take one more GPU step, and check
+    64x64 windows of it against the oracle run on the window plus a margin of
+    10 r + 2 cells (one step of ten stages depends on 10 r cells each way)."""
+    say("case: shock-bubble 2048x1024 WENO", order, "SSPRK(10,4), windowed one-step parity after 3 GPU steps")
+    spec, q = W.shock_bubble(2048, 1024)
+    spec = dict(spec, time_integrator="ssp104", weno_order=order, cfl_desired=2.45, cfl_max=2.5)
+    s = solver(spec, q)
+    s.autotune(reps=1)
+    s.advance(1.0, max_steps=3)
+    q1 = s.get_state()
+    dt = s.clock()["dt_next"]
+    s.step(dt)
+    g = s.get_state()
+    s.close()
+    nx, ny = spec["num_cells"]
+    h = (spec["upper"][0] - spec["lower"][0]) / nx
+    mg = 10 * (order + 1) // 2 + 2
+    for (j0, i0) in ((480, 180), (0, 0), (960, 1984), (300, 420)):
+        lo_j, hi_j = max(j0 - mg, 0), min(j0 + 64 + mg, ny)
+        lo_i, hi_i = max(i0 - mg, 0), min(i0 + 64 + mg, nx)
+        ws = dict(spec, num_cells=(hi_i - lo_i, hi_j - lo_j),
+                  lower=(spec["lower"][0] + lo_i * h, spec["lower"][1] + lo_j * h),
+                  upper=(spec["lower"][0] + hi_i * h, spec["lower"][1] + hi_j * h),
+                  bc_lower=(spec["bc_lower"][0] if lo_i == 0 else "extrap", "extrap"),
+                  bc_upper=("extrap", "extrap"))
+        qw = q1[:, lo_j:hi_j, lo_i:hi_i]
+        o, _ = oracle.step(ws, qw, dt)
+        oj, oi = j0 - lo_j, i0 - lo_i
+        ow = o[:, oj:oj + 64, oi:oi + 64]
+        gw = g[:, j0:j0 + 64, i0:i0 + 64]
+        assert fp64_err(gw, ow, spec) <= rounding_tol(ws, qw, [dt]), (j0, i0)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32_kahan"])
 def test_sharpclaw_weno17_tiling_does_not_change_results(prec):
     say("case: WENO17 SSPRK(10,4) seg_rows 3/16/100 bitwise equal", prec)
