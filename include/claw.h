@@ -190,30 +190,35 @@ int claw_num_aux(const claw_config* cfg);
 /* Exact device bytes claw_create needs for cfg (0 if cfg is invalid). */
 size_t claw_workspace_bytes(const claw_config* cfg);
 
-/* Validate cfg and build a handle over the caller's device buffer d_ws
+/* Validate cfg and build a handle (the solver and solution objects of the
+ * paper's interface, Section 3) over the caller's device buffer d_ws
  * (>= claw_workspace_bytes(cfg) bytes, 256-byte aligned, on the current
  * device).  hip_stream: a hipStream_t or NULL.  *out receives the handle. */
 int claw_create(const claw_config* cfg, void* d_ws, size_t ws_bytes, void* hip_stream,
                 claw_t* out);
 
-/* Copy the state in.  q: float64[m][ny][nx], host (on_device = 0) or device
+/* Copy the state in (a solution's q, Section 3; component first as there).
+ * q: float64[m][ny][nx], host (on_device = 0) or device
  * memory.  Resets the compensation terms (FP32 mode).  Does not touch the clock. */
 int claw_set_state(claw_t h, const double* q, int on_device);
 
-/* Copy the aux fields in (elasticity: rho, lambda, mu; p-system: K, rho), float64[na][ny][nx]. */
+/* Copy the aux fields in (Section 3: spatially varying coefficients; elasticity: rho, lambda,
+ * mu; p-system: K, rho, Section 7.3), float64[na][ny][nx]. */
 int claw_set_aux(claw_t h, const double* aux, int on_device);
 
 /* Copy the state out as float64[m][ny][nx] (FP32 mode: value minus
  * compensation, formed in float64). */
 int claw_get_state(claw_t h, double* q_out, int on_device);
 
-/* One step of exactly dt (no controller, no retry).  *courant_out (may be
+/* One step of exactly dt (the method of Section 2, eq. fluxdiff, in the
+ * configured form of Section 2.1; no controller, no retry).  *courant_out (may be
  * NULL) receives dt * max|wave speed|/spacing over the faces bounding
  * interior cells (SharpClaw: in the first stage).  The step is always
  * applied and the clock advances by dt. */
 int claw_step(claw_t h, double dt, double* courant_out);
 
-/* Advance to t_end with the step controller on the host (one 8-byte
+/* Advance to t_end with the step controller (Section 4: the Courant number
+ * is checked after every step and the next step size chosen) on the host (one 8-byte
  * device-to-host read per attempt):
  *   dt_try = min(dt, t_end - t); step; C = dt_try * speed;
  *   C <= cfl_max: accept (t = t_end exactly on the clipped step);
@@ -232,15 +237,17 @@ int claw_advance(claw_t h, double t_end, long long max_steps, claw_stats* st);
 int claw_advance_graph(claw_t h, double t_end, int steps_per_graph, long long max_steps,
                        claw_stats* st);
 
-/* Conserved totals: totals[k] = sum over cells of q_k * dx * dy, float64
+/* Conserved totals (Section 2, eq. conslaw: the quantities the finite-volume
+ * form conserves): totals[k] = sum over cells of q_k * dx * dy, float64
  * (FP32 mode: of value minus compensation). */
 int claw_totals(claw_t h, double* totals);
 
-/* Read / restore the clock (checkpointing). */
+/* Read / restore the clock (checkpointing; not a passage of the paper). */
 int claw_get_clock(claw_t h, claw_stats* st);
 int claw_set_clock(claw_t h, const claw_stats* st);
 
-/* Tiling of the 2D kernels; results are bitwise independent of it. */
+/* Tiling of the 2D kernels (an implementation parameter, not in the paper);
+ * results are bitwise independent of it. */
 int claw_set_tuning(claw_t h, const claw_tuning* tn);
 int claw_get_tuning(claw_t h, claw_tuning* tn);
 
@@ -261,7 +268,8 @@ int claw_time_kernel(claw_t h, double dt, int reps, double* avg_ms);
 int claw_destroy(claw_t h);
 
 /* ---------------------------------------------------------------------------
- * Batching: one launch advances every member grid by one attempt, each with
+ * Batching (for serving many small problems; not in the paper, whose
+ * controller of Section 4 each member runs): one launch advances every member grid by one attempt, each with
  * its own clock, dt controller and t_end.  Members must be classic 2D
  * handles with the same riemann solver, limiter, transverse mode and
  * precision, created on the same
