@@ -67,14 +67,16 @@ def dam_break_1d(n=1000, hl=2.0, hr=1.0, **kw):
 # ---------------------------------------------------------------------------
 # 2D radial dam break: [-2.5,2.5]^2, h=2 where the cell centre has r<0.5 else 1.
 # ---------------------------------------------------------------------------
-def radial_dam_break(n=1024, ny=None, **kw):
+def radial_dam_break(n=1024, ny=None, h_in=2.0, h_out=1.0, **kw):
+    """h_in where the cell centre has r < 0.5, h_out elsewhere (2 and 1 in the
+    benchmark; a deep column over a thin layer makes the collapse transonic)."""
     ny = n if ny is None else ny
     spec = _base(2, (n, ny), (-2.5, -2.5), (2.5, 2.5), "sw_roe", entropy_fix=1,
                  problem_data=[1.0], transverse=2, cfl_desired=0.9, cfl_max=1.0, **kw)
     x, y = centers(spec)
     X, Y = np.meshgrid(x, y)
     q = np.zeros((3, ny, n))
-    q[0] = np.where(X * X + Y * Y < 0.25, 2.0, 1.0)
+    q[0] = np.where(X * X + Y * Y < 0.25, h_in, h_out)
     return spec, q
 
 
