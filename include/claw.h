@@ -70,7 +70,8 @@ enum claw_status {
   CLAW_E_NONPHYSICAL = -5, /* non-finite Courant number (NaN/Inf in the state) */
   CLAW_E_BUDGET = -6,      /* batch: no free slot */
   CLAW_E_STATE = -7,       /* call order (e.g. stepping before claw_set_state) */
-  CLAW_E_MAXSTEPS = -8     /* claw_advance: max_steps attempts did not reach t_end */
+  CLAW_E_MAXSTEPS = -8,    /* claw_advance: max_steps attempts did not reach t_end */
+  CLAW_E_TOOBIG = -9       /* claw_step_static: the grid needs more than CLAW_STATIC_SCRATCH_BYTES */
 };
 
 enum claw_scheme { CLAW_CLASSIC = 1, CLAW_SHARPCLAW = 2 };
@@ -293,6 +294,49 @@ int claw_batch_finished(claw_batch_t b, claw_t* out, int cap, int* n_out);
 /* Clock of one member (synchronised). */
 int claw_batch_member_clock(claw_batch_t b, claw_t h, claw_stats* st);
 int claw_batch_destroy(claw_batch_t b);
+
+/* ---------------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one step
+ * of exactly dt, as claw_step computes it, from a float64 state in device
+ * memory to a float64 state in device memory, with no handle and no caller
+ * workspace.  Every intermediate -- grid descriptor, controller record,
+ * Courant-reduction slots and, as the configuration needs them, the float32
+ * state with its compensation, the Runge-Kutta stage buffers, the split
+ * step's intermediate states and float32 aux -- lives in one fixed array of
+ * CLAW_STATIC_SCRATCH_BYTES inside the library, one copy per device, held
+ * from the library's first use on that device until the process ends.  In
+ * FP64 the classic step reads d_q_in and writes d_q_out directly.
+ *
+ *   cfg        configuration as for claw_create (validated the same way)
+ *   d_q_in     float64[m][ny][nx] on the current device, read only
+ *   d_aux      float64[na][ny][nx] on the current device (NULL if na = 0)
+ *   d_q_out    float64[m][ny][nx] on the current device; must not overlap d_q_in
+ *   dt         the step size (> 0); the step is always taken
+ *   d_courant  one float64 on the current device: receives dt * max|speed| /
+ *              spacing over the faces bounding interior cells (SharpClaw: in
+ *              the first stage); non-finite for a non-physical state
+ *   hip_stream hipStream_t (NULL: the legacy default stream)
+ *
+ * The call only enqueues work on hip_stream (a fill kernel, the step's
+ * kernels, conversions, one device-to-device copy for SharpClaw in FP64): it
+ * does not synchronise, allocate or free, and issues no memset or
+ * host-to-device copy, so a captured sequence of calls replays as it is.
+ * The first call on a device looks up that device's array (do it once
+ * outside capture).  All calls on one device share the array: calls that
+ * overlap in time on one device (two streams, two threads) race and give
+ * wrong results; calls in one stream order are safe.  Each call resets the
+ * controller record and reduction slots it uses.
+ *
+ * Returns CLAW_OK, CLAW_E_INVAL (bad configuration or arguments, missing
+ * aux, overlapping buffers), CLAW_E_TOOBIG (claw_static_bytes(cfg) exceeds
+ * CLAW_STATIC_SCRATCH_BYTES) or CLAW_E_DEVICE (a launch failed).
+ * ------------------------------------------------------------------------- */
+#define CLAW_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+/* Bytes of the static array claw_step_static would use for cfg (0 if invalid). */
+size_t claw_static_bytes(const claw_config* cfg);
+int claw_step_static(const claw_config* cfg, const double* d_q_in, const double* d_aux,
+                     double* d_q_out, double dt, double* d_courant, void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -12,7 +12,9 @@ HEADER = os.path.join(_HERE, "..", "include", "claw.h")
 
 CLAW_OK = 0
 ERRORS = {-1: "CLAW_E_INVAL", -2: "CLAW_E_NOMEM", -3: "CLAW_E_DEVICE", -4: "CLAW_E_REJECTED",
-          -5: "CLAW_E_NONPHYSICAL", -6: "CLAW_E_BUDGET", -7: "CLAW_E_STATE", -8: "CLAW_E_MAXSTEPS"}
+          -5: "CLAW_E_NONPHYSICAL", -6: "CLAW_E_BUDGET", -7: "CLAW_E_STATE", -8: "CLAW_E_MAXSTEPS",
+          -9: "CLAW_E_TOOBIG"}
+STATIC_SCRATCH_BYTES = 64 << 20   # CLAW_STATIC_SCRATCH_BYTES
 SCHEMES = {"classic": 1, "sharpclaw": 2}
 SOLVERS = {"advection": 1, "sw_roe": 2, "euler_hlle": 3, "elastic_vc": 4, "euler_roe": 5,
            "psystem": 6}
@@ -115,6 +117,8 @@ def load_library():
         "claw_batch_member_clock": ([vp, vp, stp], C.c_int),
         "claw_batch_finished": ([vp, C.POINTER(vp), C.c_int, ip], C.c_int),
         "claw_batch_destroy": ([vp], C.c_int),
+        "claw_static_bytes": ([cfgp], C.c_size_t),
+        "claw_step_static": ([cfgp, vp, vp, vp, C.c_double, vp, vp], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)

@@ -42,6 +42,9 @@ hipError_t launch_cell_speed(int ndim, int riemann, int fp32, const GridDesc* g,
 int totals_blocks();
 hipError_t launch_totals(int fp32, const void* q, const void* c, int m, size_t n, double cell,
                          double* part, double* out, hipStream_t st);
+hipError_t launch_static_setup(const GridDesc& g, GridDesc* d_grid, Ctrl* d_ctrl,
+                               SpeedSlot* d_slots, hipStream_t st);
+hipError_t launch_static_courant(const Ctrl* d_ctrl, double dt, double* out, hipStream_t st);
 }  // namespace claw
 
 using namespace claw;
@@ -194,7 +197,11 @@ struct claw_batch {
 
 namespace {
 
-size_t layout(const claw_config& c, size_t off[16]) {
+// Byte offsets of every array of a handle's workspace (slot -> offset, -1 if
+// absent).  caller_state: the layout of claw_step_static's scratch, where an
+// FP64 state and aux stay in the caller's buffers and the totals and a-priori
+// speed are not needed.
+size_t layout(const claw_config& c, size_t off[16], bool caller_state = false) {
   const int m = num_eqn_of(c), na = num_aux_of(c);
   const size_t N = (size_t)c.num_cells[0] * (c.ndim == 2 ? c.num_cells[1] : 1);
   const size_t rb = c.precision == CLAW_FP32_KAHAN ? 4 : 8;
@@ -206,14 +213,19 @@ size_t layout(const claw_config& c, size_t off[16]) {
     p += align_up(bytes);
   };
   for (int s = 0; s < 16; ++s) off[s] = (size_t)-1;
+  const bool own_state = !(caller_state && !fp32);          // FP64 static step: caller's buffers
   take(0, sizeof(GridDesc));
   take(1, sizeof(Ctrl));
-  take(2, (size_t)m * totals_blocks() * sizeof(double));   // totals partials
-  take(3, 8 * sizeof(double));                             // totals out
-  take(4, sizeof(unsigned long long));                     // a-priori speed
+  if (!caller_state) {
+    take(2, (size_t)m * totals_blocks() * sizeof(double)); // totals partials
+    take(3, 8 * sizeof(double));                           // totals out
+    take(4, sizeof(unsigned long long));                   // a-priori speed
+  }
   take(15, kSpeedSlots * sizeof(SpeedSlot));               // launch-end Courant reduction
-  take(5, m * N * rb);                                     // q[0]
-  if (classic) take(6, m * N * rb);                        // q[1]
+  if (own_state) {
+    take(5, m * N * rb);                                   // q[0]
+    if (classic) take(6, m * N * rb);                      // q[1]
+  }
   if (fp32) {
     take(7, m * N * rb);                                   // c[0]
     if (classic) take(8, m * N * rb);                      // c[1]
@@ -230,7 +242,7 @@ size_t layout(const claw_config& c, size_t off[16]) {
       if (fp32) take(14, m * N * rb);
     }
   }
-  if (na) take(11, na * N * rb);                           // aux
+  if (na && own_state) take(11, na * N * rb);              // aux
   return p;
 }
 
@@ -509,68 +521,25 @@ void absorb_ctrl(claw_t h, const Ctrl& c) {
   h->clock.max_courant = c.max_courant;
 }
 
-}  // namespace
-
-extern "C" {
-
-const char* claw_strerror(int s) {
-  switch (s) {
-    case CLAW_OK: return "ok";
-    case CLAW_E_INVAL: return "invalid argument or unsupported configuration";
-    case CLAW_E_NOMEM: return "workspace smaller than claw_workspace_bytes()";
-    case CLAW_E_DEVICE: return "HIP runtime call failed";
-    case CLAW_E_REJECTED: return "step rejected: Courant number above cfl_max";
-    case CLAW_E_NONPHYSICAL: return "non-finite Courant number (NaN or Inf in the state)";
-    case CLAW_E_BUDGET: return "no free batch slot";
-    case CLAW_E_STATE: return "call order: state not set or handle in use";
-    case CLAW_E_MAXSTEPS: return "max_steps attempts did not reach t_end";
-  }
-  return "unknown status";
+// Defaults of optional configuration fields filled in.
+claw_config normalised(const claw_config& c) {
+  claw_config n = c;
+  if (n.weno_eps <= 0.0) n.weno_eps = 1e-6;
+  if (n.time_integrator == 0) n.time_integrator = CLAW_SSP33;
+  if (n.weno_order == 0) n.weno_order = 5;
+  return n;
 }
 
-int claw_num_eqn(const claw_config* cfg) { return validate(cfg) ? 0 : num_eqn_of(*cfg); }
-int claw_num_aux(const claw_config* cfg) { return validate(cfg) ? 0 : num_aux_of(*cfg); }
-
-size_t claw_workspace_bytes(const claw_config* cfg) {
-  if (validate(cfg) != CLAW_OK) return 0;
-  size_t off[16];
-  return layout(*cfg, off);
-}
-
-int claw_create(const claw_config* cfg, void* d_ws, size_t ws_bytes, void* hip_stream,
-                claw_t* out) {
-  if (!out) return CLAW_E_INVAL;
-  *out = nullptr;
-  int rc = validate(cfg);
-  if (rc) return rc;
-  if (!d_ws || ((uintptr_t)d_ws % kAlign) != 0) return CLAW_E_INVAL;
-  size_t off[16];
-  const size_t need = layout(*cfg, off);
-  if (ws_bytes < need) return CLAW_E_NOMEM;
-  claw_t h = new (std::nothrow) claw_solver();
-  if (!h) return CLAW_E_NOMEM;
-  h->cfg = *cfg;
-  if (h->cfg.weno_eps <= 0.0) h->cfg.weno_eps = 1e-6;
-  if (h->cfg.time_integrator == 0) h->cfg.time_integrator = CLAW_SSP33;
-  if (h->cfg.weno_order == 0) h->cfg.weno_order = 5;
-  if (hipGetDevice(&h->device) != hipSuccess) { delete h; return CLAW_E_DEVICE; }
+// Everything of a handle that follows from its configuration and its
+// workspace: counts, the host copy of the grid descriptor, device pointers
+// carved from `base` at the offsets `off`, and the tiling.
+void fill_handle(claw_t h, const size_t off[16], char* base) {
+  const claw_config* cfg = &h->cfg;
   h->m = num_eqn_of(*cfg);
   h->na = num_aux_of(*cfg);
   h->kr = kernel_riemann(*cfg);
   h->fp32 = cfg->precision == CLAW_FP32_KAHAN;
   h->ncell = (size_t)cfg->num_cells[0] * (cfg->ndim == 2 ? cfg->num_cells[1] : 1);
-  if (hip_stream) {
-    h->stream = (hipStream_t)hip_stream;
-  } else {
-    if (hipStreamCreate(&h->stream) != hipSuccess) { delete h; return CLAW_E_DEVICE; }
-    h->own_stream = true;
-  }
-  if (hipHostMalloc((void**)&h->h_ctrl, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess) {
-    if (h->own_stream) hipStreamDestroy(h->stream);
-    delete h;
-    return CLAW_E_DEVICE;
-  }
-  char* base = (char*)d_ws;
   h->d_grid = (GridDesc*)buf(h, off, 0, base);
   h->d_ctrl = (Ctrl*)buf(h, off, 1, base);
   h->d_part = (double*)buf(h, off, 2, base);
@@ -614,11 +583,69 @@ int claw_create(const claw_config* cfg, void* d_ws, size_t ws_bytes, void* hip_s
     set_tiling(h, t.first);
     h->seg_rows_x = t.second;
   }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* claw_strerror(int s) {
+  switch (s) {
+    case CLAW_OK: return "ok";
+    case CLAW_E_INVAL: return "invalid argument or unsupported configuration";
+    case CLAW_E_NOMEM: return "workspace smaller than claw_workspace_bytes()";
+    case CLAW_E_DEVICE: return "HIP runtime call failed";
+    case CLAW_E_REJECTED: return "step rejected: Courant number above cfl_max";
+    case CLAW_E_NONPHYSICAL: return "non-finite Courant number (NaN or Inf in the state)";
+    case CLAW_E_BUDGET: return "no free batch slot";
+    case CLAW_E_STATE: return "call order: state not set or handle in use";
+    case CLAW_E_MAXSTEPS: return "max_steps attempts did not reach t_end";
+    case CLAW_E_TOOBIG:
+      return "grid needs more than the CLAW_STATIC_SCRATCH_BYTES of claw_step_static";
+  }
+  return "unknown status";
+}
+
+int claw_num_eqn(const claw_config* cfg) { return validate(cfg) ? 0 : num_eqn_of(*cfg); }
+int claw_num_aux(const claw_config* cfg) { return validate(cfg) ? 0 : num_aux_of(*cfg); }
+
+size_t claw_workspace_bytes(const claw_config* cfg) {
+  if (validate(cfg) != CLAW_OK) return 0;
+  size_t off[16];
+  return layout(*cfg, off);
+}
+
+int claw_create(const claw_config* cfg, void* d_ws, size_t ws_bytes, void* hip_stream,
+                claw_t* out) {
+  if (!out) return CLAW_E_INVAL;
+  *out = nullptr;
+  int rc = validate(cfg);
+  if (rc) return rc;
+  if (!d_ws || ((uintptr_t)d_ws % kAlign) != 0) return CLAW_E_INVAL;
+  size_t off[16];
+  const size_t need = layout(*cfg, off);
+  if (ws_bytes < need) return CLAW_E_NOMEM;
+  claw_t h = new (std::nothrow) claw_solver();
+  if (!h) return CLAW_E_NOMEM;
+  h->cfg = normalised(*cfg);
+  if (hipGetDevice(&h->device) != hipSuccess) { delete h; return CLAW_E_DEVICE; }
+  if (hip_stream) {
+    h->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreate(&h->stream) != hipSuccess) { delete h; return CLAW_E_DEVICE; }
+    h->own_stream = true;
+  }
+  if (hipHostMalloc((void**)&h->h_ctrl, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess) {
+    if (h->own_stream) hipStreamDestroy(h->stream);
+    delete h;
+    return CLAW_E_DEVICE;
+  }
+  fill_handle(h, off, (char*)d_ws);
   Ctrl c0;
   std::memset(&c0, 0, sizeof(c0));
   rc = CLAW_OK;
   if (hipMemcpyAsync(h->d_ctrl, &c0, sizeof(Ctrl), hipMemcpyHostToDevice, h->stream) != hipSuccess ||
-      hipMemsetAsync(g.slots, 0, kSpeedSlots * sizeof(SpeedSlot), h->stream) != hipSuccess ||
+      hipMemsetAsync(h->hg.slots, 0, kSpeedSlots * sizeof(SpeedSlot), h->stream) != hipSuccess ||
       upload_grid(h) != CLAW_OK || hipStreamSynchronize(h->stream) != hipSuccess)
     rc = CLAW_E_DEVICE;
   if (rc) {
@@ -1216,6 +1243,110 @@ int claw_batch_advance(claw_batch_t b, int attempts, int* n_active) {
   }
   if (n_active) *n_active = act;
   return status ? status : CLAW_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// claw_step_static: one step without a caller workspace.
+// ---------------------------------------------------------------------------
+namespace {
+
+// Device memory of claw_step_static: grid descriptor, controller record,
+// Courant-reduction slots and, as the configuration needs them, the
+// working-precision state, stage and sweep buffers and aux.  Each device
+// holds its own copy from the library's first use on it until the process
+// ends.  In host code the symbol is a stand-in, not a device address: only
+// the address hipGetSymbolAddress returns on a device is used.
+static __device__ __align__(256) unsigned char scratch[CLAW_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch[kMaxDevices] = {};
+
+// The current device's scratch address, looked up once per device (with
+// that device current).
+int scratch_base(int dev, char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return CLAW_E_DEVICE;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return CLAW_E_DEVICE;
+    g_scratch[dev] = (char*)p;
+  }
+  *out = g_scratch[dev];
+  return CLAW_OK;
+}
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  return x < y + nb && y < x + na;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t claw_static_bytes(const claw_config* cfg) {
+  if (validate(cfg) != CLAW_OK) return 0;
+  size_t off[16];
+  return layout(normalised(*cfg), off, true);
+}
+
+int claw_step_static(const claw_config* cfg, const double* d_q_in, const double* d_aux,
+                     double* d_q_out, double dt, double* d_courant, void* hip_stream) {
+  int rc = validate(cfg);
+  if (rc) return rc;
+  if (!d_q_in || !d_q_out || !d_courant || !(dt > 0.0)) return CLAW_E_INVAL;
+  const claw_config c = normalised(*cfg);
+  const int m = num_eqn_of(c), na = num_aux_of(c);
+  if (na && !d_aux) return CLAW_E_INVAL;
+  const size_t N = (size_t)c.num_cells[0] * (c.ndim == 2 ? c.num_cells[1] : 1);
+  const size_t n = (size_t)m * N;
+  if (overlap(d_q_in, n * sizeof(double), d_q_out, n * sizeof(double)) ||
+      overlap(d_courant, sizeof(double), d_q_out, n * sizeof(double)) ||
+      overlap(d_courant, sizeof(double), d_q_in, n * sizeof(double)))
+    return CLAW_E_INVAL;
+  size_t off[16];
+  if (layout(c, off, true) > CLAW_STATIC_SCRATCH_BYTES) return CLAW_E_TOOBIG;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  char* base = nullptr;
+  if ((rc = scratch_base(dev, &base))) return rc;
+  // a handle on the stack over the scratch: nothing is allocated
+  claw_solver h{};
+  h.cfg = c;
+  h.device = dev;
+  h.stream = (hipStream_t)hip_stream;
+  fill_handle(&h, off, base);
+  GridDesc& g = h.hg;
+  const bool classic = c.scheme == CLAW_CLASSIC;
+  const hipStream_t st = h.stream;
+  if (!h.fp32) {
+    g.aux = d_aux;
+    if (classic) {
+      // the step reads Q^n from q[0] and writes Q^{n+1} to q[1]
+      g.q[0] = const_cast<double*>(d_q_in);
+      g.q[1] = d_q_out;
+    } else {
+      // the Runge-Kutta stages update Q in place: start from a copy
+      HIPCHK(hipMemcpyAsync(d_q_out, d_q_in, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+      g.q[0] = d_q_out;
+      g.q[1] = nullptr;
+    }
+  }
+  HIPCHK(launch_static_setup(g, h.d_grid, h.d_ctrl, g.slots, st));
+  if (h.fp32) {
+    HIPCHK(launch_load_state(1, g.q[0], g.c[0], d_q_in, n, st));
+    if (na) HIPCHK(launch_convert(1, (void*)g.aux, d_aux, (size_t)na * N, st));
+  }
+  if ((rc = launch_attempt_host(&h, dt, false))) return rc;
+  HIPCHK(launch_static_courant(h.d_ctrl, dt, d_courant, st));
+  if (h.fp32) {
+    const int dst = classic ? 1 : 0;
+    HIPCHK(launch_store_state(1, d_q_out, g.q[dst], g.c[dst], n, st));
+  }
+  return CLAW_OK;
 }
 
 }  // extern "C"

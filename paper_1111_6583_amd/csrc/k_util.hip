@@ -91,6 +91,27 @@ __global__ void k_totals_final(const double* __restrict__ part, int m, int nb, d
   }
 }
 
+// Head of a step in a scratch buffer that keeps the previous call's
+// contents: the grid descriptor (passed by value), a zeroed controller
+// record and zeroed Courant-reduction slots.  A fill kernel rather than
+// memset and copy nodes, so a captured sequence replays it as it is.
+__global__ void k_static_setup(GridDesc g, GridDesc* __restrict__ dst, Ctrl* __restrict__ ctrl,
+                               SpeedSlot* __restrict__ slots) {
+  if (threadIdx.x == 0) *dst = g;
+  unsigned int* c = (unsigned int*)ctrl;
+  for (unsigned t = threadIdx.x; t < sizeof(Ctrl) / sizeof(unsigned int); t += blockDim.x) c[t] = 0u;
+  unsigned int* sl = (unsigned int*)slots;
+  for (unsigned t = threadIdx.x; t < kSpeedSlots * sizeof(SpeedSlot) / sizeof(unsigned int);
+       t += blockDim.x)
+    sl[t] = 0u;
+}
+
+// Courant number of the step just taken: dt times the launch-end maximum of
+// |speed| / spacing that the step kernels left in the controller record.
+__global__ void k_static_courant(const Ctrl* __restrict__ ctrl, double dt, double* __restrict__ out) {
+  if (threadIdx.x == 0) *out = dt * ctrl->last_speed;
+}
+
 // ---------------------------------------------------------------------------
 static dim3 grid_for(size_t n) {
   size_t b = (n + 255) / 256;
@@ -160,6 +181,17 @@ hipError_t launch_cell_speed(int ndim, int riemann, int fp32, const GridDesc* g,
                              unsigned long long* out, hipStream_t st) {
   return fp32 ? cell_speed_t<float>(ndim, riemann, g, src, n, out, st)
               : cell_speed_t<double>(ndim, riemann, g, src, n, out, st);
+}
+
+hipError_t launch_static_setup(const GridDesc& g, GridDesc* d_grid, Ctrl* d_ctrl,
+                               SpeedSlot* d_slots, hipStream_t st) {
+  hipLaunchKernelGGL(k_static_setup, dim3(1), dim3(256), 0, st, g, d_grid, d_ctrl, d_slots);
+  return hipGetLastError();
+}
+
+hipError_t launch_static_courant(const Ctrl* d_ctrl, double dt, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_static_courant, dim3(1), dim3(64), 0, st, d_ctrl, dt, out);
+  return hipGetLastError();
 }
 
 int totals_blocks() { return kTotBlocks; }

@@ -166,3 +166,31 @@ def test_size_limit():
     assert _bytes(dict(spec, num_cells=(50000, 50000)))[0] == 0
     n, m = _bytes(dict(spec, num_cells=(44000, 44000)))
     assert n >= 2 * 3 * 44000 * 44000 * 8
+
+
+def test_static_step_size_limit_is_checked_on_the_host():
+    """claw_step_static rejects a grid whose intermediates exceed its fixed
+    array (CLAW_E_TOOBIG) before touching a device, and reports the bytes it
+    would use: nothing beyond control blocks for an FP64 classic step (state
+    in the caller's buffers), stage buffers for SharpClaw."""
+    lib = _claw.load_library()
+    spec, _ = W.radial_dam_break(1024)
+    c = _claw.make_config(spec)
+    assert lib.claw_static_bytes(C.byref(c)) < 64 * 1024
+    c32 = _claw.make_config(dict(spec, precision="fp32_kahan"))
+    n32 = lib.claw_static_bytes(C.byref(c32))
+    assert 4 * 3 * 1024 * 1024 * 4 <= n32 < 4 * 3 * 1024 * 1024 * 4 + 64 * 1024
+    big, _ = W.shock_bubble(2048, 1024)
+    cb = _claw.make_config(dict(big, precision="fp32_kahan"))
+    assert lib.claw_static_bytes(C.byref(cb)) > _claw.STATIC_SCRATCH_BYTES
+    # disjoint (never dereferenced) addresses: every check below fails before a launch
+    a, b, z = C.c_void_p(1 << 40), C.c_void_p(1 << 41), C.c_void_p(1 << 42)
+    rc = lib.claw_step_static(C.byref(cb), a, None, b, 1e-3, z, None)
+    assert rc == -9
+    assert "CLAW_STATIC_SCRATCH_BYTES" in lib.claw_strerror(rc).decode()
+    # argument checks, also host-side
+    assert lib.claw_step_static(C.byref(c), None, None, b, 1e-3, z, None) == -1   # no input
+    assert lib.claw_step_static(C.byref(c), a, None, a, 1e-3, z, None) == -1      # in = out
+    assert lib.claw_step_static(C.byref(c), a, None, b, 0.0, z, None) == -1       # dt <= 0
+    el, _, _ = W.layered_elastic(64)
+    assert lib.claw_step_static(C.byref(_claw.make_config(el)), a, None, b, 1e-3, z, None) == -1

@@ -1,0 +1,90 @@
+"""claw_step_static (the entry point that allocates nothing) against
+claw_step on a handle with its own workspace: two calls in a row on the same
+device array, the second on a smaller grid, must give the same states and
+Courant numbers bit for bit (the same kernels run on the same data)."""
+
+import ctypes as C
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1111_6583_amd import workloads as W
+from paper_1111_6583_amd._claw import check, load_library, make_config
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def handle_step(spec, q, aux, dt):
+    from paper_1111_6583_amd import Solver
+    s = Solver(spec)
+    s.set_state(q)
+    if aux is not None:
+        s.set_aux(aux)
+    c = s.step(dt)
+    out = s.get_state()
+    s.close()
+    return out, c
+
+
+def static_step(spec, q, aux, dt, stream):
+    lib = load_library()
+    cfg = make_config(spec)
+    dq = torch.as_tensor(q, dtype=torch.float64).contiguous().cuda()
+    da = None if aux is None else torch.as_tensor(aux, dtype=torch.float64).contiguous().cuda()
+    # the output starts as garbage: the step must write every cell
+    out = torch.full_like(dq, float("nan"))
+    cour = torch.full((1,), float("nan"), dtype=torch.float64, device="cuda")
+    check(lib.claw_step_static(C.byref(cfg), C.c_void_p(dq.data_ptr()),
+                               None if da is None else C.c_void_p(da.data_ptr()),
+                               C.c_void_p(out.data_ptr()), float(dt),
+                               C.c_void_p(cour.data_ptr()), C.c_void_p(stream.cuda_stream)),
+          "claw_step_static")
+    stream.synchronize()
+    return out.cpu().numpy(), float(cour.cpu()[0])
+
+
+def _cases():
+    big, qb = W.radial_dam_break(300, ny=200)
+    small, qs = W.radial_dam_break(70, ny=45)
+    yield "sw fp64", (big, qb, None, 2e-3), (small, qs, None, 8e-3)
+    yield "sw fp32", (dict(big, precision="fp32_kahan"), qb, None, 2e-3), \
+        (dict(small, precision="fp32_kahan"), qs, None, 8e-3)
+    yield "sw strang fp64", (dict(big, dimensional_split="strang"), qb, None, 2e-3), \
+        (dict(small, dimensional_split="godunov"), qs, None, 8e-3)
+    eb, qeb = W.shock_bubble(256, 128)
+    es, qes = W.shock_bubble(96, 40)
+    yield "euler fp64", (eb, qeb, None, 1e-3), (es, qes, None, 2e-3)
+    yield "euler ssp104 weno7 fp32", \
+        (dict(eb, precision="fp32_kahan", time_integrator="ssp104", weno_order=7), qeb, None, 1e-3), \
+        (dict(es, precision="fp32_kahan", time_integrator="ssp104", weno_order=7), qes, None, 2e-3)
+    el, ql, al = W.layered_elastic(200)
+    el2, ql2, al2 = W.layered_elastic(60)
+    yield "elastic fp32", (dict(el, precision="fp32_kahan"), ql, al, 1e-3), \
+        (dict(el2, precision="fp32_kahan"), ql2, al2, 4e-3)
+    ps, qp, ap = W.psystem_checkerboard(10, 8, ny_periods=6)
+    ps2, qp2, ap2 = W.psystem_checkerboard(6, 5, ny_periods=3)
+    yield "psystem fp64", (ps, qp, ap, 2e-3), (ps2, qp2, ap2, 4e-3)
+    d1, q1 = W.dam_break_1d(1000)
+    d2, q2 = W.dam_break_1d(300)
+    yield "1d fp64", (d1, q1, None, 5e-3), (d2, q2, None, 1e-2)
+
+
+@pytest.mark.parametrize("case", [c[0] for c in _cases()])
+def test_static_step_equals_handle_step_twice(case):
+    _, first, second = next(c for c in _cases() if c[0] == case)
+    stream = torch.cuda.Stream()
+    for spec, q, aux, dt in (first, second):
+        say("case: claw_step_static", case, spec["num_cells"], "dt", dt)
+        g, cg = static_step(spec, q, aux, dt, stream)
+        h, ch = handle_step(spec, q, aux, dt)
+        assert np.isfinite(g).all()
+        np.testing.assert_array_equal(g, h)
+        assert cg == ch
+
