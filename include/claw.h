@@ -114,9 +114,12 @@ enum claw_split {
 };
 enum claw_precision {
   CLAW_FP64 = 1,       /* all arithmetic in float64 */
-  CLAW_FP32_KAHAN = 2  /* reconstruction, Riemann and limiter arithmetic in float32; the state is
+  CLAW_FP32_KAHAN = 2, /* reconstruction, Riemann and limiter arithmetic in float32; the state is
                           float32 with a float32 compensation term per value (Kahan summation of
                           each update); dt control, Courant reduction and totals in float64 */
+  CLAW_FP32 = 3        /* as CLAW_FP32_KAHAN without the compensation (plain float32 updates), to
+                          measure what the compensated update gains; classic 2D shallow water
+                          (unsplit) and SharpClaw 2D Euler with WENO5 only (else CLAW_E_INVAL) */
 };
 
 typedef struct claw_config {
@@ -175,7 +178,9 @@ typedef struct claw_tuning {
   int segs;              /* row segments (work items per column strip) of the 2D kernels;
                             > 0 overrides seg_rows (at most ny).  claw_get_tuning fills both,
                             seg_rows being the longest segment */
-  int reserved;
+  int order;             /* order of the tiles over the workgroups of a launch: 0 strips
+                            fastest, 1 segments fastest, 2 and 3 the same with each of the
+                            GPU's 8 XCDs (own L2) given a contiguous band of tiles */
 } claw_tuning;
 
 typedef struct claw_solver* claw_t;
@@ -252,9 +257,11 @@ int claw_set_clock(claw_t h, const claw_stats* st);
 int claw_set_tuning(claw_t h, const claw_tuning* tn);
 int claw_get_tuning(claw_t h, claw_tuning* tn);
 
-/* Time one step (without applying it) for each candidate seg_rows and keep
+/* Time one step (without applying it) for each candidate tiling and keep
  * the fastest; *out (may be NULL) receives it.  reps: timed repetitions.
- * Split steps tune seg_rows (y sweeps) first, then seg_rows_x. */
+ * Candidates: row segment counts (rows per segment 4..128 and counts that
+ * fill whole waves per SIMD), then the four tile orders at the best count;
+ * split steps tune the y sweeps' segments first, then seg_rows_x. */
 int claw_autotune(claw_t h, int reps, claw_tuning* out);
 
 /* Launch the step's main kernel `reps` times back to back on the handle's
@@ -280,16 +287,34 @@ int claw_destroy(claw_t h);
 size_t claw_batch_workspace_bytes(int max_grids);
 int claw_batch_create(int max_grids, void* d_ws, size_t ws_bytes, void* hip_stream,
                       claw_batch_t* out);
-/* Add a handle (its state must be set) with its own end time. */
+/* Add a handle (its state must be set) with its own end time; it joins the
+ * next launched group.  Synchronises only the member's own stream. */
 int claw_batch_add(claw_batch_t b, claw_t h, double t_end);
+/* Remove a member.  One that had stopped as of the view leaves without any
+ * wait (its clock is the view's; groups still in flight skip it, but may
+ * still read its controller: keep its workspace valid until the next
+ * claw_batch_wait returns).  Otherwise the batch stream is synchronised. */
 int claw_batch_remove(claw_batch_t b, claw_t h);
 /* Run `attempts` device-controlled attempts for every member (members
  * that reached t_end idle); *n_active (may be NULL) receives the number of
- * members still short of their t_end.  Synchronises the batch stream. */
+ * members still short of their t_end.  Waits for every group in flight
+ * (= claw_batch_launch + claw_batch_wait). */
 int claw_batch_advance(claw_batch_t b, int attempts, int* n_active);
-/* Members whose controller has stopped (reached t_end or failed) as of
- * the last claw_batch_advance: up to `cap` handles into out[], count in
- * *n_out.  They stay members until claw_batch_remove. */
+/* Enqueue a group of `attempts` device-controlled attempts for every current
+ * member, then an asynchronous copy of the member controllers to pinned host
+ * memory; returns without synchronising.  Membership changes made before the
+ * call take effect in this group.  At most two groups may be in flight
+ * (CLAW_E_STATE otherwise): launching the next group before waiting for the
+ * previous one keeps the GPU busy while the host admits and retires. */
+int claw_batch_launch(claw_batch_t b, int attempts);
+/* Wait for the oldest group in flight (CLAW_E_STATE if none) and make its
+ * controller copies the batch's view: claw_batch_finished and
+ * claw_batch_remove read it.  *n_active (may be NULL): members of that group
+ * still short of their t_end. */
+int claw_batch_wait(claw_batch_t b, int* n_active);
+/* Members whose controller has stopped (reached t_end or failed) as of the
+ * view: up to `cap` handles into out[], count in *n_out.  They stay members
+ * until claw_batch_remove. */
 int claw_batch_finished(claw_batch_t b, claw_t* out, int cap, int* n_out);
 /* Clock of one member (synchronised). */
 int claw_batch_member_clock(claw_batch_t b, claw_t h, claw_stats* st);

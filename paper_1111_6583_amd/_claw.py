@@ -22,7 +22,7 @@ SOURCES = {"none": 0, "axisymmetric": 1}
 SPLITS = {"none": 0, "godunov": 1, "strang": 2}
 LIMITERS = {"none": 0, "minmod": 1, "mc": 2}
 BCS = {"extrap": 1, "periodic": 2, "wall": 3, "dirichlet": 4}
-PRECISIONS = {"fp64": 1, "fp32_kahan": 2}
+PRECISIONS = {"fp64": 1, "fp32_kahan": 2, "fp32": 3}
 INTEGRATORS = {"ssp33": 1, "ssp104": 2}
 SIDES = ("x_lower", "x_upper", "y_lower", "y_upper")
 
@@ -51,7 +51,7 @@ class ClawStats(C.Structure):
 
 class ClawTuning(C.Structure):
     _fields_ = [("seg_rows", C.c_int), ("seg_rows_x", C.c_int), ("segs", C.c_int),
-                ("reserved", C.c_int)]
+                ("order", C.c_int)]
 
 
 class ClawError(RuntimeError):
@@ -114,6 +114,8 @@ def load_library():
         "claw_batch_add": ([vp, vp, C.c_double], C.c_int),
         "claw_batch_remove": ([vp, vp], C.c_int),
         "claw_batch_advance": ([vp, C.c_int, ip], C.c_int),
+        "claw_batch_launch": ([vp, C.c_int], C.c_int),
+        "claw_batch_wait": ([vp, ip], C.c_int),
         "claw_batch_member_clock": ([vp, vp, stp], C.c_int),
         "claw_batch_finished": ([vp, C.POINTER(vp), C.c_int, ip], C.c_int),
         "claw_batch_destroy": ([vp], C.c_int),

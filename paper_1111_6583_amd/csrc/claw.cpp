@@ -19,7 +19,7 @@
 #include "claw_internal.h"
 
 namespace claw {
-hipError_t launch_classic2d(int riemann, int fp32, int lim, int trans, int nblocks, hipStream_t st,
+hipError_t launch_classic2d(int riemann, int prec, int lim, int trans, int nblocks, hipStream_t st,
                             const GridDesc* d_grids, const int* d_bstart, int ngrids, int mode,
                             double dt, int src);
 hipError_t launch_classic1d(int riemann, int fp32, int nblocks, hipStream_t st,
@@ -27,7 +27,7 @@ hipError_t launch_classic1d(int riemann, int fp32, int nblocks, hipStream_t st,
 hipError_t launch_classic1d_run(int riemann, int fp32, int m, int nx, hipStream_t st,
                                 const GridDesc* d_grids);
 size_t classic1d_run_smem(int m, int nx, int fp32);
-hipError_t launch_sharp_stage(int ndim, int riemann, int fp32, int weno_r, int kind, int nblocks,
+hipError_t launch_sharp_stage(int ndim, int riemann, int prec, int weno_r, int kind, int nblocks,
                               hipStream_t st, const GridDesc* d_grids, int mode, double dt,
                               const StageArgs& sa);
 hipError_t launch_sweep(int dir, int riemann, int fp32, int lim, hipStream_t st,
@@ -97,7 +97,16 @@ int validate(const claw_config* c) {
     if ((c->bc_lower[d] == CLAW_BC_PERIODIC) != (c->bc_upper[d] == CLAW_BC_PERIODIC))
       return CLAW_E_INVAL;
   }
-  if (c->precision != CLAW_FP64 && c->precision != CLAW_FP32_KAHAN) return CLAW_E_INVAL;
+  if (c->precision != CLAW_FP64 && c->precision != CLAW_FP32_KAHAN && c->precision != CLAW_FP32)
+    return CLAW_E_INVAL;
+  if (c->precision == CLAW_FP32) {
+    // plain FP32 kernels exist for the two workloads its comparison is made on
+    const bool sw = c->scheme == CLAW_CLASSIC && c->riemann == CLAW_RP_SW_ROE && c->ndim == 2 &&
+                    c->dimensional_split == CLAW_SPLIT_NONE;
+    const bool eu = c->scheme == CLAW_SHARPCLAW && c->riemann == CLAW_RP_EULER_HLLE &&
+                    c->ndim == 2 && (c->weno_order == 0 || c->weno_order == 5);
+    if (!sw && !eu) return CLAW_E_INVAL;
+  }
   if (c->tracer != 0 && (c->tracer != 1 || c->riemann != CLAW_RP_EULER_ROE)) return CLAW_E_INVAL;
   if (c->source != CLAW_SOURCE_NONE &&
       (c->source != CLAW_SOURCE_AXISYMMETRIC || c->riemann != CLAW_RP_EULER_ROE || c->ndim != 2 ||
@@ -135,7 +144,10 @@ int validate(const claw_config* c) {
 // Process-wide tiling cache: (4 scheme + split mode, riemann, precision, WENO order, nx, ny)
 // -> (row segments, seg_rows_x).
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int, int, int>, std::pair<int, int>> g_tune;
+struct Tiling {
+  int segs, seg_rows_x, order;
+};
+std::map<std::tuple<int, int, int, int, int, int>, Tiling> g_tune;
 
 int weno_r_of(const claw_config& c) { return c.weno_order >= 7 ? (c.weno_order + 1) / 2 : 3; }
 bool ssp104(const claw_config& c) { return c.time_integrator == CLAW_SSP104; }
@@ -154,7 +166,8 @@ int default_seg_rows_x(int ny) { return std::min(ny, 4); }
 struct claw_solver {
   claw_config cfg;
   int device = 0;
-  int m = 0, na = 0, fp32 = 0;
+  int m = 0, na = 0, fp32 = 0;   // fp32: float32 storage (both FP32 precisions)
+  int pk = 0;                    // kernel precision: 0 FP64, 1 FP32 + Kahan, 2 plain FP32
   int kr = 0;                    // kernel variant of the Riemann solver
   void* split_c[2] = {nullptr, nullptr};   // compensations of the split step's intermediates
   int seg_rows_x = 0;            // rows per workgroup of the split step's x sweeps
@@ -177,6 +190,10 @@ struct claw_solver {
   int graph_k = 0;
 };
 
+// Launch groups of a batch that may be in flight at once (claw_batch_launch
+// without claw_batch_wait).
+constexpr int kBatchInFlight = 2;
+
 struct claw_batch {
   int max_grids = 0;
   int device = 0;
@@ -184,15 +201,28 @@ struct claw_batch {
   bool own_stream = false;
   GridDesc* d_grids = nullptr;
   int* d_bstart = nullptr;
-  Ctrl* d_ctrls = nullptr;        // gathered copies of member controllers
+  Ctrl* d_ctrls = nullptr;        // gathered copies of member controllers (one set per group)
   std::vector<claw_t> members;
   std::vector<int> bstart;
   bool dirty = true;
-  int riemann = 0, fp32 = 0, limiter = 0, transverse = 0;
+  int riemann = 0, fp32 = 0, limiter = 0, transverse = 0;   // fp32: the members' kernel precision
   hipGraphExec_t graph = nullptr;
   int graph_k = 0;
-  Ctrl* h_ctrls = nullptr;
-  int gathered = -1;              // members covered by h_ctrls (-1: stale)
+  // groups in flight: their member lists, pinned controller copies, events
+  Ctrl* h_ctrls[kBatchInFlight] = {nullptr, nullptr};
+  std::vector<claw_t> snap[kBatchInFlight];
+  hipEvent_t ev[kBatchInFlight] = {nullptr, nullptr};
+  long long launched = 0, waited = 0;   // groups launched / completed (waited for)
+  // the view: member controllers as of the last completed group
+  const Ctrl* view = nullptr;
+  const std::vector<claw_t>* view_members = nullptr;
+  // pinned upload buffers of the grid tables, one per group slot (a slot's
+  // buffer is rewritten only after the group that used it has completed)
+  GridDesc* h_grids[kBatchInFlight] = {nullptr, nullptr};
+  int* h_bstart[kBatchInFlight] = {nullptr, nullptr};
+  // graphs replaced while groups that launch them may still be in flight,
+  // with the number of groups launched when they were replaced
+  std::vector<std::pair<hipGraphExec_t, long long>> retired;
 };
 
 namespace {
@@ -204,8 +234,9 @@ namespace {
 size_t layout(const claw_config& c, size_t off[16], bool caller_state = false) {
   const int m = num_eqn_of(c), na = num_aux_of(c);
   const size_t N = (size_t)c.num_cells[0] * (c.ndim == 2 ? c.num_cells[1] : 1);
-  const size_t rb = c.precision == CLAW_FP32_KAHAN ? 4 : 8;
-  const bool fp32 = c.precision == CLAW_FP32_KAHAN;
+  const size_t rb = c.precision == CLAW_FP64 ? 8 : 4;
+  const bool fp32 = c.precision != CLAW_FP64;
+  const bool kahan = c.precision == CLAW_FP32_KAHAN;
   const bool classic = c.scheme == CLAW_CLASSIC;
   size_t p = 0;
   auto take = [&](int slot, size_t bytes) {
@@ -226,7 +257,7 @@ size_t layout(const claw_config& c, size_t off[16], bool caller_state = false) {
     take(5, m * N * rb);                                   // q[0]
     if (classic) take(6, m * N * rb);                      // q[1]
   }
-  if (fp32) {
+  if (kahan) {
     take(7, m * N * rb);                                   // c[0]
     if (classic) take(8, m * N * rb);                      // c[1]
   }
@@ -236,10 +267,10 @@ size_t layout(const claw_config& c, size_t off[16], bool caller_state = false) {
     if (ssp104(c)) take(12, m * N * rb);                   // s3
   } else if (split(c)) {
     take(9, m * N * rb);                                   // state after the first sweep
-    if (fp32) take(13, m * N * rb);                        //   and its compensation
+    if (kahan) take(13, m * N * rb);                       //   and its compensation
     if (strang(c)) {
       take(10, m * N * rb);                                // state after the second sweep
-      if (fp32) take(14, m * N * rb);
+      if (kahan) take(14, m * N * rb);
     }
   }
   if (na && own_state) take(11, na * N * rb);              // aux
@@ -252,12 +283,11 @@ std::tuple<int, int, int, int, int, int> tune_key(claw_t h) {
                          h->cfg.ndim == 2 ? h->cfg.num_cells[1] : 1);
 }
 
-std::pair<int, int> tiling_for(claw_t h) {
+Tiling tiling_for(claw_t h) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   auto it = g_tune.find(tune_key(h));
   const int ny = h->cfg.ndim == 2 ? h->cfg.num_cells[1] : 1;
-  return it != g_tune.end() ? it->second
-                            : std::make_pair(default_segs(ny), default_seg_rows_x(ny));
+  return it != g_tune.end() ? it->second : Tiling{default_segs(ny), default_seg_rows_x(ny), 0};
 }
 
 int segs_from_rows(int ny, int seg_rows) {
@@ -375,7 +405,7 @@ int launch_sharp_stages(claw_t h, int from, int to, int mode, double dt) {
   int kind[10];
   const int n = sharp_plan(h, st, kind);
   for (int s = from; s < std::min(to, n); ++s)
-    HIPCHK(launch_sharp_stage(h->cfg.ndim, h->kr, h->fp32, h->hg.weno_r, kind[s],
+    HIPCHK(launch_sharp_stage(h->cfg.ndim, h->kr, h->pk, h->hg.weno_r, kind[s],
                               h->hg.nblocks, h->stream, h->d_grid, mode, dt, st[s]));
   return CLAW_OK;
 }
@@ -429,7 +459,7 @@ int launch_attempt_host(claw_t h, double dt, bool stage1_only) {
   if (split(h->cfg)) return launch_split(h, kHostDt, dt);
   if (h->cfg.scheme == CLAW_CLASSIC) {
     if (h->cfg.ndim == 2)
-      HIPCHK(launch_classic2d(h->kr, h->fp32, g.limiter, g.transverse, g.nblocks, h->stream, h->d_grid, nullptr, 1,
+      HIPCHK(launch_classic2d(h->kr, h->pk, g.limiter, g.transverse, g.nblocks, h->stream, h->d_grid, nullptr, 1,
                               kHostDt, dt, h->src));
     else
       HIPCHK(launch_classic1d(h->kr, h->fp32, g.nblocks, h->stream, h->d_grid, kHostDt, dt,
@@ -448,7 +478,7 @@ int launch_attempt_device(claw_t h) {
   if (split(h->cfg)) return launch_split(h, kDeviceCtrl, 0.0);
   if (h->cfg.scheme == CLAW_CLASSIC) {
     if (h->cfg.ndim == 2)
-      HIPCHK(launch_classic2d(h->kr, h->fp32, g.limiter, g.transverse, g.nblocks, h->stream, h->d_grid, nullptr, 1,
+      HIPCHK(launch_classic2d(h->kr, h->pk, g.limiter, g.transverse, g.nblocks, h->stream, h->d_grid, nullptr, 1,
                               kDeviceCtrl, 0.0, 0));
     else
       HIPCHK(launch_classic1d(h->kr, h->fp32, g.nblocks, h->stream, h->d_grid, kDeviceCtrl,
@@ -538,7 +568,8 @@ void fill_handle(claw_t h, const size_t off[16], char* base) {
   h->m = num_eqn_of(*cfg);
   h->na = num_aux_of(*cfg);
   h->kr = kernel_riemann(*cfg);
-  h->fp32 = cfg->precision == CLAW_FP32_KAHAN;
+  h->fp32 = cfg->precision != CLAW_FP64;
+  h->pk = cfg->precision == CLAW_FP64 ? 0 : (cfg->precision == CLAW_FP32_KAHAN ? 1 : 2);
   h->ncell = (size_t)cfg->num_cells[0] * (cfg->ndim == 2 ? cfg->num_cells[1] : 1);
   h->d_grid = (GridDesc*)buf(h, off, 0, base);
   h->d_ctrl = (Ctrl*)buf(h, off, 1, base);
@@ -579,9 +610,10 @@ void fill_handle(claw_t h, const size_t off[16], char* base) {
   h->split_c[0] = buf(h, off, 13, base);
   h->split_c[1] = buf(h, off, 14, base);
   {
-    const std::pair<int, int> t = tiling_for(h);
-    set_tiling(h, t.first);
-    h->seg_rows_x = t.second;
+    const Tiling t = tiling_for(h);
+    set_tiling(h, t.segs);
+    h->seg_rows_x = t.seg_rows_x;
+    h->hg.order = h->cfg.ndim == 2 ? t.order : 0;
   }
 }
 
@@ -685,7 +717,7 @@ int claw_set_state(claw_t h, const double* q, int on_device) {
     std::vector<float> tmp(n);
     for (size_t t = 0; t < n; ++t) tmp[t] = (float)q[t];
     HIPCHK(hipMemcpyAsync(dq, tmp.data(), n * sizeof(float), hipMemcpyHostToDevice, h->stream));
-    HIPCHK(hipMemsetAsync(dc, 0, n * sizeof(float), h->stream));
+    if (dc) HIPCHK(hipMemsetAsync(dc, 0, n * sizeof(float), h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
   }
   HIPCHK(hipStreamSynchronize(h->stream));
@@ -734,9 +766,9 @@ int claw_get_state(claw_t h, double* out, int on_device) {
     HIPCHK(hipMemcpyAsync(out, dq, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
   } else {
-    std::vector<float> tq(n), tc(n);
+    std::vector<float> tq(n), tc(n, 0.0f);
     HIPCHK(hipMemcpyAsync(tq.data(), dq, n * sizeof(float), hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(hipMemcpyAsync(tc.data(), dc, n * sizeof(float), hipMemcpyDeviceToHost, h->stream));
+    if (dc) HIPCHK(hipMemcpyAsync(tc.data(), dc, n * sizeof(float), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     for (size_t t = 0; t < n; ++t) out[t] = (double)tq[t] - (double)tc[t];
   }
@@ -898,10 +930,12 @@ int claw_set_clock(claw_t h, const claw_stats* st) {
 }
 
 int claw_set_tuning(claw_t h, const claw_tuning* tn) {
-  if (!h || !tn || (tn->seg_rows < 1 && tn->segs < 1)) return CLAW_E_INVAL;
+  if (!h || !tn || (tn->seg_rows < 1 && tn->segs < 1) || tn->order < 0 || tn->order > 3)
+    return CLAW_E_INVAL;
   HIPCHK(hipSetDevice(h->device));
   set_tiling(h, tn->segs > 0 ? tn->segs : segs_from_rows(h->hg.ny, tn->seg_rows));
   h->seg_rows_x = tn->seg_rows_x > 0 ? tn->seg_rows_x : 0;
+  h->hg.order = h->cfg.ndim == 2 ? tn->order : 0;
   int rc = upload_grid(h);
   if (rc) return rc;
   if (h->graph) { hipGraphExecDestroy(h->graph); h->graph = nullptr; }
@@ -914,6 +948,7 @@ int claw_get_tuning(claw_t h, claw_tuning* tn) {
   tn->seg_rows = h->hg.seg_rows;
   tn->seg_rows_x = h->seg_rows_x > 0 ? h->seg_rows_x : h->hg.seg_rows;
   tn->segs = h->hg.segs;
+  tn->order = h->hg.order;
   return CLAW_OK;
 }
 
@@ -984,20 +1019,23 @@ int claw_autotune(claw_t h, int reps, claw_tuning* out) {
     apply(best);
     return best;
   };
+  h->hg.order = 0;
   const int best = tune(cands, [&](int c) { set_tiling(h, c); });
-  int best_x = 0;
+  int best_x = 0, best_order = 0;
   if (!rc && split(h->cfg)) {
     std::vector<int> cx;
     for (int c : {1, 2, 3, 4, 6, 8, 12, 16, 24, 32})
       if (c <= ny) cx.push_back(c);
     best_x = tune(cx, [&](int c) { h->seg_rows_x = c; });
   }
+  if (!rc && h->cfg.ndim == 2)
+    best_order = tune(std::vector<int>{0, 1, 2, 3}, [&](int o) { h->hg.order = o; });
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (rc) return rc;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[tune_key(h)] = std::make_pair(best, best_x);
+    g_tune[tune_key(h)] = Tiling{best, best_x, best_order};
   }
   if ((rc = upload_grid(h))) return rc;
   if (h->graph) { hipGraphExecDestroy(h->graph); h->graph = nullptr; }
@@ -1006,6 +1044,7 @@ int claw_autotune(claw_t h, int reps, claw_tuning* out) {
     out->seg_rows = h->hg.seg_rows;
     out->seg_rows_x = best_x > 0 ? best_x : h->hg.seg_rows;
     out->segs = h->hg.segs;
+    out->order = h->hg.order;
   }
   return sync(h);
 }
@@ -1043,41 +1082,79 @@ size_t claw_batch_workspace_bytes(int max_grids) {
   if (max_grids < 1) return 0;
   return align_up((size_t)max_grids * sizeof(GridDesc)) +
          align_up((size_t)(max_grids + 1) * sizeof(int)) +
-         align_up((size_t)max_grids * sizeof(Ctrl));
+         kBatchInFlight * align_up((size_t)max_grids * sizeof(Ctrl));
 }
 
 }  // extern "C"
 
 namespace {
-// Copy every member's controller into one contiguous array (one readback).
-int batch_gather(claw_batch_t b) {
+Ctrl* batch_dctrls(claw_batch_t b, int slot) {
+  return (Ctrl*)((char*)b->d_ctrls + slot * align_up((size_t)b->max_grids * sizeof(Ctrl)));
+}
+
+// Enqueue the copy of every member's controller into one contiguous device
+// array and from there into the pinned host array of group slot `slot`
+// (one readback), then the group's completion event.  No synchronisation.
+int batch_gather_async(claw_batch_t b, int slot) {
+  Ctrl* d = batch_dctrls(b, slot);
   for (size_t k = 0; k < b->members.size(); ++k)
-    HIPCHK(hipMemcpyAsync(b->d_ctrls + k, b->members[k]->d_ctrl, sizeof(Ctrl),
-                          hipMemcpyDeviceToDevice, b->stream));
+    HIPCHK(hipMemcpyAsync(d + k, b->members[k]->d_ctrl, sizeof(Ctrl), hipMemcpyDeviceToDevice,
+                          b->stream));
   if (!b->members.empty())
-    HIPCHK(hipMemcpyAsync(b->h_ctrls, b->d_ctrls, b->members.size() * sizeof(Ctrl),
+    HIPCHK(hipMemcpyAsync(b->h_ctrls[slot], d, b->members.size() * sizeof(Ctrl),
                           hipMemcpyDeviceToHost, b->stream));
-  HIPCHK(hipStreamSynchronize(b->stream));
-  b->gathered = (int)b->members.size();
+  b->snap[slot] = b->members;
+  HIPCHK(hipEventRecord(b->ev[slot], b->stream));
   return CLAW_OK;
 }
 
-int batch_rebuild(claw_batch_t b) {
-  std::vector<GridDesc> gd(b->members.size());
-  b->bstart.assign(b->members.size() + 1, 0);
-  for (size_t k = 0; k < b->members.size(); ++k) {
+// The member's controller as of the view (nullptr if it is not in it).
+const Ctrl* view_of(claw_batch_t b, claw_t h) {
+  if (!b->view || !b->view_members) return nullptr;
+  const std::vector<claw_t>& v = *b->view_members;
+  for (size_t k = 0; k < v.size(); ++k)
+    if (v[k] == h) return b->view + k;
+  return nullptr;
+}
+
+// Upload the member tables for the group about to be launched (slot `slot`),
+// stream-ordered after the groups already in flight, which keep reading the
+// previous tables until they end.
+int batch_rebuild(claw_batch_t b, int slot) {
+  const size_t ng = b->members.size();
+  GridDesc* gd = b->h_grids[slot];
+  int* bs = b->h_bstart[slot];
+  b->bstart.assign(ng + 1, 0);
+  for (size_t k = 0; k < ng; ++k) {
     gd[k] = b->members[k]->hg;
     b->bstart[k + 1] = b->bstart[k] + gd[k].nblocks;
   }
-  if (!gd.empty()) {
-    HIPCHK(hipMemcpyAsync(b->d_grids, gd.data(), gd.size() * sizeof(GridDesc),
-                          hipMemcpyHostToDevice, b->stream));
-    HIPCHK(hipMemcpyAsync(b->d_bstart, b->bstart.data(), b->bstart.size() * sizeof(int),
-                          hipMemcpyHostToDevice, b->stream));
+  for (size_t k = 0; k <= ng; ++k) bs[k] = b->bstart[k];
+  if (ng) {
+    HIPCHK(hipMemcpyAsync(b->d_grids, gd, ng * sizeof(GridDesc), hipMemcpyHostToDevice,
+                          b->stream));
+    HIPCHK(hipMemcpyAsync(b->d_bstart, bs, (ng + 1) * sizeof(int), hipMemcpyHostToDevice,
+                          b->stream));
   }
-  if (b->graph) { hipGraphExecDestroy(b->graph); b->graph = nullptr; }
+  if (b->graph) {
+    b->retired.emplace_back(b->graph, b->launched);
+    b->graph = nullptr;
+  }
   b->dirty = false;
   return CLAW_OK;
+}
+
+// Destroy the replaced graphs whose last launches have completed.
+void batch_reap(claw_batch_t b) {
+  auto it = b->retired.begin();
+  while (it != b->retired.end()) {
+    if (it->second <= b->waited) {
+      hipGraphExecDestroy(it->first);
+      it = b->retired.erase(it);
+    } else {
+      ++it;
+    }
+  }
 }
 }  // namespace
 
@@ -1104,11 +1181,17 @@ int claw_batch_create(int max_grids, void* d_ws, size_t ws_bytes, void* hip_stre
     delete b;
     return CLAW_E_DEVICE;
   }
-  if (hipHostMalloc((void**)&b->h_ctrls, (size_t)max_grids * sizeof(Ctrl), hipHostMallocDefault) !=
-      hipSuccess) {
-    if (b->own_stream) hipStreamDestroy(b->stream);
-    delete b;
-    return CLAW_E_DEVICE;
+  for (int k = 0; k < kBatchInFlight; ++k) {
+    if (hipHostMalloc((void**)&b->h_ctrls[k], (size_t)max_grids * sizeof(Ctrl),
+                      hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&b->h_grids[k], (size_t)max_grids * sizeof(GridDesc),
+                      hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&b->h_bstart[k], (size_t)(max_grids + 1) * sizeof(int),
+                      hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev[k], hipEventDisableTiming) != hipSuccess) {
+      claw_batch_destroy(b);
+      return CLAW_E_DEVICE;
+    }
   }
   *out = b;
   return CLAW_OK;
@@ -1117,9 +1200,15 @@ int claw_batch_create(int max_grids, void* d_ws, size_t ws_bytes, void* hip_stre
 int claw_batch_destroy(claw_batch_t b) {
   if (!b) return CLAW_E_INVAL;
   hipSetDevice(b->device);
-  hipStreamSynchronize(b->stream);
+  if (b->stream) hipStreamSynchronize(b->stream);
   if (b->graph) hipGraphExecDestroy(b->graph);
-  if (b->h_ctrls) hipHostFree(b->h_ctrls);
+  for (auto& r : b->retired) hipGraphExecDestroy(r.first);
+  for (int k = 0; k < kBatchInFlight; ++k) {
+    if (b->h_ctrls[k]) hipHostFree(b->h_ctrls[k]);
+    if (b->h_grids[k]) hipHostFree(b->h_grids[k]);
+    if (b->h_bstart[k]) hipHostFree(b->h_bstart[k]);
+    if (b->ev[k]) hipEventDestroy(b->ev[k]);
+  }
   if (b->own_stream) hipStreamDestroy(b->stream);
   delete b;
   return CLAW_OK;
@@ -1134,7 +1223,7 @@ int claw_batch_add(claw_batch_t b, claw_t h, double t_end) {
   for (claw_t o : b->members)
     if (o == h) return CLAW_E_INVAL;
   if (!b->members.empty() &&
-      (b->riemann != h->kr || b->fp32 != h->fp32 || b->limiter != h->hg.limiter ||
+      (b->riemann != h->kr || b->fp32 != h->pk || b->limiter != h->hg.limiter ||
        b->transverse != h->hg.transverse))
     return CLAW_E_INVAL;
   HIPCHK(hipSetDevice(b->device));
@@ -1147,12 +1236,11 @@ int claw_batch_add(claw_batch_t b, claw_t h, double t_end) {
   HIPCHK(hipMemcpyAsync(h->d_ctrl, h->h_ctrl, sizeof(Ctrl), hipMemcpyHostToDevice, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   b->riemann = h->kr;
-  b->fp32 = h->fp32;
+  b->fp32 = h->pk;
   b->limiter = h->hg.limiter;
   b->transverse = h->hg.transverse;
   b->members.push_back(h);
   b->dirty = true;
-  b->gathered = -1;
   return CLAW_OK;
 }
 
@@ -1161,13 +1249,19 @@ int claw_batch_remove(claw_batch_t b, claw_t h) {
   auto it = std::find(b->members.begin(), b->members.end(), h);
   if (it == b->members.end()) return CLAW_E_INVAL;
   HIPCHK(hipSetDevice(b->device));
-  HIPCHK(hipStreamSynchronize(b->stream));
-  int rc = read_ctrl(h);
-  if (rc) return rc;
-  absorb_ctrl(h, *h->h_ctrl);
+  const Ctrl* v = view_of(b, h);
+  if (v && !v->active) {
+    // stopped as of the view: later groups skip it (a stopped controller
+    // never restarts), so the view holds its final controller (no wait)
+    absorb_ctrl(h, *v);
+  } else {
+    if (b->launched > b->waited) HIPCHK(hipStreamSynchronize(b->stream));
+    int rc = read_ctrl(h);
+    if (rc) return rc;
+    absorb_ctrl(h, *h->h_ctrl);
+  }
   b->members.erase(it);
   b->dirty = true;
-  b->gathered = -1;
   return CLAW_OK;
 }
 
@@ -1192,57 +1286,82 @@ int claw_batch_member_clock(claw_batch_t b, claw_t h, claw_stats* st) {
 int claw_batch_finished(claw_batch_t b, claw_t* out, int cap, int* n_out) {
   if (!b || !n_out || (cap > 0 && !out)) return CLAW_E_INVAL;
   int n = 0;
-  if (b->gathered == (int)b->members.size()) {
-    for (size_t k = 0; k < b->members.size(); ++k)
-      if (!b->h_ctrls[k].active) {
-        if (n < cap) out[n] = b->members[k];
-        ++n;
-      }
+  if (b->view && b->view_members) {
+    const std::vector<claw_t>& v = *b->view_members;
+    for (size_t k = 0; k < v.size(); ++k) {
+      if (b->view[k].active) continue;
+      if (std::find(b->members.begin(), b->members.end(), v[k]) == b->members.end()) continue;
+      if (n < cap) out[n] = v[k];
+      ++n;
+    }
   }
   *n_out = std::min(n, cap);
   return CLAW_OK;
 }
 
-int claw_batch_advance(claw_batch_t b, int attempts, int* n_active) {
+int claw_batch_launch(claw_batch_t b, int attempts) {
   if (!b || attempts < 0) return CLAW_E_INVAL;
+  if (b->launched - b->waited >= kBatchInFlight) return CLAW_E_STATE;
   HIPCHK(hipSetDevice(b->device));
-  if (b->members.empty()) {
-    if (n_active) *n_active = 0;
-    return CLAW_OK;
-  }
   int rc;
-  if (b->dirty && (rc = batch_rebuild(b))) return rc;
+  const int slot = (int)(b->launched % kBatchInFlight);
+  if (b->dirty && (rc = batch_rebuild(b, slot))) return rc;
   const int ng = (int)b->members.size();
-  const int total = b->bstart[ng];
-  constexpr int kGraph = 16;
-  if (attempts >= kGraph && !b->graph) {
-    hipGraph_t g;
-    HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    for (int s = 0; s < kGraph; ++s)
-      launch_classic2d(b->riemann, b->fp32, b->limiter, b->transverse, total, b->stream, b->d_grids, b->d_bstart, ng,
-                       kDeviceCtrl, 0.0, 0);
-    HIPCHK(hipStreamEndCapture(b->stream, &g));
-    const hipError_t e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
-    HIPCHK(e);
-    b->graph_k = kGraph;
+  if (ng > 0) {
+    const int total = b->bstart[ng];
+    constexpr int kGraph = 16;
+    if (attempts >= kGraph && !b->graph) {
+      hipGraph_t g;
+      HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+      for (int s = 0; s < kGraph; ++s)
+        launch_classic2d(b->riemann, b->fp32, b->limiter, b->transverse, total, b->stream,
+                         b->d_grids, b->d_bstart, ng, kDeviceCtrl, 0.0, 0);
+      HIPCHK(hipStreamEndCapture(b->stream, &g));
+      const hipError_t e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      HIPCHK(e);
+      b->graph_k = kGraph;
+    }
+    int done = 0;
+    while (b->graph && attempts - done >= b->graph_k) {
+      HIPCHK(hipGraphLaunch(b->graph, b->stream));
+      done += b->graph_k;
+    }
+    for (; done < attempts; ++done)
+      HIPCHK(launch_classic2d(b->riemann, b->fp32, b->limiter, b->transverse, total, b->stream,
+                              b->d_grids, b->d_bstart, ng, kDeviceCtrl, 0.0, 0));
   }
-  int done = 0;
-  while (b->graph && attempts - done >= b->graph_k) {
-    HIPCHK(hipGraphLaunch(b->graph, b->stream));
-    done += b->graph_k;
-  }
-  for (; done < attempts; ++done)
-    HIPCHK(launch_classic2d(b->riemann, b->fp32, b->limiter, b->transverse, total, b->stream, b->d_grids, b->d_bstart, ng,
-                            kDeviceCtrl, 0.0, 0));
-  if ((rc = batch_gather(b))) return rc;
+  if ((rc = batch_gather_async(b, slot))) return rc;
+  b->launched += 1;
+  return CLAW_OK;
+}
+
+int claw_batch_wait(claw_batch_t b, int* n_active) {
+  if (!b) return CLAW_E_INVAL;
+  if (b->launched == b->waited) return CLAW_E_STATE;
+  HIPCHK(hipSetDevice(b->device));
+  const int slot = (int)(b->waited % kBatchInFlight);
+  HIPCHK(hipEventSynchronize(b->ev[slot]));
+  b->waited += 1;
+  batch_reap(b);
+  b->view = b->h_ctrls[slot];
+  b->view_members = &b->snap[slot];
   int act = 0, status = 0;
-  for (int k = 0; k < ng; ++k) {
-    act += b->h_ctrls[k].active ? 1 : 0;
-    if (b->h_ctrls[k].status) status = b->h_ctrls[k].status;
+  for (size_t k = 0; k < b->snap[slot].size(); ++k) {
+    act += b->view[k].active ? 1 : 0;
+    if (b->view[k].status) status = b->view[k].status;
   }
   if (n_active) *n_active = act;
   return status ? status : CLAW_OK;
+}
+
+int claw_batch_advance(claw_batch_t b, int attempts, int* n_active) {
+  if (!b || attempts < 0) return CLAW_E_INVAL;
+  int rc = CLAW_OK;
+  while (b->launched > b->waited && rc == CLAW_OK) rc = claw_batch_wait(b, nullptr);
+  if (rc) return rc;
+  if ((rc = claw_batch_launch(b, attempts))) return rc;
+  return claw_batch_wait(b, n_active);
 }
 
 }  // extern "C"

@@ -45,12 +45,38 @@ __host__ __device__ __forceinline__ int seg_begin(int seg, int n, int segs) {
   return (int)(((long long)seg * n) / segs);
 }
 
+// Tile (strip, segment) of workgroup lb of a grid with `strips` x `segs`
+// tiles.  order 0: strips fastest; 1: segments fastest; 2 and 3: the same
+// over XCD-grouped indices.  Consecutive workgroups of a launch go round-robin
+// to the GPU's 8 XCDs (each with its own L2); grouping gives XCD x the
+// contiguous band of tiles [start_x, start_x + count_x), so tiles that share
+// halo rows or columns mostly share an L2.  A bijection for any tile count;
+// results do not depend on the order.
+constexpr int kXcds = 8;
+__host__ __device__ __forceinline__ void tile_of(int lb, int strips, int segs, int order,
+                                                 int& strip, int& seg) {
+  int t = lb;
+  if (order >= 2) {
+    const int n = strips * segs, q = n / kXcds, r = n % kXcds;
+    const int x = lb % kXcds, k = lb / kXcds;
+    t = x * q + (x < r ? x : r) + k;
+  }
+  if (order & 1) {
+    seg = t % segs;
+    strip = t / segs;
+  } else {
+    strip = t % strips;
+    seg = t / strips;
+  }
+}
+
 // Everything a kernel needs about one grid.  Lives in device memory.
 struct GridDesc {
   int nx, ny;
   int strips, segs;               // column strips x row segments = workgroups
   int seg_rows;                   // rows of the longest segment
   int nblocks;                    // workgroups of one launch over this grid
+  int order;                      // tile order of the workgroups (see tile_of)
   int bc[4];                      // x-lower, x-upper, y-lower, y-upper
   int limiter, transverse, efix, scheme;
   int source;                     // 1: axisymmetric Euler source (r = y), fractional step

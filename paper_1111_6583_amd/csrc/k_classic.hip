@@ -88,7 +88,8 @@ __global__ __launch_bounds__(kLanes) void k_classic2d(const GridDesc* __restrict
     src = src_host;
   }
   const int lb = ngrids > 1 ? b - bstart[gi] : b;
-  const int strip = lb % G.strips, seg = lb / G.strips;
+  int strip, seg;
+  tile_of(lb, G.strips, G.segs, G.order, strip, seg);
   const int nx = G.nx, ny = G.ny;
   const size_t plane = (size_t)nx * ny;
   const int lane = threadIdx.x;
@@ -742,11 +743,40 @@ static hipError_t launch2d_t(int riemann, int lim, int trans, dim3 grid, hipStre
 
 // limiter and transverse mode are compile-time in the 2D kernel (no branches
 // in the marching loop); every member of a batch shares them
-hipError_t launch_classic2d(int riemann, int fp32, int lim, int trans, int nblocks, hipStream_t st,
+// plain FP32 (no compensation): shallow water only
+template <int LIM, int TRANS>
+static hipError_t launch2d_plain32_lt(dim3 grid, hipStream_t st, const GridDesc* g, const int* bs,
+                                      int ng, int mode, double dt, int src) {
+  hipLaunchKernelGGL((k_classic2d<float, ShallowWater<float, 2>, false, LIM, TRANS>), grid,
+                     dim3(kLanes), 0, st, g, bs, ng, mode, dt, src);
+  return hipGetLastError();
+}
+template <int LIM>
+static hipError_t launch2d_plain32_l(int trans, dim3 grid, hipStream_t st, const GridDesc* g,
+                                     const int* bs, int ng, int mode, double dt, int src) {
+  switch (trans) {
+    case 0: return launch2d_plain32_lt<LIM, 0>(grid, st, g, bs, ng, mode, dt, src);
+    case 1: return launch2d_plain32_lt<LIM, 1>(grid, st, g, bs, ng, mode, dt, src);
+    case 2: return launch2d_plain32_lt<LIM, 2>(grid, st, g, bs, ng, mode, dt, src);
+  }
+  return hipErrorInvalidValue;
+}
+
+// prec: 0 FP64, 1 FP32 with Kahan-compensated updates, 2 plain FP32
+hipError_t launch_classic2d(int riemann, int prec, int lim, int trans, int nblocks, hipStream_t st,
                             const GridDesc* d_grids, const int* d_bstart, int ngrids, int mode,
                             double dt, int src) {
   const dim3 grid(nblocks);
-  return fp32 ? launch2d_t<float, true>(riemann, lim, trans, grid, st, d_grids, d_bstart, ngrids,
+  if (prec == 2) {
+    if (riemann != 2) return hipErrorInvalidValue;
+    switch (lim) {
+      case 0: return launch2d_plain32_l<0>(trans, grid, st, d_grids, d_bstart, ngrids, mode, dt, src);
+      case 1: return launch2d_plain32_l<1>(trans, grid, st, d_grids, d_bstart, ngrids, mode, dt, src);
+      case 2: return launch2d_plain32_l<2>(trans, grid, st, d_grids, d_bstart, ngrids, mode, dt, src);
+    }
+    return hipErrorInvalidValue;
+  }
+  return prec ? launch2d_t<float, true>(riemann, lim, trans, grid, st, d_grids, d_bstart, ngrids,
                                         mode, dt, src)
               : launch2d_t<double, false>(riemann, lim, trans, grid, st, d_grids, d_bstart, ngrids,
                                           mode, dt, src);

@@ -196,18 +196,45 @@ __device__ __forceinline__ void stage_finish(const GridDesc& G, int mode, int fi
   }
 }
 
+// FP32 WENO5 keeps the stencil's rows in an LDS ring instead of registers:
+// row r enters slot r mod 5 (boundary conditions applied) over the row that
+// left the window, the y stencil reads the five rows of its own column and
+// the x stencil the four neighbouring columns of the row being finalised.
+// The window then costs no row-to-row moves and x-neighbours no lane shifts
+// (FP32 stage 59 against 62 us at 2048x1024).  FP64 keeps the register window:
+// there the ring saved no time at two waves per SIMD, and the register budget
+// of three waves (168) made the compiler spill (stage 160 us).
+template <typename R, int RH> struct UseRing {
+  static constexpr bool value = RH == 3 && sizeof(R) == 4;
+};
+
+// The ring of one wave: rows x components x 64 lanes, padded by two elements
+// at each end so that reads at lane +-2 of any row stay inside the array (the
+// edge lanes that read a neighbouring row's or the padding's values are halo
+// lanes whose results are discarded).
+template <typename R, int M, int NW>
+struct Ring {
+  R v[2 + NW * M * kLanes + 2];
+  __device__ __forceinline__ R& at(int slot, int k, int lane) {
+    return v[2 + (slot * M + k) * kLanes + lane];
+  }
+};
+
 template <typename R, class P, int RH, int KIND, bool KAHAN>
 __global__ __launch_bounds__(kLanes) void k_sharp2d(const GridDesc* __restrict__ grids, int mode,
                                                     double dt_host, StageArgs sa) {
   constexpr int M = P::M, NW = 2 * RH - 1;
   constexpr int H = RH, U = kLanes - 2 * H;
+  constexpr bool kRing = UseRing<R, RH>::value;
+  __shared__ Ring<R, M, kRing ? NW : 1> ring;
   const GridDesc& G = grids[0];
   Ctrl* ctrl = G.ctrl;
   double dtd;
   if (!stage_dt(ctrl, mode, dt_host, sa.first, dtd)) return;
   const R gdt = (R)(sa.gamma * dtd);
   const R a1 = (R)sa.a1, b1 = (R)sa.b1, a2 = (R)sa.a2, b2 = (R)sa.b2, wq = (R)sa.w;
-  const int strip = blockIdx.x % G.strips, seg = blockIdx.x / G.strips;
+  int strip, seg;
+  tile_of(blockIdx.x, G.strips, G.segs, G.order, strip, seg);
   const int nx = G.nx, ny = G.ny;
   const size_t plane = (size_t)nx * ny;
   const int lane = threadIdx.x;
@@ -236,14 +263,16 @@ __global__ __launch_bounds__(kLanes) void k_sharp2d(const GridDesc* __restrict__
     load_aux<R, P>(aN, aux, plane, nx, mx, map_axis(j0 - 2 * RH + 1, ny, bcy0, bcy1, H));
   }
 
-  R w[NW][M];          // rows r-NW+1 .. r
+  constexpr int NWR = kRing ? 1 : NW;
+  R w[NWR][M];         // register window: rows r-NW+1 .. r
   R qyl_prev[M], g_lo[M];
 #pragma unroll
   for (int k = 0; k < M; ++k) {
     qyl_prev[k] = g_lo[k] = R(0);
 #pragma unroll
-    for (int s = 0; s < NW; ++s) w[s][k] = R(0);
+    for (int s = 0; s < NWR; ++s) w[s][k] = R(0);
   }
+  int slot = 0;        // ring slot of row r
   const gconst<R> P1 = as_gconst<R>(sa.p1);
   const gconst<R> Qn = as_gconst<R>(G.q[0]);
   const gconst<R> Cn = as_gconst<R>(G.c[0]);
@@ -265,12 +294,23 @@ __global__ __launch_bounds__(kLanes) void k_sharp2d(const GridDesc* __restrict__
   for (int r = j0 - RH; r <= j1 + RH - 1; ++r) {
 #pragma unroll
     for (int k = 0; k < M; ++k) { up[k] = pp[k]; uq[k] = pq[k]; uc[k] = pc[k]; }
+    if constexpr (kRing) {
+      // row r replaces row r - NW in the ring; the barriers keep the other
+      // lanes' reads of the old row before, and their reads of row r after
+      __syncthreads();
 #pragma unroll
-    for (int s = 0; s < NW - 1; ++s)
+      for (int k = 0; k < M; ++k) ring.at(slot, k, lane) = nxt[k];
+      __syncthreads();
+    } else {
 #pragma unroll
-      for (int k = 0; k < M; ++k) w[s][k] = w[s + 1][k];
+      for (int s = 0; s < NW - 1; ++s)
 #pragma unroll
-    for (int k = 0; k < M; ++k) w[NW - 1][k] = nxt[k];
+        for (int k = 0; k < M; ++k) w[s][k] = w[s + 1][k];
+#pragma unroll
+      for (int k = 0; k < M; ++k) w[NW - 1][k] = nxt[k];
+    }
+    // ring slot of window row s (0 = oldest, NW - 1 = row r)
+    auto wslot = [&](int s_) { const int t = slot + 1 + s_; return t >= NW ? t - NW : t; };
     const bool more = r + 1 <= j1 + RH - 1;
     AxisMap mynext{0, 0, 0};
     if (more) {
@@ -303,7 +343,10 @@ __global__ __launch_bounds__(kLanes) void k_sharp2d(const GridDesc* __restrict__
       for (int k = 0; k < M; ++k) {
         R col[NW];
 #pragma unroll
-        for (int s = 0; s < NW; ++s) col[s] = w[s][k];
+        for (int s = 0; s < NW; ++s) {
+          if constexpr (kRing) col[s] = ring.at(wslot(s), k, lane);
+          else col[s] = w[s][k];
+        }
         weno_edges<RH>(col, eps, qyl[k], qyr[k]);
       }
       if (r >= j0 + RH - 1) {
@@ -314,15 +357,23 @@ __global__ __launch_bounds__(kLanes) void k_sharp2d(const GridDesc* __restrict__
         if (r >= j0 + RH) {
           // row f = c-1 (window row RH-2) is complete: x edge values, x-face fluxes
           R xl[M], xr[M];
+          R Sf[M];
 #pragma unroll
           for (int k = 0; k < M; ++k) {
             R row[NW];
-            row[RH - 1] = w[RH - 2][k];
+            if constexpr (kRing) {
+              const int fs = wslot(RH - 2);
 #pragma unroll
-            for (int s = 1; s < RH; ++s) {
-              row[RH - 1 - s] = shfl_prev(row[RH - s]);
-              row[RH - 1 + s] = shfl_next(row[RH - 2 + s]);
+              for (int s = 0; s < NW; ++s) row[s] = ring.at(fs, k, lane - (RH - 1) + s);
+            } else {
+              row[RH - 1] = w[RH - 2][k];
+#pragma unroll
+              for (int s = 1; s < RH; ++s) {
+                row[RH - 1 - s] = shfl_prev(row[RH - s]);
+                row[RH - 1 + s] = shfl_next(row[RH - 2 + s]);
+              }
             }
+            Sf[k] = row[RH - 1];
             weno_edges<RH>(row, eps, xl[k], xr[k]);
           }
           R ql[M], F[M], al[NA];
@@ -336,7 +387,7 @@ __global__ __launch_bounds__(kLanes) void k_sharp2d(const GridDesc* __restrict__
           for (int k = 0; k < M; ++k) {
             const R Fr = shfl_next(F[k]);
             Lv[k] = -(Fr - F[k]) * rdx - (g_up[k] - g_lo[k]) * rdy;
-            Sc[k] = w[RH - 2][k];
+            Sc[k] = Sf[k];
           }
           store = true;
         }
@@ -354,6 +405,7 @@ __global__ __launch_bounds__(kLanes) void k_sharp2d(const GridDesc* __restrict__
     if (store && own)
       stage_store<R, P, KIND, KAHAN>(sa, O1, O2, Cout, (size_t)(r - RH) * nx + i, plane, Sc, Lv,
                                      gdt, a1, b1, a2, b2, wq, up, uq, uc);
+    slot = slot + 1 == NW ? 0 : slot + 1;
   }
   const double speed = own ? max_nan((double)smx * (1.0 / G.dx), (double)smy * (1.0 / G.dy))
                            : (own_face ? (double)smx * (1.0 / G.dx) : 0.0);

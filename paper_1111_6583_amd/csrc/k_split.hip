@@ -128,7 +128,8 @@ __global__ __launch_bounds__(kLanes) void k_sweep_x(const GridDesc* __restrict__
     dt = dt_host;
     src = src_host;
   }
-  const int strip = blockIdx.x % sa.strips, seg = blockIdx.x / sa.strips;
+  int strip, seg;
+  tile_of(blockIdx.x, sa.strips, sa.segs, G.order, strip, seg);
   const int nx = G.nx, ny = G.ny;
   const size_t plane = (size_t)nx * ny;
   const int lane = threadIdx.x;
@@ -237,7 +238,8 @@ __global__ __launch_bounds__(kLanes) void k_sweep_y(const GridDesc* __restrict__
     dt = dt_host;
     src = src_host;
   }
-  const int strip = blockIdx.x % sa.strips, seg = blockIdx.x / sa.strips;
+  int strip, seg;
+  tile_of(blockIdx.x, sa.strips, sa.segs, G.order, strip, seg);
   const int nx = G.nx, ny = G.ny;
   const size_t plane = (size_t)nx * ny;
   const int i = strip * kLanes + (int)threadIdx.x;

@@ -33,7 +33,9 @@ def _aligned_workspace(nbytes: int, device):
 class Solver:
     """One grid: a libclaw handle over a torch-allocated workspace."""
 
-    def __init__(self, spec: dict, device="cuda:0"):
+    def __init__(self, spec: dict, device="cuda:0", stream=None):
+        """stream: a torch.cuda.Stream the handle enqueues on (None: the
+        library creates a private stream)."""
         self.lib = load_library()
         self.spec = dict(spec)
         self.cfg = make_config(spec)
@@ -49,8 +51,10 @@ class Solver:
         nd = self.cfg.ndim
         self.shape = (self.m, self.cfg.num_cells[1] if nd == 2 else 1, self.cfg.num_cells[0])
         self._ws, ptr = _aligned_workspace(self.nbytes, self.device)
+        self.stream = stream
         h = C.c_void_p()
-        check(self.lib.claw_create(C.byref(self.cfg), C.c_void_p(ptr), self.nbytes, None,
+        check(self.lib.claw_create(C.byref(self.cfg), C.c_void_p(ptr), self.nbytes,
+                                   None if stream is None else C.c_void_p(stream.cuda_stream),
                                    C.byref(h)), "claw_create")
         self.h = h
 
@@ -123,14 +127,16 @@ class Solver:
         return ms.value
 
     # -- tiling ------------------------------------------------------------
-    def set_tuning(self, seg_rows: int = 0, seg_rows_x: int = 0, segs: int = 0):
+    def set_tuning(self, seg_rows: int = 0, seg_rows_x: int = 0, segs: int = 0, order: int = 0):
         """Rows per workgroup of the 2D kernels (the y sweeps of a split
         step) and of the x sweeps of a split step (0: seg_rows); segs > 0
-        sets the number of row segments instead of seg_rows."""
+        sets the number of row segments instead of seg_rows; order: tile
+        order over the workgroups (0-3, see claw_tuning)."""
         tn = ClawTuning()
         tn.seg_rows = int(seg_rows)
         tn.seg_rows_x = int(seg_rows_x)
         tn.segs = int(segs)
+        tn.order = int(order)
         check(self.lib.claw_set_tuning(self.h, C.byref(tn)), "claw_set_tuning")
 
     def get_segs(self) -> int:
@@ -142,6 +148,11 @@ class Solver:
         tn = ClawTuning()
         check(self.lib.claw_get_tuning(self.h, C.byref(tn)), "claw_get_tuning")
         return tn.seg_rows
+
+    def get_order(self) -> int:
+        tn = ClawTuning()
+        check(self.lib.claw_get_tuning(self.h, C.byref(tn)), "claw_get_tuning")
+        return tn.order
 
     def get_tuning_x(self) -> int:
         tn = ClawTuning()
@@ -168,15 +179,17 @@ class Solver:
 class Batch:
     """Several classic 2D grids advanced by one launch per attempt."""
 
-    def __init__(self, max_grids: int, device="cuda:0"):
+    def __init__(self, max_grids: int, device="cuda:0", stream=None):
         self.lib = load_library()
         self.device = torch.device(device)
         torch.cuda.set_device(self.device)
         nb = int(self.lib.claw_batch_workspace_bytes(int(max_grids)))
         self._ws, ptr = _aligned_workspace(nb, self.device)
+        self.stream = stream
         h = C.c_void_p()
-        check(self.lib.claw_batch_create(int(max_grids), C.c_void_p(ptr), nb, None, C.byref(h)),
-              "claw_batch_create")
+        check(self.lib.claw_batch_create(int(max_grids), C.c_void_p(ptr), nb,
+                                         None if stream is None else C.c_void_p(stream.cuda_stream),
+                                         C.byref(h)), "claw_batch_create")
         self.h = h
         self.members = []
 
@@ -191,6 +204,16 @@ class Batch:
     def advance(self, attempts: int) -> int:
         n = C.c_int(0)
         check(self.lib.claw_batch_advance(self.h, int(attempts), C.byref(n)), "claw_batch_advance")
+        return n.value
+
+    def launch(self, attempts: int):
+        """Enqueue a group of attempts without waiting (at most two in flight)."""
+        check(self.lib.claw_batch_launch(self.h, int(attempts)), "claw_batch_launch")
+
+    def wait(self) -> int:
+        """Wait for the oldest group in flight; returns its active members."""
+        n = C.c_int(0)
+        check(self.lib.claw_batch_wait(self.h, C.byref(n)), "claw_batch_wait")
         return n.value
 
     def finished(self):

@@ -194,3 +194,20 @@ def test_static_step_size_limit_is_checked_on_the_host():
     assert lib.claw_step_static(C.byref(c), a, None, b, 0.0, z, None) == -1       # dt <= 0
     el, _, _ = W.layered_elastic(64)
     assert lib.claw_step_static(C.byref(_claw.make_config(el)), a, None, b, 1e-3, z, None) == -1
+
+
+def test_plain_fp32_precision_only_where_built():
+    """CLAW_FP32 (no compensation) exists for classic 2D shallow water and
+    SharpClaw 2D Euler with WENO5; other configurations are refused, and its
+    workspace holds no compensation arrays."""
+    lib = _claw.load_library()
+    sw, _ = W.radial_dam_break(256)
+    nk = lib.claw_workspace_bytes(C.byref(_claw.make_config(dict(sw, precision="fp32_kahan"))))
+    npl = lib.claw_workspace_bytes(C.byref(_claw.make_config(dict(sw, precision="fp32"))))
+    assert npl > 0 and npl < nk - 2 * 3 * 256 * 256 * 4 + 64 * 1024
+    eu, _ = W.shock_bubble(128, 64)
+    assert lib.claw_workspace_bytes(C.byref(_claw.make_config(dict(eu, precision="fp32")))) > 0
+    for bad in (dict(eu, precision="fp32", weno_order=7), dict(sw, precision="fp32", dimensional_split="godunov")):
+        assert lib.claw_workspace_bytes(C.byref(_claw.make_config(bad))) == 0
+    el, _, _ = W.layered_elastic(64)
+    assert lib.claw_workspace_bytes(C.byref(_claw.make_config(dict(el, precision="fp32")))) == 0

@@ -872,13 +872,32 @@ def test_tiling_does_not_change_results(prec):
         outs.append(replay(spec, q, [2e-3] * 12, seg_rows=sr))
     np.testing.assert_array_equal(outs[0], outs[1])
     np.testing.assert_array_equal(outs[0], outs[2])
-    # segment counts whose segments start on odd and even rows alike
-    for segs in (7, 13, 37):
+    # segment counts whose segments start on odd and even rows alike, in
+    # every tile order
+    for segs, order in ((7, 0), (13, 1), (37, 2), (13, 3), (7, 3)):
         s = solver(spec, q)
-        s.set_tuning(segs=segs)
+        s.set_tuning(segs=segs, order=order)
         for _ in range(12):
             s.step(2e-3)
         np.testing.assert_array_equal(s.get_state(), outs[0])
+        s.close()
+
+
+@pytest.mark.parametrize("order", [0, 1, 2, 3])
+def test_tile_order_does_not_change_results(order):
+    """Every tile order gives the same bits on every path: classic 2D, split
+    sweeps, SharpClaw (FP32 ring and FP64 register windows)."""
+    say("case: tile order", order, "bitwise, classic / split / SharpClaw")
+    sw, qs = W.radial_dam_break(130, ny=77)
+    eu, qe = W.shock_bubble(150, 70)
+    for spec, q, dt in ((sw, qs, 2e-3), (dict(sw, dimensional_split="strang"), qs, 2e-3),
+                        (eu, qe, 1e-3), (dict(eu, precision="fp32_kahan"), qe, 1e-3)):
+        ref = replay(spec, q, [dt] * 5, seg_rows=9)
+        s = solver(spec, q)
+        s.set_tuning(segs=11, order=order)
+        for _ in range(5):
+            s.step(dt)
+        np.testing.assert_array_equal(s.get_state(), ref)
         s.close()
 
 
