@@ -164,7 +164,7 @@ def grid_label(q) -> str:
     return f"{q.shape[2]}x{q.shape[1]}"
 
 
-def timed_run(spec, q, aux, steps, warmup, t_end, segs=0, order=0, graph_k=16):
+def timed_run(spec, q, aux, steps, warmup, t_end, segs=0, order=0, seg_rows_x=0, graph_k=16):
     import torch
     from paper_1111_6583_amd import Solver
     s = Solver(spec)
@@ -172,7 +172,7 @@ def timed_run(spec, q, aux, steps, warmup, t_end, segs=0, order=0, graph_k=16):
     if aux is not None:
         s.set_aux(aux)
     if segs > 0:
-        s.set_tuning(segs=segs, order=order)
+        s.set_tuning(segs=segs, order=order, seg_rows_x=seg_rows_x)
     else:
         s.autotune(reps=3)
     if warmup:
@@ -223,13 +223,13 @@ def roofline(r, launches_per_step, bytes_per_cell, flops_per_cell, kernel, dtype
     return out
 
 
-def run_workload(W, name, precision, steps, warmup, segs=0, order=0):
+def run_workload(W, name, precision, steps, warmup, segs=0, order=0, seg_rows_x=0):
     desc, make, lps, bpc, fpc, kernel, t_end, sw = WORKLOADS[name]
     spec, q, aux = make(W)
     if sw is not None and steps is None:
         steps, warmup = sw
     r = timed_run(dict(spec, precision=precision), q, aux, steps, warmup, t_end, segs=segs,
-                  order=order)
+                  order=order, seg_rows_x=seg_rows_x)
     dtype = "f64" if precision == "fp64" else "f32"
     r["roofline"] = roofline(r, lps, bpc[precision], fpc,
                              kernel.format(R="double" if dtype == "f64" else "float"), dtype)
@@ -441,6 +441,8 @@ def main():
     ap.add_argument("--segs", type=int, default=0,
                     help="fixed number of row segments of the headline (0: autotune)")
     ap.add_argument("--order", type=int, default=0, help="tile order with --segs (0-3)")
+    ap.add_argument("--seg-rows-x", type=int, default=0,
+                    help="rows per segment of a split step's x sweeps with --segs")
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--cpu-steps-1t", type=int, default=5)
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -462,7 +464,7 @@ def main():
     from paper_1111_6583_amd import workloads as W
 
     log(f"headline: {a.headline} {a.precision}")
-    h = run_workload(W, a.headline, a.precision, a.steps, a.warmup, a.segs, a.order)
+    h = run_workload(W, a.headline, a.precision, a.steps, a.warmup, a.segs, a.order, a.seg_rows_x)
     line = {
         "metric": "cell-updates/s per GPU (FP64 vs FP32 at stated L1 err); p50/p99 solve latency",
         "value": h["value"], "unit": "cell-updates/s", "n_gpus": 1, "steps": h["steps"],

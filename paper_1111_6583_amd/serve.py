@@ -137,6 +137,25 @@ class Tuner:
                 for n in self.buckets}
 
 
+class _PinnedPool:
+    """Reusable pinned host buffers for results leaving the device (sizes
+    rounded up to 1 MiB): a fresh pinned allocation of every request's size
+    would cost the host more than the copy."""
+
+    def __init__(self):
+        self.free = collections.defaultdict(list)
+
+    def take(self, shape, dtype=torch.float64):
+        n = int(np.prod(shape)) * torch.tensor([], dtype=dtype).element_size()
+        key = -(-n // (1 << 20)) << 20
+        buf = self.free[key].pop() if self.free[key] else torch.empty(key, dtype=torch.uint8,
+                                                                        pin_memory=True)
+        return buf, buf[:n].view(dtype).view(shape)
+
+    def give(self, buf):
+        self.free[buf.numel()].append(buf)
+
+
 class _Streams:
     """A small pool of non-blocking torch streams for request handles."""
 
@@ -160,15 +179,16 @@ def _admit(req, precision, tuner, device, stream):
     return s
 
 
-def collect(copying, lat, results, keep, t0, block):
+def collect(copying, lat, results, keep, t0, block, pool):
     """Complete the retirements whose result has reached host memory (all of
     them if block): latency ends when that is seen (checked once per group,
     so a result may be counted up to one group late).  Removes them from
-    `copying`; returns their cell-updates."""
+    `copying`, returns their pinned buffers to the pool and their
+    cell-updates."""
     cu = 0
     still = []
     for item in copying:
-        req, ck, dev, host, ev = item
+        req, ck, dev, buf, host, ev = item
         if block:
             ev.synchronize()
         elif not ev.query():
@@ -177,7 +197,8 @@ def collect(copying, lat, results, keep, t0, block):
         lat[req["id"]] = time.perf_counter() - t0 - req["arrival"]
         cu += req["n"] * req["n"] * ck["accepted"]
         if keep:
-            results[req["id"]] = (host.numpy(), ck)
+            results[req["id"]] = (host.numpy().copy(), ck)
+        pool.give(buf)
     copying[:] = still
     return cu
 
@@ -200,7 +221,8 @@ def run_trace(trace, budget_bytes=8 << 30, max_grids=64, attempts=16, precision=
     max_resident = 0
     in_flight = 0
     graveyard = []         # handles retired at the last wait: kept until one more group completes
-    copying = []           # (request, clock, device result, pinned host result, copy-done event)
+    copying = []           # (request, clock, device result, pinned buffer, host view, copy-done event)
+    pool = _PinnedPool()
     groups = 0
     # host time by activity, and the GPU's busy time (events around each group)
     t_admit = t_retire = t_wait = 0.0
@@ -240,7 +262,7 @@ def run_trace(trace, budget_bytes=8 << 30, max_grids=64, attempts=16, precision=
                 continue          # queue a second group before waiting
         if not in_flight:
             cell_updates += collect(copying, lat, results, keep_results, t0,
-                                    block=not (pending or waiting))
+                                    block=not (pending or waiting), pool=pool)
             if pending:
                 time.sleep(max(0.0, pending[0]["arrival"] - (time.perf_counter() - t0)))
             continue
@@ -263,15 +285,15 @@ def run_trace(trace, budget_bytes=8 << 30, max_grids=64, attempts=16, precision=
             # the result leaves the device asynchronously: float64 on the
             # device, then into pinned host memory on the request's stream
             dev = s.get_state(device=True)
-            host = torch.empty(dev.shape, dtype=dev.dtype, pin_memory=True)
+            buf, host = pool.take(dev.shape)
             with torch.cuda.stream(s.stream):
                 host.copy_(dev, non_blocking=True)
                 ev = torch.cuda.Event()
                 ev.record(s.stream)
-            copying.append((req, ck, dev, host, ev))
+            copying.append((req, ck, dev, buf, host, ev))
             graveyard.append(s)
             used -= nb
-        cell_updates += collect(copying, lat, results, keep_results, t0, block=False)
+        cell_updates += collect(copying, lat, results, keep_results, t0, block=False, pool=pool)
         t_retire += time.perf_counter() - tr
     wall = time.perf_counter() - t0
     for s in graveyard:

@@ -13,6 +13,7 @@ checks status codes.
 
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 
 import numpy as np
@@ -75,7 +76,9 @@ class Solver:
 
     def get_state(self, device=False):
         if device:
-            out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+            # allocated on the handle's stream, which writes it
+            with torch.cuda.stream(self.stream) if self.stream is not None else contextlib.nullcontext():
+                out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
             check(self.lib.claw_get_state(self.h, C.c_void_p(out.data_ptr()), 1), "claw_get_state")
             return out
         out = np.empty(self.shape, dtype=np.float64)
