@@ -38,6 +38,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# timed steps by default: whole graphs of 16 attempts, so that no early-exit
+# launch enters the timed region or a kernel trace of it
+DEFAULT_STEPS = 192
 # Published MI355X vector peaks (dense): FP64 78.6 TFLOP/s; FP32 157.3 TFLOP/s,
 # which counts packed dual FP32 issue (the kernels are built without packed
 # FP32, so half of it is their ceiling)
@@ -122,6 +125,9 @@ def _split(W, kind):
     return dict(spec, dimensional_split=kind), q, None
 
 
+# template precision in kernel labels ("float+Kahan": FP32 with a compensated update)
+KERNEL_PRECISION = {"fp64": "double", "fp32_kahan": "float+Kahan", "fp32": "float"}
+
 # name -> description, maker, launches per step, bytes per cell and launch by
 # precision, flops per cell and launch, kernel label, t_end, (steps, warmup)
 WORKLOADS = {
@@ -138,14 +144,14 @@ WORKLOADS = {
     "elastic": ("2D linear elasticity, 16 seeded layers, classic variable-coefficient Riemann "
                 "solver, MC, full transverse, 2048x2048, CFL 0.9",
                 lambda W: W.layered_elastic(2048), 1, {"fp64": 104, "fp32_kahan": 92}, None,
-                "k_classic2d<{R},Elastic>", 10.0, (100, 10)),
+                "k_classic2d<{R},Elastic>", 10.0, (96, 16)),
     "euler_axisym": ("classic axisymmetric Euler shock-bubble 1280x320 (Roe, tracer, source)",
                      lambda W: W.shock_bubble_axisym(1280, 320) + (None,), 1, {"fp64": 80}, 1160.0,
-                     "k_classic2d<{R},EulerRoe+tracer>", 1.0, (100, 10)),
+                     "k_classic2d<{R},EulerRoe+tracer>", 1.0, (96, 16)),
     "psystem": ("2D p-system checkerboard 4800^2 (20 x 20 periods, 240 cells each), SharpClaw "
                 "WENO5 + SSPRK(10,4)", lambda W: W.psystem_checkerboard(240, 20), 10,
                 {"fp64": 71.2, "fp32_kahan": 39.2}, 696.0, "k_sharp2d<{R},PSystem,SSPRK104>",
-                1e9, (10, 2)),
+                1e9, (16, 16)),
     "sw_godunov": ("2D shallow-water radial dam break 1024^2, Godunov-split sweeps",
                    lambda W: _split(W, "godunov"), 2, {"fp64": 48}, 173.0,
                    "k_sweep_x/y<{R},ShallowWater> (godunov)", 1.0, None),
@@ -157,7 +163,7 @@ for _o in (5, 7, 9, 17):
     WORKLOADS[f"euler_ssp104_weno{_o}"] = (
         f"2D Euler shock-bubble 2048x1024, SharpClaw SSPRK(10,4) WENO{_o}, CFL 2.45/2.5",
         (lambda o: (lambda W: _sb104(W, o)))(_o), 10, {"fp64": 73.6}, euler_stage_flops(_o),
-        f"k_sharp2d<{{R}},EulerHLLE,SSPRK104,WENO{_o}>", 1.0, (10, 2))
+        f"k_sharp2d<{{R}},EulerHLLE,SSPRK104,WENO{_o}>", 1.0, (16, 16))
 
 
 def grid_label(q) -> str:
@@ -185,7 +191,8 @@ def timed_run(spec, q, aux, steps, warmup, t_end, segs=0, order=0, seg_rows_x=0,
     wall = time.perf_counter() - t0
     acc = st["accepted"] - c0["accepted"]
     ncell = int(q.shape[1] * q.shape[2])
-    out = dict(cells=ncell, grid=grid_label(q), steps=acc, rejected=st["rejected"] - c0["rejected"],
+    out = dict(cells=ncell, grid=grid_label(q), steps=acc, warmup=warmup,
+               rejected=st["rejected"] - c0["rejected"],
                wall_s=wall, gpu_ms=st["gpu_ms"], segs=s.get_segs(), seg_rows=s.get_tuning(),
                order=s.get_order(), t=st["t"], value=ncell * acc / wall,
                ms_per_step=1e3 * wall / max(acc, 1))
@@ -226,13 +233,13 @@ def roofline(r, launches_per_step, bytes_per_cell, flops_per_cell, kernel, dtype
 def run_workload(W, name, precision, steps, warmup, segs=0, order=0, seg_rows_x=0):
     desc, make, lps, bpc, fpc, kernel, t_end, sw = WORKLOADS[name]
     spec, q, aux = make(W)
-    if sw is not None and steps is None:
-        steps, warmup = sw
+    if steps is None:
+        steps, warmup = sw if sw is not None else (DEFAULT_STEPS, warmup)
     r = timed_run(dict(spec, precision=precision), q, aux, steps, warmup, t_end, segs=segs,
                   order=order, seg_rows_x=seg_rows_x)
     dtype = "f64" if precision == "fp64" else "f32"
-    r["roofline"] = roofline(r, lps, bpc[precision], fpc,
-                             kernel.format(R="double" if dtype == "f64" else "float"), dtype)
+    r["roofline"] = roofline(r, lps, bpc[precision], fpc, kernel.format(R=KERNEL_PRECISION[precision]),
+                             dtype)
     r["workload"] = desc
     r["precision"] = precision
     return r
@@ -432,8 +439,9 @@ def copy_only(mib, launches):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=None,
+                    help=f"timed steps (default {DEFAULT_STEPS}, or the workload's own count)")
+    ap.add_argument("--warmup", type=int, default=16)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--headline", choices=sorted(WORKLOADS), default="euler",
                     help="workload of the headline line (default: the shock-bubble)")
@@ -468,7 +476,7 @@ def main():
     line = {
         "metric": "cell-updates/s per GPU (FP64 vs FP32 at stated L1 err); p50/p99 solve latency",
         "value": h["value"], "unit": "cell-updates/s", "n_gpus": 1, "steps": h["steps"],
-        "warmup": a.warmup, "ms_per_step": h["ms_per_step"], "higher_is_better": True,
+        "warmup": h["warmup"], "ms_per_step": h["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if a.precision == "fp64" else "f32",
         "data": "synthetic (seeded initial data generated on the host)",
@@ -488,8 +496,7 @@ def main():
                            ("euler_ssp104_weno5", "fp64"), ("euler_ssp104_weno7", "fp64"),
                            ("euler_ssp104_weno9", "fp64"), ("euler_ssp104_weno17", "fp64")):
             log(f"{name} {prec}")
-            r = run_workload(W, name, prec, None if WORKLOADS[name][7] else a.steps,
-                             a.warmup)
+            r = run_workload(W, name, prec, a.steps, a.warmup)
             if prec != "fp64":
                 err, sample = l1_sample(W, name, prec)
                 r["l1_err_vs_fp64_oracle"] = err
