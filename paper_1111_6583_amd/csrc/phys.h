@@ -811,32 +811,38 @@ struct PSystem {
 
 // WENO5 (Jiang-Shu), component-wise: from the five cell averages centred on
 // cell i, the value at its right edge (qL, the left state of face i+1/2) and
-// at its left edge (qR, the right state of face i-1/2).  The smoothness
-// indicators are shared by both edges.  With D_k = (eps + beta_k)^2 the
-// normalised weights d_k/D_k / sum_j d_j/D_j equal d_k P_k / sum_j d_j P_j,
-// P_k = prod_{j != k} D_j, so each edge needs one reciprocal.
+// at its left edge (qR, the right state of face i-1/2).  Everything is
+// written in the first differences da..dd of the window:
+//  - smoothness indicators: 13/12 t^2 + 1/4 u^2 with t the stencil's second
+//    difference and u its one-sided derivative term; the weights use
+//    4 (eps + beta_k) = 4 eps + 13/3 t^2 + u^2, which leaves the normalised
+//    weights unchanged;
+//  - with D_k = (4 eps + 4 beta_k)^2, the weights d_k/D_k / sum_j d_j/D_j
+//    equal d_k P_k / sum_j d_j P_j, P_k = prod_{j != k} D_j, so each edge
+//    needs one reciprocal; the linear weights (1, 6, 3)/10 of the right edge
+//    and (3, 6, 1)/10 of the left share 6 P_1 and are not normalised;
+//  - the three candidate edge values, times 6, relative to the centre value:
+//    the result is v0 plus a weighted correction, so the differences, not
+//    the values, carry the rounding.
 template <typename R>
 __device__ __forceinline__ void weno5_edges(R vm2, R vm1, R v0, R vp1, R vp2, R eps, R& qL, R& qR) {
-  const R t0 = vm2 - R(2) * vm1 + v0, u0 = vm2 - R(4) * vm1 + R(3) * v0;
-  const R t1 = vm1 - R(2) * v0 + vp1, u1 = vm1 - vp1;
-  const R t2 = v0 - R(2) * vp1 + vp2, u2 = R(3) * v0 - R(4) * vp1 + vp2;
-  const R c13 = R(13.0 / 12.0);
-  const R e0 = eps + (c13 * t0 * t0 + R(0.25) * u0 * u0);
-  const R e1 = eps + (c13 * t1 * t1 + R(0.25) * u1 * u1);
-  const R e2 = eps + (c13 * t2 * t2 + R(0.25) * u2 * u2);
+  const R da = vm1 - vm2, db = v0 - vm1, dc = vp1 - v0, dd = vp2 - vp1;
+  const R t0 = db - da, t1 = dc - db, t2 = dd - dc;
+  const R u0 = R(3) * db - da, u1 = db + dc, u2 = dd - R(3) * dc;
+  const R c = R(13.0 / 3.0), e4 = R(4) * eps;
+  const R e0 = (c * t0) * t0 + (u0 * u0 + e4);
+  const R e1 = (c * t1) * t1 + (u1 * u1 + e4);
+  const R e2 = (c * t2) * t2 + (u2 * u2 + e4);
   const R D0 = e0 * e0, D1 = e1 * e1, D2 = e2 * e2;
-  const R P0 = D1 * D2, P1 = D0 * D2, P2 = D0 * D1;
-  // candidate edge values times 6
-  const R l0 = R(2) * vm2 - R(7) * vm1 + R(11) * v0;
-  const R l1 = -vm1 + R(5) * v0 + R(2) * vp1;
-  const R l2 = R(2) * v0 + R(5) * vp1 - vp2;
-  const R r0 = -vm2 + R(5) * vm1 + R(2) * v0;
-  const R r1 = R(2) * vm1 + R(5) * v0 - vp1;
-  const R r2 = R(11) * v0 - R(7) * vp1 + R(2) * vp2;
-  const R aL0 = R(0.1) * P0, aL1 = R(0.6) * P1, aL2 = R(0.3) * P2;
-  const R aR0 = R(0.3) * P0, aR1 = R(0.6) * P1, aR2 = R(0.1) * P2;
-  qL = (aL0 * l0 + aL1 * l1 + aL2 * l2) * (R(1.0 / 6.0) * frcp(aL0 + aL1 + aL2));
-  qR = (aR0 * r0 + aR1 * r1 + aR2 * r2) * (R(1.0 / 6.0) * frcp(aR0 + aR1 + aR2));
+  const R P0 = D1 * D2, A1 = R(6) * (D0 * D2), P2 = D0 * D1;
+  const R A2 = R(3) * P2, B0 = R(3) * P0;
+  // 6 (candidate - v0): right edge l0..l2, left edge r0..r2
+  const R l0 = R(5) * db - R(2) * da, l1 = db + R(2) * dc, l2 = R(4) * dc - dd;
+  const R r0 = da - R(4) * db, r1 = -(R(2) * db + dc), r2 = R(2) * dd - R(5) * dc;
+  const R nL = P0 * l0 + A1 * l1 + A2 * l2, sL = P0 + A1 + A2;
+  const R nR = B0 * r0 + A1 * r1 + P2 * r2, sR = B0 + A1 + P2;
+  qL = v0 + nL * (R(1.0 / 6.0) * frcp(sL));
+  qR = v0 + nR * (R(1.0 / 6.0) * frcp(sR));
 }
 
 }  // namespace claw
