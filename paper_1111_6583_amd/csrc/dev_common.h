@@ -118,6 +118,7 @@ template <typename R, int M>
 struct EdgeStates {
   R x[M];             // this lane's x side (used if its column is a Dirichlet ghost)
   R ylo[M], yhi[M];   // lower / upper y side
+  bool xany;          // some lane of the wave maps a wall or Dirichlet ghost column
 };
 template <typename R, int M>
 __device__ __forceinline__ EdgeStates<R, M> edge_states(const GridDesc& G, const AxisMap& mx) {
@@ -128,6 +129,8 @@ __device__ __forceinline__ EdgeStates<R, M> edge_states(const GridDesc& G, const
     e.ylo[k] = (R)G.bcstate[2][k];
     e.yhi[k] = (R)G.bcstate[3][k];
   }
+  // wave-uniform, so strips away from such a boundary skip the x fix-up
+  e.xany = __builtin_amdgcn_ballot_w64(mx.kind != 0) != 0;
   return e;
 }
 
@@ -145,14 +148,23 @@ __device__ __forceinline__ void load_raw(R (&v)[M], gconst<R> q, size_t plane, i
 template <typename R, class P>
 __device__ __forceinline__ void apply_bc(R (&v)[P::M], const AxisMap& mx, const AxisMap& my,
                                          const EdgeStates<R, P::M>& e) {
+  // both branches are wave-uniform (the row's map is the same for every
+  // lane); a plain map needs no fix-up
+  if (e.xany) {
 #pragma unroll
-  for (int k = 0; k < P::M; ++k) {
-    R x = v[k];
-    x = mx.kind == 2 ? e.x[k] : x;
-    if (P::odd(0, k)) x = mx.kind == 1 ? -x : x;
-    if (P::odd(1, k)) x = my.kind == 1 ? -x : x;
-    x = my.kind == 2 ? (my.side ? e.yhi[k] : e.ylo[k]) : x;
-    v[k] = x;
+    for (int k = 0; k < P::M; ++k) {
+      R x = mx.kind == 2 ? e.x[k] : v[k];
+      if (P::odd(0, k)) x = mx.kind == 1 ? -x : x;
+      v[k] = x;
+    }
+  }
+  if (my.kind != 0) {
+#pragma unroll
+    for (int k = 0; k < P::M; ++k) {
+      R x = v[k];
+      if (P::odd(1, k)) x = my.kind == 1 ? -x : x;
+      v[k] = my.kind == 2 ? (my.side ? e.yhi[k] : e.ylo[k]) : x;
+    }
   }
 }
 template <typename R, class P>

@@ -282,10 +282,11 @@ __global__ __launch_bounds__(kLanes) void k_sharp2d(const GridDesc* __restrict__
   constexpr bool kPoint = KIND != kStagePlain;
   constexpr bool kQ = KIND == kStageFinal && KAHAN;
   // Row r+1 is loaded while row r is processed (software pipelining) and
-  // enters the window with its boundary conditions applied just before row
-  // r's results are stored (the wait for the load then comes a row of work
-  // after it was issued, and never behind stores).  The pointwise inputs of
-  // the row finalised next iteration are read ahead too.
+  // enters the window with its boundary conditions applied at the end of
+  // the iteration (the wait for the load then comes a row of work after it
+  // was issued).  The finished row is stored where it is computed, so its
+  // results are not carried to the end of the iteration.  The pointwise
+  // inputs of the row finalised next iteration are read ahead too.
   R pre[M], nxt[M], pp[M], pq[M], pc[M], up[M], uq[M], uc[M];
   load_state<R, P>(nxt, S, plane, nx, mx, map_axis(j0 - RH, ny, bcy0, bcy1, H), es);
 #pragma unroll
@@ -334,8 +335,6 @@ __global__ __launch_bounds__(kLanes) void k_sharp2d(const GridDesc* __restrict__
         }
       }
     }
-    R Lv[M], Sc[M];
-    bool store = false;
     if (r >= j0 + RH - 2) {
       // y edge values of the window's centre row c = r - RH + 1
       R qyl[M], qyr[M];
@@ -376,7 +375,7 @@ __global__ __launch_bounds__(kLanes) void k_sharp2d(const GridDesc* __restrict__
             Sf[k] = row[RH - 1];
             weno_edges<RH>(row, eps, xl[k], xr[k]);
           }
-          R ql[M], F[M], al[NA];
+          R ql[M], F[M], al[NA], Lv[M];
 #pragma unroll
           for (int k = 0; k < M; ++k) ql[k] = shfl_prev(xl[k]);
 #pragma unroll
@@ -387,9 +386,10 @@ __global__ __launch_bounds__(kLanes) void k_sharp2d(const GridDesc* __restrict__
           for (int k = 0; k < M; ++k) {
             const R Fr = shfl_next(F[k]);
             Lv[k] = -(Fr - F[k]) * rdx - (g_up[k] - g_lo[k]) * rdy;
-            Sc[k] = Sf[k];
           }
-          store = true;
+          if (own)
+            stage_store<R, P, KIND, KAHAN>(sa, O1, O2, Cout, (size_t)(r - RH) * nx + i, plane, Sf,
+                                           Lv, gdt, a1, b1, a2, b2, wq, up, uq, uc);
         }
 #pragma unroll
         for (int k = 0; k < M; ++k) g_lo[k] = g_up[k];
@@ -402,9 +402,6 @@ __global__ __launch_bounds__(kLanes) void k_sharp2d(const GridDesc* __restrict__
       for (int k = 0; k < M; ++k) nxt[k] = pre[k];
       apply_bc<R, P>(nxt, mx, mynext, es);
     }
-    if (store && own)
-      stage_store<R, P, KIND, KAHAN>(sa, O1, O2, Cout, (size_t)(r - RH) * nx + i, plane, Sc, Lv,
-                                     gdt, a1, b1, a2, b2, wq, up, uq, uc);
     slot = slot + 1 == NW ? 0 : slot + 1;
   }
   const double speed = own ? max_nan((double)smx * (1.0 / G.dx), (double)smy * (1.0 / G.dy))
