@@ -373,10 +373,17 @@ def serving(W, n_requests, n_warm):
     r = serve.run_trace(trace, tuner=tuner)
     lat = r["latencies"]
     half = lat[: len(lat) // 2]
+    # p50 / p99 per 500 consecutive requests (in arrival order): they swing
+    # with bursts of large grids, but do not drift if the load is carried
+    win = [(round(float(np.percentile(lat[i:i + 500], 50)), 4),
+            round(float(np.percentile(lat[i:i + 500], 99)), 4)) for i in range(0, len(lat), 500)]
+    st = r.get("stats", {})
     return dict(requests=len(trace), warmup_requests=n_warm, offered_req_s=200.0,
                 throughput_req_s=r["throughput_req_s"], p50_s=r["p50"], p99_s=r["p99"],
                 first_half_p50_s=float(np.percentile(half, 50)),
                 first_half_p99_s=float(np.percentile(half, 99)),
+                p50_p99_per_500_requests=win,
+                gpu_busy_fraction=round(st["gpu_busy_s"] / r["wall"], 3) if "gpu_busy_s" in st else None,
                 cell_updates_per_s=r["cell_updates_per_s"], wall_s=r["wall"],
                 max_resident=r["max_resident"], precision="fp32_kahan", budget_gib=8,
                 tiling_by_bucket=tuner.describe(), **r.get("stats", {}))

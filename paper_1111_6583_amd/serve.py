@@ -139,21 +139,33 @@ class Tuner:
 
 class _PinnedPool:
     """Reusable pinned host buffers for results leaving the device (sizes
-    rounded up to 1 MiB): a fresh pinned allocation of every request's size
-    would cost the host more than the copy."""
+    rounded up to a power of two, at least 1 MiB): a fresh pinned allocation
+    of every request's size would cost the host more than the copy.  One
+    pool per device lives as long as the process, so a warm-up trace leaves
+    it filled for the next."""
 
     def __init__(self):
         self.free = collections.defaultdict(list)
 
     def take(self, shape, dtype=torch.float64):
         n = int(np.prod(shape)) * torch.tensor([], dtype=dtype).element_size()
-        key = -(-n // (1 << 20)) << 20
+        key = max(1 << 20, 1 << (n - 1).bit_length())
         buf = self.free[key].pop() if self.free[key] else torch.empty(key, dtype=torch.uint8,
                                                                         pin_memory=True)
         return buf, buf[:n].view(dtype).view(shape)
 
     def give(self, buf):
         self.free[buf.numel()].append(buf)
+
+
+_pools = {}
+
+
+def _pinned_pool(device):
+    key = str(device)
+    if key not in _pools:
+        _pools[key] = _PinnedPool()
+    return _pools[key]
 
 
 class _Streams:
@@ -222,7 +234,7 @@ def run_trace(trace, budget_bytes=8 << 30, max_grids=64, attempts=16, precision=
     in_flight = 0
     graveyard = []         # handles retired at the last wait: kept until one more group completes
     copying = []           # (request, clock, device result, pinned buffer, host view, copy-done event)
-    pool = _PinnedPool()
+    pool = _pinned_pool(device)
     groups = 0
     # host time by activity, and the GPU's busy time (events around each group)
     t_admit = t_retire = t_wait = 0.0
