@@ -220,9 +220,19 @@ struct Ring {
   }
 };
 
+// Waves per SIMD the 2D stage kernel is built for: the FP32 WENO5 kernels
+// (window in LDS) fit four in 128 registers, and every stage must, or the
+// one tiling shared by the stages leaves a partial second round of waves
+// in the stage that fits fewer (the compensated final stage needed 136).
+template <typename R, int RH>
+constexpr int sharp2d_waves_per_simd() {
+  return UseRing<R, RH>::value ? 4 : 1;
+}
+
 template <typename R, class P, int RH, int KIND, bool KAHAN>
-__global__ __launch_bounds__(kLanes) void k_sharp2d(const GridDesc* __restrict__ grids, int mode,
-                                                    double dt_host, StageArgs sa) {
+__global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(
+    sharp2d_waves_per_simd<R, RH>()))) void k_sharp2d(const GridDesc* __restrict__ grids, int mode,
+                                                      double dt_host, StageArgs sa) {
   constexpr int M = P::M, NW = 2 * RH - 1;
   constexpr int H = RH, U = kLanes - 2 * H;
   constexpr bool kRing = UseRing<R, RH>::value;
