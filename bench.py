@@ -180,7 +180,7 @@ def timed_run(spec, q, aux, steps, warmup, t_end, segs=0, order=0, seg_rows_x=0,
     if segs > 0:
         s.set_tuning(segs=segs, order=order, seg_rows_x=seg_rows_x)
     else:
-        s.autotune(reps=3)
+        s.autotune(reps=10)
     if warmup:
         s.advance(t_end, max_steps=warmup, steps_per_graph=graph_k)
     c0 = s.clock()
