@@ -99,8 +99,10 @@ struct GridDesc {
 
 // One SharpClaw Runge-Kutta stage (see k_sharp.hip): y = S + gamma dt L(S),
 // then PLAIN out1 = y; COMBINE out1 = a1 P1 + b1 y (and out2 = a2 P1 + b2 y
-// if out2 is set); FINAL Q = a1 P1 + b1 y in place.
-enum StageKind { kStagePlain = 0, kStageCombine = 1, kStageFinal = 2 };
+// if out2 is set); FINAL Q = a1 P1 + b1 y in place.  FINAL_Q is FINAL with
+// P1 = Q^n known at compile time (SSPRK(3,3)): the compensated FP32 kernels
+// then keep one copy of Q^n instead of two (launch-side choice).
+enum StageKind { kStagePlain = 0, kStageCombine = 1, kStageFinal = 2, kStageFinalQ = 3 };
 struct StageArgs {
   const void* in;    // S
   void* out1;

@@ -143,10 +143,11 @@ __device__ __forceinline__ void stage_store(const StageArgs& sa, gmut<R> O1, gmu
     }
   } else {
     if constexpr (KAHAN) {
+      const bool p1q = KIND == kStageFinalQ || sa.p1_is_q;
 #pragma unroll
       for (int k = 0; k < M; ++k) {
         const R q = pq[k];
-        const R inc = (sa.p1_is_q ? R(0) : a1 * (pp[k] - w * q)) + b1 * ((S[k] - q) + gdt * L[k]);
+        const R inc = (p1q ? R(0) : a1 * (pp[k] - w * q)) + b1 * ((S[k] - q) + gdt * L[k]);
         const R y = inc - pc[k];
         const R t = q + y;
         C[k * plane + idx] = (t - q) - y;
@@ -290,7 +291,7 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(
   const gmut<R> O2 = as_gmut<R>(sa.out2);
   const gmut<R> Cout = as_gmut<R>(G.c[0]);
   constexpr bool kPoint = KIND != kStagePlain;
-  constexpr bool kQ = KIND == kStageFinal && KAHAN;
+  constexpr bool kQ = KIND >= kStageFinal && KAHAN;
   // Row r+1 is loaded while row r is processed (software pipelining) and
   // enters the window with its boundary conditions applied at the end of
   // the iteration (the wait for the load then comes a row of work after it
@@ -338,11 +339,13 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(
       const size_t idx = (size_t)fn * nx + ic;
 #pragma unroll
       for (int k = 0; k < M; ++k) {
-        pp[k] = P1[k * plane + idx];
-        if constexpr (kQ) {
-          pq[k] = sa.p1_is_q ? pp[k] : Qn[k * plane + idx];
-          pc[k] = Cn[k * plane + idx];
+        if constexpr (KIND == kStageFinalQ) {
+          pq[k] = Qn[k * plane + idx];
+        } else {
+          pp[k] = P1[k * plane + idx];
+          if constexpr (kQ) pq[k] = sa.p1_is_q ? pp[k] : Qn[k * plane + idx];
         }
+        if constexpr (kQ) pc[k] = Cn[k * plane + idx];
       }
     }
     if (r >= j0 + RH - 2) {
@@ -530,7 +533,12 @@ static hipError_t sharp_kind(int riemann, int kind, dim3 grid, hipStream_t st, c
     case kStagePlain: return sharp_t<R, K, NDIM, RH, kStagePlain>(riemann, grid, st, g, mode, dt, sa);
     case kStageCombine:
       return sharp_t<R, K, NDIM, RH, kStageCombine>(riemann, grid, st, g, mode, dt, sa);
-    case kStageFinal: return sharp_t<R, K, NDIM, RH, kStageFinal>(riemann, grid, st, g, mode, dt, sa);
+    case kStageFinal:
+      if constexpr (K && NDIM == 2 && RH == 3) {
+        if (sa.p1_is_q)
+          return sharp_t<R, K, NDIM, RH, kStageFinalQ>(riemann, grid, st, g, mode, dt, sa);
+      }
+      return sharp_t<R, K, NDIM, RH, kStageFinal>(riemann, grid, st, g, mode, dt, sa);
   }
   return hipErrorInvalidValue;
 }
