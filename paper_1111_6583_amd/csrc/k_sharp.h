@@ -372,21 +372,32 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(
           R Sf[M];
 #pragma unroll
           for (int k = 0; k < M; ++k) {
-            R row[NW];
-            if constexpr (kRing) {
-              const int fs = wslot(RH - 2);
-#pragma unroll
-              for (int s = 0; s < NW; ++s) row[s] = ring.at(fs, k, lane - (RH - 1) + s);
+            if constexpr (!kRing && RH == 3) {
+              // each lane forms one first difference, v(i+1) - v(i); the
+              // others are its neighbours' (the same subtraction of the same
+              // values), so four lane shifts and one subtraction per component
+              const R v0 = w[RH - 2][k];
+              const R dc = shfl_next(v0) - v0;
+              const R db = shfl_prev(dc);
+              weno5_edges_d(v0, shfl_prev(db), db, dc, shfl_next(dc), eps, xl[k], xr[k]);
+              Sf[k] = v0;
             } else {
-              row[RH - 1] = w[RH - 2][k];
+              R row[NW];
+              if constexpr (kRing) {
+                const int fs = wslot(RH - 2);
 #pragma unroll
-              for (int s = 1; s < RH; ++s) {
-                row[RH - 1 - s] = shfl_prev(row[RH - s]);
-                row[RH - 1 + s] = shfl_next(row[RH - 2 + s]);
+                for (int s = 0; s < NW; ++s) row[s] = ring.at(fs, k, lane - (RH - 1) + s);
+              } else {
+                row[RH - 1] = w[RH - 2][k];
+#pragma unroll
+                for (int s = 1; s < RH; ++s) {
+                  row[RH - 1 - s] = shfl_prev(row[RH - s]);
+                  row[RH - 1 + s] = shfl_next(row[RH - 2 + s]);
+                }
               }
+              Sf[k] = row[RH - 1];
+              weno_edges<RH>(row, eps, xl[k], xr[k]);
             }
-            Sf[k] = row[RH - 1];
-            weno_edges<RH>(row, eps, xl[k], xr[k]);
           }
           R ql[M], F[M], al[NA], Lv[M];
 #pragma unroll

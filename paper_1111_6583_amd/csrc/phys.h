@@ -824,9 +824,11 @@ struct PSystem {
 //  - the three candidate edge values, times 6, relative to the centre value:
 //    the result is v0 plus a weighted correction, so the differences, not
 //    the values, carry the rounding.
+// The same from the centre value and the window's four first differences
+// da = v(-1) - v(-2), db = v(0) - v(-1), dc = v(1) - v(0), dd = v(2) - v(1)
+// (a caller that has them from its neighbours passes them directly).
 template <typename R>
-__device__ __forceinline__ void weno5_edges(R vm2, R vm1, R v0, R vp1, R vp2, R eps, R& qL, R& qR) {
-  const R da = vm1 - vm2, db = v0 - vm1, dc = vp1 - v0, dd = vp2 - vp1;
+__device__ __forceinline__ void weno5_edges_d(R v0, R da, R db, R dc, R dd, R eps, R& qL, R& qR) {
   const R t0 = db - da, t1 = dc - db, t2 = dd - dc;
   const R u0 = R(3) * db - da, u1 = db + dc, u2 = dd - R(3) * dc;
   const R c = R(13.0 / 3.0), e4 = R(4) * eps;
@@ -843,6 +845,11 @@ __device__ __forceinline__ void weno5_edges(R vm2, R vm1, R v0, R vp1, R vp2, R 
   const R nR = B0 * r0 + A1 * r1 + P2 * r2, sR = B0 + A1 + P2;
   qL = v0 + nL * (R(1.0 / 6.0) * frcp(sL));
   qR = v0 + nR * (R(1.0 / 6.0) * frcp(sR));
+}
+
+template <typename R>
+__device__ __forceinline__ void weno5_edges(R vm2, R vm1, R v0, R vp1, R vp2, R eps, R& qL, R& qR) {
+  weno5_edges_d(v0, vm1 - vm2, v0 - vm1, vp1 - v0, vp2 - vp1, eps, qL, qR);
 }
 
 }  // namespace claw
