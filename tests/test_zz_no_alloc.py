@@ -61,6 +61,8 @@ def _cases():
     eb, qeb = W.shock_bubble(256, 128)
     es, qes = W.shock_bubble(96, 40)
     yield "euler fp64", (eb, qeb, None, 1e-3), (es, qes, None, 2e-3)
+    yield "euler fp32", (dict(eb, precision="fp32_kahan"), qeb, None, 1e-3), \
+        (dict(es, precision="fp32_kahan"), qes, None, 2e-3)
     yield "euler ssp104 weno7 fp32", \
         (dict(eb, precision="fp32_kahan", time_integrator="ssp104", weno_order=7), qeb, None, 1e-3), \
         (dict(es, precision="fp32_kahan", time_integrator="ssp104", weno_order=7), qes, None, 2e-3)
