@@ -37,11 +37,13 @@ namespace claw {
 // alternately; the loop body is instantiated for both buffer phases, so no
 // buffer is copied while its loads are in flight).  Measured on MI355X:
 // two rows ahead take 8-12% off the elasticity step (the kernel that waits on
-// memory most) and 7% off FP32 shallow water; the FP64 shallow-water and
-// Euler steps are as fast or faster with one (more code, same occupancy).
+// memory most), 7% off FP32 shallow water and 7% off the Euler step with a
+// tracer (one wave per SIMD: nothing else hides its loads); the FP64
+// shallow-water step is as fast or faster with one (more code, same
+// occupancy).
 template <typename R, class P>
 constexpr int classic_prefetch() {
-  return (std::is_same<P, Elastic<R>>::value ||
+  return (std::is_same<P, Elastic<R>>::value || std::is_same<P, EulerRoe<R, 2, true>>::value ||
           (sizeof(R) == 4 && std::is_same<P, ShallowWater<R, 2>>::value))
              ? 2
              : 1;
