@@ -222,6 +222,13 @@ def roofline(r, launches_per_step, bytes_per_cell, flops_per_cell, kernel, dtype
     if rec is not None:
         out["valu_issue_share"] = rec.get("valu_issue_share")
         out["profile"] = rec.get("profile")
+        # what the counters say limits the launch: the share of the SIMDs'
+        # time spent issuing VALU instructions against the fraction of the
+        # HBM peak its measured traffic takes
+        hbm_busy = rec["bytes_per_launch"] / avg_s / (HBM_PEAK_GBS * 1e9)
+        out["hbm_busy_measured"] = round(hbm_busy, 3)
+        issue = rec.get("valu_issue_share") or 0.0
+        out["bound_measured"] = "alu" if issue >= hbm_busy else "hbm"
     if flops_per_cell:
         tf = flops_per_cell * r["cells"] / avg_s / 1e12
         out["alu"] = dict(achieved=round(tf, 3), peak=PEAK_TFLOPS[dtype], unit="TFLOP/s",

@@ -76,6 +76,20 @@ def test_roofline_is_the_hbm_fraction_of_the_average_launch(monkeypatch):
     assert out["alu"]["frac"] == pytest.approx(1040.0 * cells / avg_s / 1e12 / 78.6, abs=1e-4)
 
 
+def test_measured_bound_compares_issue_with_hbm_busy(monkeypatch):
+    cells = 1024 * 1024
+    r = dict(steps=100, rejected=0, gpu_ms=100 * 50e-3, cells=cells, grid="1024x1024")
+    # 50 us per launch: 200 MB of measured traffic is half of the 8 TB/s peak
+    rec = dict(bytes_per_launch=200e6, valu_issue_share=0.3, profile="p.md")
+    monkeypatch.setattr(bench, "measured_counters", lambda key: rec)
+    out = bench.roofline(r, 1, 48, 554.0, "k", "f64")
+    assert out["traffic"] == 200e6 and out["profile"] == "p.md"
+    assert out["hbm_busy_measured"] == pytest.approx(0.5, abs=1e-3)
+    assert out["bound_measured"] == "hbm"
+    rec["valu_issue_share"] = 0.7
+    assert bench.roofline(r, 1, 48, 554.0, "k", "f64")["bound_measured"] == "alu"
+
+
 def test_weno_stage_flop_counts():
     assert bench.euler_stage_flops(5) == 1040.0
     # order 2r - 1: 8 edge pairs of candidates 2r(2r-1), indicators
